@@ -1,0 +1,332 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test targets a plausible mistake in the oracle: a wrong site/bit mapping,
+a wrong basis order, a dropped or sign-flipped hopping term (including the
+fermionic wrap-around sign), a wrong diagonal, a broken eigensolver.
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- bases ----
+
+def test_table1_bases_and_index():
+    """Sec. II Table I: bases, 1-based indices and Eq. (count2)."""
+    g = gold("table1_m3_n2_1.json")
+    up = oracle.enumerate_basis(g["M"], g["n_up"])
+    dn = oracle.enumerate_basis(g["M"], g["n_dn"])
+    assert up.tolist() == g["basis_up"]
+    assert dn.tolist() == g["basis_dn"]
+    keys = oracle.two_spin_keys(g["M"], up, dn)
+    # every row of the table: (Index_up, Index_dn, Index) with the two-spin key
+    # I = I_up + 2^M I_dn sitting at position Index in the sorted key list
+    for iu, idn, idx in g["combined_index_1based"]:
+        I = g["basis_up"][iu - 1] + (g["basis_dn"][idn - 1] << g["M"])
+        assert int(keys[idx - 1]) == I
+    ex = g["worked_example"]
+    I = ex["up_state"] + (ex["dn_state"] << g["M"])
+    assert int(np.searchsorted(keys, I)) + 1 == ex["index_1based"]
+
+
+@pytest.mark.parametrize("M", range(0, 15))
+def test_enumeration_brute_force(M):
+    """Algorithm I equals 'all subsets of N sites, as integers, ascending' and
+    has C(M, N) members (Eq. count3)."""
+    for N in range(0, M + 1):
+        got = oracle.enumerate_basis(M, N)
+        ref = sorted(sum(1 << s for s in c) for c in itertools.combinations(range(M), N))
+        assert got.tolist() == ref
+        assert len(got) == math.comb(M, N)
+
+
+@pytest.mark.parametrize("M", [16, 18])
+def test_enumeration_counts_large(M):
+    for N in (1, M // 2 - 1, M // 2):
+        got = oracle.enumerate_basis(M, N)
+        assert len(got) == math.comb(M, N)
+        assert np.all(np.diff(got.astype(np.int64)) > 0)
+        pc = np.array([bin(int(v)).count("1") for v in got[:: max(1, len(got) // 500)]])
+        assert np.all(pc == N)
+
+
+@pytest.mark.parametrize("M", [4, 6, 9, 12])
+def test_complement_rule(M):
+    """Sec. IX: at half filling the (M-N)-electron basis is the bitwise NOT of
+    the N-electron basis in reverse order."""
+    mask = (1 << M) - 1
+    for N in range(M + 1):
+        a = oracle.enumerate_basis(M, N)
+        b = oracle.enumerate_basis(M, M - N)
+        assert [(~int(v)) & mask for v in a[::-1]] == b.tolist()
+
+
+def test_two_spin_key_order_matches_count2():
+    """Sorted two-spin keys put the down state as the major index and the up
+    state as the minor one: Index = Index_dn * count_up + Index_up (0-based)."""
+    up = oracle.enumerate_basis(6, 2)
+    dn = oracle.enumerate_basis(6, 3)
+    keys = oracle.two_spin_keys(6, up, dn)
+    cu = len(up)
+    for n in range(len(keys)):
+        assert int(keys[n]) == int(up[n % cu]) + (int(dn[n // cu]) << 6)
+
+
+# ------------------------------------------------- Hamiltonian entries ----
+
+def _jordan_wigner_H(model):
+    """Independent construction: fermion modes 0..2M-1 (up sites, then down
+    sites), c_m = I (modes > m) x a x Z (modes < m) on the 2^(2M) Fock space,
+    so the computational basis vector with bits n is the ket with creation
+    operators in increasing mode order (Sec. II).  H from Eq. (count1)."""
+    M = model.n_sites
+    K = 2 * M
+    a = sp.csr_matrix(np.array([[0.0, 1.0], [0.0, 0.0]]))
+    Z = sp.csr_matrix(np.diag([1.0, -1.0]))
+    I2 = sp.identity(2, format="csr")
+
+    def c(m):
+        op = sp.identity(1, format="csr")
+        for k in range(K - 1, -1, -1):  # first factor = most significant bit
+            f = a if k == m else (Z if k < m else I2)
+            op = sp.kron(op, f, format="csr")
+        return op
+
+    cs = [c(m) for m in range(K)]
+    ns = [cm.T @ cm for cm in cs]
+    H = sp.csr_matrix((2 ** K, 2 ** K))
+    for (i, j), t in zip(model.bonds, model.t):
+        for s in (0, 1):
+            p, q = i + s * M, j + s * M
+            H = H - t * (cs[p].T @ cs[q] + cs[q].T @ cs[p])
+    for i in range(M):
+        H = H + model.U[i] * (ns[i] @ ns[i + M]) + model.eps[i] * (ns[i] + ns[i + M])
+    return H
+
+
+@pytest.mark.parametrize("seed,M,nb", [(1, 3, 3), (2, 4, 5), (3, 4, 6), (4, 5, 7), (5, 5, 10), (6, 6, 9)])
+def test_jordan_wigner_entries(seed, M, nb):
+    """Every entry of the oracle H equals the sector block of the Fock-space
+    Jordan-Wigner Hamiltonian: pins the hopping signs for arbitrary bonds, the
+    diagonal, and the basis order, for all sectors."""
+    base = W.random_graph(M, nb, seed=seed, site_U=True)
+    Hf = _jordan_wigner_H(base).tocsr()
+    for n_up in range(M + 1):
+        for n_dn in range(M + 1):
+            m = base.with_params(n_up=n_up, n_dn=n_dn)
+            sec = oracle.Sector(m)
+            keys = sec.keys.astype(np.int64)
+            ref = Hf[keys][:, keys].toarray()
+            got = sec.dense()
+            np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
+
+
+def test_wrap_sign_even_filling_ring():
+    """On a ring with even N_sigma the wrap-around hop carries a -1 (fermion
+    statistics).  With U=0 the many-body ground energy is then the sum of the
+    lowest periodic one-body levels; a missing sign would give the
+    antiperiodic levels instead."""
+    m = W.ring(8, U=0.0, n_up=4, n_dn=4)
+    sec, e0, _ = oracle.ground_state(m)
+    h = np.zeros((8, 8))
+    for (i, j), t in zip(m.bonds, m.t):
+        h[i, j] -= t
+        h[j, i] -= t
+    w = np.linalg.eigvalsh(h)
+    assert abs(e0 - 2 * w[:4].sum()) < 1e-10
+    assert abs(e0 - (-9.656854249492)) < 1e-9
+    # antiperiodic levels differ
+    h2 = h.copy()
+    h2[0, 7] = h2[7, 0] = +1.0
+    w2 = np.linalg.eigvalsh(h2)
+    assert abs(2 * w2[:4].sum() - e0) > 1e-3
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_u0_closed_form_random(seed):
+    """U=0: E0 = sum of the lowest N_up plus the lowest N_dn eigenvalues of the
+    one-body matrix h_ij = -t_ij (bonds), h_ii = eps_i."""
+    m = W.random_graph(7, 11, seed=seed)
+    m = m.with_params(U=[0.0] * 7, n_up=3, n_dn=2)
+    sec, e0, _ = oracle.ground_state(m)
+    h = np.diag(np.array(m.eps))
+    for (i, j), t in zip(m.bonds, m.t):
+        h[i, j] -= t
+        h[j, i] -= t
+    w = np.linalg.eigvalsh(h)
+    assert abs(e0 - (w[:3].sum() + w[:2].sum())) < 1e-10
+
+
+def test_t0_closed_form():
+    """t=0: H is diagonal; E0 = U * max(0, N_up + N_dn - M) for uniform U."""
+    for (n_up, n_dn) in [(2, 2), (3, 3), (4, 2), (5, 4)]:
+        m = W.ring(6, t=0.0, U=3.5, n_up=n_up, n_dn=n_dn)
+        sec = oracle.Sector(m)
+        H = sec.dense()
+        assert np.count_nonzero(H - np.diag(np.diag(H))) == 0
+        assert abs(np.diag(H).min() - 3.5 * max(0, n_up + n_dn - 6)) < 1e-14
+
+
+def test_full_sector_rule():
+    """Sec. III B: if N_up or N_dn equals M every diagonal is U min(N_up, N_dn)."""
+    for (n_up, n_dn) in [(5, 2), (1, 5), (5, 5)]:
+        m = W.ring(5, U=2.5, n_up=n_up, n_dn=n_dn)
+        H = oracle.Sector(m).dense()
+        assert np.allclose(np.diag(H), 2.5 * min(n_up, n_dn), atol=0, rtol=0)
+
+
+def test_double_occupancy_offset_identity():
+    """Algorithm II's offset: for N_up + N_dn > M every state has at least
+    N_up + N_dn - M doubly occupied sites, and #double = N_up + N_dn - M + #empty."""
+    M = 6
+    for n_up, n_dn in [(4, 4), (5, 3), (6, 2)]:
+        m = W.ring(M, t=0.0, U=1.0, n_up=n_up, n_dn=n_dn)
+        sec = oracle.Sector(m)
+        d = np.diag(sec.dense())
+        mask = (1 << M) - 1
+        for n, k in enumerate(sec.keys):
+            a, b = int(k) & mask, int(k) >> M
+            empty = bin(~a & ~b & mask).count("1")
+            assert d[n] == n_up + n_dn - M + empty
+
+
+def test_dimer_closed_form():
+    """Two sites, one electron per spin: E0 = (U - sqrt(U^2 + 16 t^2)) / 2."""
+    for U, t in [(4.0, 1.0), (0.0, 1.0), (10.0, 0.3), (2.0, -0.7)]:
+        m = W.dimer(U=U, t=t)
+        _, e0, _ = oracle.ground_state(m)
+        assert abs(e0 - (U - math.sqrt(U * U + 16 * t * t)) / 2) < 1e-13
+
+
+@pytest.mark.parametrize("name", ["ring8", "aim"])
+def test_hermitian_and_nnz_formula(name):
+    """H is exactly symmetric; the number of off-diagonal entries due to spin-up
+    hops is nnz(H_up) * count_dn with nnz(H_up) = 2 |bonds| C(M-2, N_up - 1)
+    (Sec. IV A, with F = 2 |bonds|)."""
+    m = W.config("ring8") if name == "ring8" else W.aim_batch(3)[2]
+    sec = oracle.Sector(m)
+    rp, col, val = sec.csr()
+    H = sp.csr_matrix((val, col, rp), shape=(sec.dim, sec.dim))
+    assert (H != H.T).nnz == 0
+    M = m.n_sites
+    rows = np.repeat(np.arange(sec.dim), np.diff(rp))
+    off = rows != col
+    kr = sec.keys[rows[off]]
+    kc = sec.keys[col[off]]
+    same_dn = (kr >> np.uint64(M)) == (kc >> np.uint64(M))
+    nb = len(m.bonds)
+    assert same_dn.sum() == 2 * nb * math.comb(M - 2, m.n_up - 1) * sec.cd
+    assert (~same_dn).sum() == 2 * nb * math.comb(M - 2, m.n_dn - 1) * sec.cu
+    assert off.sum() + sec.dim == len(col)
+
+
+# ------------------------------------------------------------ solvers ----
+
+@pytest.mark.parametrize("seed", [21, 22, 23, 24])
+def test_lanczos_matches_dense(seed):
+    m = W.random_graph(8, 12, seed=seed)
+    sec = oracle.Sector(m)
+    H = sec.dense()
+    e_ref = np.linalg.eigvalsh(H)[0]
+    csr = sec.csr()
+    for reorth in (True, False):
+        r = oracle.lanczos(lambda x: oracle.spmv(csr, x), sec.dim, oracle.start_vector(5, sec.dim),
+                           reorth=reorth, tol=1e-13)
+        assert abs(r.e0 - e_ref) <= 1e-10 * abs(e_ref)
+        res = np.linalg.norm(H @ r.psi - r.e0 * r.psi)
+        assert res < 1e-6
+
+
+def test_ring8_u4_dense_vs_lanczos():
+    m = W.config("ring8")
+    sec = oracle.Sector(m)
+    H = sec.dense()
+    e_ref = np.linalg.eigvalsh(H)[0]
+    _, e0, psi = oracle.ground_state(m)
+    assert abs(e0 - e_ref) < 1e-10 * abs(e_ref)
+
+
+@pytest.mark.slow
+def test_table4_m14():
+    """Sec. V, Table IV: ring M=14, U=4, t=1, N=7/7, E_min = -8.0883491038
+    (printed value truncated at 10 decimals)."""
+    g = gold("table4_emin.json")
+    row = [r for r in g["rows"] if r["M"] == 14][0]
+    m = W.config("ring14_u4")
+    sec = oracle.Sector(m)
+    assert sec.dim == row["dim"]
+    csr = sec.csr()
+    r = oracle.lanczos(lambda x: oracle.spmv(csr, x), sec.dim, oracle.start_vector(7542, sec.dim),
+                       tol=1e-12, want_vector=False)
+    assert row["E_min"] - 1e-10 < r.e0 <= row["E_min"] + 1e-12
+
+
+# ------------------------------------------------- generator and rows ----
+
+def test_splitmix64_reference_outputs():
+    """The start-vector generator: x_k = -1 + 2 (z_k >> 11) 2^-53 with z_k the
+    SplitMix64 output for state seed + (k+1) gamma.  Reference outputs for
+    seed 1234567 fix both the mixer and the counter convention."""
+    g = gold("splitmix64_seed1234567.json")
+    x = oracle.start_vector(g["seed"], len(g["outputs"]))
+    for xk, z in zip(x, g["outputs"]):
+        expect = -1.0 + 2.0 * ((int(z) >> 11) * 2.0 ** -53)
+        assert xk == expect
+
+
+def test_apply_rows_matches_spmv_and_implicit_keys():
+    m = W.random_graph(9, 14, seed=31)
+    sec = oracle.Sector(m)
+    sec_i = oracle.Sector(m, explicit_keys=False)
+    x = oracle.start_vector(99, sec.dim)
+    y = oracle.spmv(sec.csr(), x)
+    rows = np.arange(0, sec.dim, 7)
+    np.testing.assert_allclose(sec.apply_rows(rows, x), y[rows], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(sec_i.apply_rows(rows, None, seed=99), y[rows], rtol=0, atol=1e-12)
+
+
+# -------------------------------------------------- Hellmann-Feynman ----
+
+def test_hellmann_feynman_vs_finite_differences():
+    """g^T (dH/dtheta) x with g = x = psi0 equals dE0/dtheta; central finite
+    differences of LAPACK eigenvalues pin it, and H being linear in all its
+    parameters gives the Euler identity E0 = sum theta dE0/dtheta."""
+    m = W.random_graph(6, 8, seed=41, site_U=True).with_params(n_up=3, n_dn=2)
+    sec, e0, psi = oracle.ground_state(m)
+    db, dU, de = sec.param_bilinear(psi, psi)
+    h = 1e-5
+
+    def E(mm):
+        return oracle.ground_state(mm)[1]
+
+    for b in range(len(m.bonds)):
+        tp = list(m.t); tp[b] += h
+        tm = list(m.t); tm[b] -= h
+        fd = (E(m.with_params(t=tp)) - E(m.with_params(t=tm))) / (2 * h)
+        assert abs(fd - db[b]) < 1e-7
+    for i in range(m.n_sites):
+        up = list(m.U); up[i] += h
+        um = list(m.U); um[i] -= h
+        fd = (E(m.with_params(U=up)) - E(m.with_params(U=um))) / (2 * h)
+        assert abs(fd - dU[i]) < 1e-7
+        ep = list(m.eps); ep[i] += h
+        em = list(m.eps); em[i] -= h
+        fd = (E(m.with_params(eps=ep)) - E(m.with_params(eps=em))) / (2 * h)
+        assert abs(fd - de[i]) < 1e-7
+    euler = np.dot(m.t, db) + np.dot(m.U, dU) + np.dot(m.eps, de)
+    assert abs(euler - e0) < 1e-12 * max(1.0, abs(e0))
