@@ -1,0 +1,234 @@
+/*
+ * hubbard.h -- C ABI of libhubbard, an MI355X (gfx950) library for exact
+ * diagonalisation of the one-band Hubbard model in one (N_up, N_dn) sector.
+ *
+ * Method: Sharma & Ahsan, "Organization of the Hilbert Space for Exact
+ * Diagonalization of Hubbard Model" (arXiv:1307.7542).  The sector Hamiltonian
+ * is never assembled.  It is applied as the Kronecker sum of Sec. IV A,
+ *
+ *     H = I_dn (x) H_up  +  H_dn (x) I_up  +  D,
+ *     Y = H_up V + V H_dn^T + D o V,
+ *
+ * where V is the count_up x count_dn state matrix obtained from a sector vector
+ * by the column-major reshape of Sec. IV A (element (a, b) at a + b*count_up,
+ * the 0-based form of Eq. (count2)), H_up / H_dn are the one-spin hopping
+ * matrices of Sec. IV A, and D is the diagonal (on-site repulsion, Sec. III B,
+ * plus on-site energies).
+ *
+ * Conventions
+ *   - Sites are 0-based.  Site i of a one-spin state is bit i of a 32-bit
+ *     occupation integer (Sec. II; M <= 32).
+ *   - A one-spin basis is the list of occupation integers with N set bits in
+ *     ascending order (what Algorithm I of Appendix A produces); the index of a
+ *     state is its 0-based position in that list.
+ *   - Bond (i, j) with amplitude t contributes -t (c+_i c_j + c+_j c_i) for each
+ *     spin (Eq. count1); the matrix element between two one-spin states is
+ *     -t * esign, esign = (-1)^(occupied sites strictly between i and j)
+ *     (Sec. III A).  Up operators are ordered before down operators (Sec. II),
+ *     so no sign couples the two spins and H is exactly the Kronecker sum.
+ *   - Vectors passed as device pointers hold count_up * count_dn elements of the
+ *     stated dtype, column-major as above, 256-byte aligned is recommended
+ *     (required: element alignment).  The caller owns them.
+ *
+ * Errors: every entry point returns a hub_status; none aborts or throws.
+ * hub_last_error() gives a thread-local message for the last failure.
+ *
+ * Threading: a sector is immutable after creation; concurrent hub_matvec calls
+ * on one sector from different streams are safe.  hub_ground_state allocates
+ * its own workspace per call.
+ */
+#ifndef HUBBARD_H
+#define HUBBARD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hub_status;
+#define HUB_OK 0
+#define HUB_ERR_INVALID_ARG 1   /* null pointer, bad bond, non-finite parameter, aliasing */
+#define HUB_ERR_RANGE 2         /* M outside 1..32, N outside 0..M, size overflow */
+#define HUB_ERR_OOM 3           /* device or host allocation failed */
+#define HUB_ERR_DEVICE 4        /* HIP runtime error */
+#define HUB_ERR_NOT_CONVERGED 5 /* Lanczos hit max_iter; best estimate still returned */
+#define HUB_ERR_UNSUPPORTED 6   /* option combination not supported */
+
+/* Arithmetic type of vectors and of the matrix-vector product. */
+#define HUB_F64 0
+#define HUB_F32 1
+
+#define HUB_SPIN_UP 0
+#define HUB_SPIN_DN 1
+
+/*
+ * Model: Eq. (count1) with per-bond amplitudes t_ij, per-site U_i and on-site
+ * energies eps_i (Sec. VIII uses U on the impurity only):
+ *     H = -sum_b t_b sum_s (c+_{i_b s} c_{j_b s} + h.c.)
+ *         + sum_i U_i n_{i up} n_{i dn} + sum_i eps_i (n_{i up} + n_{i dn}).
+ * Bonds are canonicalised to (min, max); repeated bonds are merged by adding
+ * their t in input order (FP64), keeping the first occurrence's position.
+ * All arrays are host memory owned by the caller and copied by create.
+ */
+typedef struct hub_model {
+    int32_t n_sites;       /* M, 1..32 */
+    int32_t n_bonds;       /* >= 0 */
+    const int32_t *bond_i; /* n_bonds site indices in 0..M-1 */
+    const int32_t *bond_j; /* n_bonds site indices, bond_j[b] != bond_i[b] */
+    const double *t;       /* n_bonds finite amplitudes */
+    const double *U;       /* M finite on-site repulsions (NULL = all zero) */
+    const double *eps;     /* M finite on-site energies (NULL = all zero) */
+} hub_model;
+
+typedef struct hub_sector hub_sector; /* opaque; lives on the device current at creation */
+
+/*
+ * Build the sector (N_up, N_dn) of `model` on the current HIP device (Sec. II,
+ * Sec. III, Sec. IV A): both one-spin bases (combinadic unrank, equivalent to
+ * Algorithm I), the hopping matrices H_up and H_dn in CSR (combinadic rank of
+ * the hopped state, esign of Sec. III A, columns ascending in each row), and the
+ * per-state on-site energy sums.  When N_up == N_dn the two spins share one set
+ * of tables (Sec. X: identical matrices for S^z = 0).  Synchronous.
+ * Errors: RANGE (M, N), INVALID_ARG (bonds, non-finite values, out == NULL),
+ * OOM, DEVICE.
+ */
+hub_status hub_sector_create(const hub_model *model, int32_t n_up, int32_t n_dn, hub_sector **out);
+
+/* Free all device and host memory of the sector.  NULL is a no-op. */
+void hub_sector_destroy(hub_sector *sec);
+
+/* count_sigma = C(M, N_sigma) (Eq. count3) and dim = count_up * count_dn. */
+hub_status hub_sector_dims(const hub_sector *sec, int64_t *count_up, int64_t *count_dn, int64_t *dim);
+
+/* Number of canonical bonds after merging, and the merged list (host arrays of
+ * that length; any pointer may be NULL). */
+hub_status hub_sector_bonds(const hub_sector *sec, int32_t *n_bonds, int32_t *bond_i, int32_t *bond_j,
+                            double *t);
+
+/* Copy the ascending one-spin basis of `spin` (count_spin entries) to host memory. */
+hub_status hub_basis(const hub_sector *sec, int32_t spin, uint64_t *host_out);
+
+/*
+ * Rank (0-based basis index) of n arbitrary occupation integers of `spin`,
+ * computed on the device by the combinadic sum (equivalent to locating the
+ * state in the Algorithm I list).  Integers that are not states of this spin
+ * sector (wrong popcount, bits at or above M) give -1.  Host in, host out.
+ */
+hub_status hub_rank(const hub_sector *sec, int32_t spin, const uint64_t *host_x, int64_t n, int64_t *host_out);
+
+/* Stored entries of H_spin (= 2 |bonds| C(M-2, N-1) for M > 2, 0 < N < M, Sec. IV A). */
+hub_status hub_hopping_nnz(const hub_sector *sec, int32_t spin, int64_t *nnz);
+
+/*
+ * Copy H_spin (Sec. IV A) in CSR to host memory: row_ptr (count+1), col (nnz,
+ * ascending within a row), val (nnz, -t_b * esign), bond_id (nnz, index of the
+ * canonical bond that produced the entry).  Any of col/val/bond_id may be NULL.
+ */
+hub_status hub_hopping_csr(const hub_sector *sec, int32_t spin, int64_t *row_ptr, int32_t *col, double *val,
+                           int32_t *bond_id);
+
+/*
+ * Write the diagonal D of H (on-site repulsion, Sec. III B, plus on-site
+ * energies) as a dim-long device vector of `dtype`.  Asynchronous on `stream`
+ * (a hipStream_t, NULL = default stream).  For tests; the matrix-vector
+ * product computes D on the fly and never stores it.
+ */
+hub_status hub_diagonal(const hub_sector *sec, int32_t dtype, void *dev_out, void *stream);
+
+/*
+ * Start vector: x_k = -1 + 2 u_k, u_k = (SplitMix64 output for state
+ * seed + (k+1) * 0x9E3779B97F4A7C15) >> 11, times 2^-53 (Steele, Lea & Flood
+ * 2014, counter-based), k the 0-based column-major index; scaled to unit FP64
+ * norm when `normalize` is non-zero.  dim elements of `dtype` on the device.
+ */
+hub_status hub_start_vector(const hub_sector *sec, int32_t dtype, uint64_t seed, int32_t normalize,
+                            void *dev_out, void *stream);
+
+/*
+ * y = H x as the Kronecker sum Y = H_up X + X H_dn^T + D o X (Sec. IV A), in
+ * `dtype` arithmetic (FP32 accumulates in FP32).  dev_x and dev_y are dim-long
+ * device vectors; they must not overlap (INVALID_ARG).  Asynchronous on
+ * `stream`.
+ */
+hub_status hub_matvec(const hub_sector *sec, int32_t dtype, const void *dev_x, void *dev_y, void *stream);
+
+/*
+ * Lanczos ground state (Sec. IV; the paper uses the plain three-term
+ * recurrence without reorthogonalisation, Sec. V).
+ *
+ *   vec_dtype = HUB_F64: vectors, products and scalars in FP64.
+ *   vec_dtype = HUB_F32: vectors and products in FP32; alpha, beta, the
+ *                        reorthogonalisation coefficients, the tridiagonal
+ *                        eigenproblem and the optional refinement in FP64.
+ *   reorth = 0: plain recurrence; psi by a second pass over the same
+ *               recurrence with the stored alpha/beta.
+ *   reorth = 1: full classical Gram-Schmidt, applied twice per step, against
+ *               all stored Lanczos vectors (needs max_iter vectors of memory);
+ *               psi from the stored vectors.
+ *   refine = 1: with psi promoted to FP64, an FP64 product gives the Rayleigh
+ *               quotient (info.e0_refined, returned as *e0) and the true
+ *               residual ||H psi - E psi|| (info.true_residual).
+ * Convergence: Ritz residual beta_{k+1} |y_k| <= tol |theta| (tested every
+ * check_every steps), or an invariant subspace (breakdown).
+ * dev_psi: NULL or a dim-long FP64 device vector receiving the unit-norm
+ * ground state with its largest-magnitude entry positive (requires
+ * want_vector).  dev_start: NULL (use `seed`) or a dim-long FP64 device start
+ * vector (normalised internally).  Synchronous with respect to `stream`.
+ * Returns NOT_CONVERGED (with the best estimate written) when max_iter is hit.
+ */
+typedef struct hub_lanczos_opts {
+    int32_t max_iter;      /* default 400 when <= 0 */
+    double tol;            /* default 1e-12 (F64) / 1e-7 (F32) when <= 0 */
+    uint64_t seed;         /* start-vector seed */
+    const void *dev_start; /* optional FP64 start vector */
+    int32_t vec_dtype;     /* HUB_F64 or HUB_F32 */
+    int32_t reorth;        /* 0 plain, 1 full */
+    int32_t want_vector;   /* compute psi */
+    int32_t refine;        /* FP64 Rayleigh quotient and residual (needs want_vector) */
+    int32_t check_every;   /* host convergence test period; default 1 when <= 0 */
+    int32_t time_kernels;  /* record HIP events around every product launch */
+} hub_lanczos_opts;
+
+typedef struct hub_lanczos_info {
+    int32_t iters;          /* Lanczos steps taken (dimension of T) */
+    int32_t converged;      /* 1 if the Ritz residual test or breakdown stopped it */
+    int32_t breakdown;      /* 1 if an invariant subspace was found */
+    int32_t matvec_count;   /* products of the Lanczos passes (refinement not counted) */
+    double e0_ritz;         /* lowest Ritz value at stop */
+    double e0_refined;      /* FP64 Rayleigh quotient of psi (refine), else e0_ritz */
+    double residual;        /* Ritz residual estimate at stop */
+    double true_residual;   /* ||H psi - E psi||_2 in FP64 (refine), else -1 */
+    double seconds;         /* wall time of the call */
+    double seconds_to_e0;   /* wall time until the Ritz test passed */
+    double matvec_ms;       /* summed event time of those products (time_kernels) */
+    int64_t matvec_bytes;   /* algorithmic bytes of one product: 2 dim s + tables */
+} hub_lanczos_info;
+
+hub_status hub_ground_state(const hub_sector *sec, const hub_lanczos_opts *opts, double *e0, void *dev_psi,
+                            void *stream, hub_lanczos_info *info);
+
+/*
+ * Bilinear forms of the parameter derivatives of H (H is linear in t, U, eps):
+ *   dbond[b] = g^T (dH/dt_b) x    (canonical bond b, both spins),
+ *   dU[i]    = sum_k n_{i up} n_{i dn}(k) g_k x_k,
+ *   deps[i]  = sum_k (n_{i up} + n_{i dn})(k) g_k x_k,
+ * for dim-long FP64 device vectors g and x.  With g = x = psi (unit norm) these
+ * are the Hellmann-Feynman derivatives of the eigenvalue.  Host outputs of
+ * length n_bonds (canonical) and M; any may be NULL.  Synchronous on `stream`.
+ */
+hub_status hub_param_bilinear(const hub_sector *sec, const void *dev_g, const void *dev_x, double *dbond,
+                              double *dU, double *deps, void *stream);
+
+/* Algorithmic bytes of one product in `dtype`: read x, write y, plus the tables. */
+hub_status hub_matvec_bytes(const hub_sector *sec, int32_t dtype, int64_t *bytes);
+
+const char *hub_status_str(hub_status s);
+const char *hub_last_error(void);
+const char *hub_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HUBBARD_H */

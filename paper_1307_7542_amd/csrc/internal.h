@@ -1,0 +1,128 @@
+// Internal declarations shared by the libhubbard translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hubbard.h"
+
+namespace hub {
+
+constexpr int kMaxSites = 32;
+constexpr int kMaxBonds = 512;
+constexpr int kBinomN = 33;  // binomial table C[n][k], 0 <= n, k <= 32
+
+void set_error(const std::string &msg);
+
+// Device tables of one spin sector (Sec. II: basis; Sec. IV A: H_sigma in CSR).
+struct SpinTables {
+    int N = 0;
+    int64_t count = 0;     // C(M, N)
+    int64_t nnz = 0;       // stored entries of H_sigma
+    uint32_t *basis = nullptr;   // [count] ascending occupation integers
+    int32_t *rp = nullptr;       // [count + 1] row pointers
+    int32_t *col = nullptr;      // [nnz] column (basis index of the hopped state), ascending per row
+    double *val64 = nullptr;     // [nnz] -t_b * esign
+    float *val32 = nullptr;      // [nnz] FP32 copy of val64 (exact: a negated / rounded t)
+    int32_t *bond = nullptr;     // [nnz] canonical bond id of the entry
+    double *e64 = nullptr;       // [count] sum_i eps_i n_i (FP64, ascending i)
+    float *e32 = nullptr;        // [count] FP32 copy
+    int32_t max_row = 0;         // longest row of H_sigma
+};
+
+}  // namespace hub
+
+struct hub_sector {
+    int device = 0;
+    int M = 0;
+    int64_t dim = 0;
+    // canonical bonds
+    int nb = 0;
+    std::vector<int32_t> bi, bj;
+    std::vector<double> t;
+    std::vector<double> U, eps;
+    int uniformU = 1;
+    double U0 = 0.0;
+    uint32_t umask = 0;
+    bool shared_spin = false;         // N_up == N_dn: spin[1] aliases spin[0]
+    hub::SpinTables spin[2];
+    uint64_t *d_binom = nullptr;      // [33 * 33]
+    int32_t *d_bi = nullptr, *d_bj = nullptr;
+    double *d_t = nullptr;
+    double *d_eps = nullptr;          // [M]
+    double *d_U64 = nullptr;          // [M] per-site U
+    float *d_U32 = nullptr;           // [M]
+    size_t lds_max = 65536;           // dynamic LDS a workgroup may request
+    int cu_count = 256;
+    std::vector<void *> owned;        // every device allocation, freed by destroy
+    int32_t *col_order = nullptr;     // processing order of the columns (down index) in the product
+};
+
+namespace hub {
+
+// ---- setup (setup.hip) -------------------------------------------------
+hub_status build_spin_tables(hub_sector *s, int spin, int N, hipStream_t st);
+hub_status rank_device(const hub_sector *s, int spin, const uint64_t *dx, int64_t n, int64_t *dout,
+                       hipStream_t st);
+
+// ---- product (matvec.hip) ----------------------------------------------
+hub_status launch_matvec(const hub_sector *s, int dtype, const void *x, void *y, hipStream_t st);
+hub_status launch_diagonal(const hub_sector *s, int dtype, void *out, hipStream_t st);
+int64_t matvec_bytes(const hub_sector *s, int dtype);
+
+// ---- vectors (vec.hip) -------------------------------------------------
+constexpr int kRedBlock = 256;
+constexpr int kRedGrid = 1024;
+int red_grid(int64_t n);
+hub_status launch_start_vector(int dtype, uint64_t seed, void *out, int64_t n, hipStream_t st);
+// partial FP64 reductions + final: result written to device double *out
+hub_status launch_dot(int dtype, const void *x, const void *y, int64_t n, double *partial, double *out,
+                      int sqrt_result, hipStream_t st);
+hub_status launch_convert(int din, const void *x, int dout, void *y, int64_t n, const double *scale_dev,
+                          int invert, hipStream_t st);
+hub_status launch_lz_a(int dtype, void *w, const void *vprev, const double *beta, const void *v, int64_t n,
+                       double *partial, double *alpha_out, hipStream_t st);
+hub_status launch_lz_b(int dtype, void *w, const void *v, const double *alpha, int64_t n, double *partial,
+                       double *beta_out, hipStream_t st);
+hub_status launch_lz_next(int dtype, const void *w, void *vnext, const double *beta, int64_t n,
+                          hipStream_t st);
+hub_status launch_lz_replay(int dtype, void *w, const void *vprev, const double *beta, const void *v,
+                            const double *alpha, int64_t n, hipStream_t st);
+hub_status launch_psi_acc(int dtype, double *psi, const void *v, const double *ycoef, int64_t n, int first,
+                          hipStream_t st);
+hub_status launch_gram(int dtype, const void *const *dQ, int k, void *w, int64_t n, double *partial,
+                       double *coef, hipStream_t st);
+hub_status launch_psi_from_basis(int dtype, const void *const *dQ, int k, const double *ycoef, double *psi,
+                                 int64_t n, hipStream_t st);
+hub_status launch_normalize_sign(double *psi, int64_t n, double *partial, double *scal, hipStream_t st);
+hub_status launch_residual(const double *hpsi, const double *psi, const double *e, int64_t n, double *partial,
+                           double *out, hipStream_t st);
+
+// ---- adjoint (adjoint.hip) ---------------------------------------------
+hub_status param_bilinear(const hub_sector *s, const double *g, const double *x, double *dbond, double *dU,
+                          double *deps, hipStream_t st);
+
+// ---- Lanczos (lanczos.cpp) ---------------------------------------------
+hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *e0_out, void *dev_psi,
+                        hipStream_t st, hub_lanczos_info *info);
+
+}  // namespace hub
+
+#define HUB_HIP(call)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) {                                                                 \
+            hub::set_error(std::string(#call) + ": " + hipGetErrorString(e_));                  \
+            return (e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation) ? HUB_ERR_OOM \
+                                                                                 : HUB_ERR_DEVICE; \
+        }                                                                                       \
+    } while (0)
+
+#define HUB_TRY(call)                   \
+    do {                                \
+        hub_status s_ = (call);         \
+        if (s_ != HUB_OK) return s_;    \
+    } while (0)

@@ -1,0 +1,371 @@
+// Host driver of the Lanczos ground-state solve (Sec. IV).  The product and all
+// vector work run in the HIP kernels of matvec.hip / vec.hip on the caller's
+// stream; alpha and beta stay in device memory and are copied to the host only
+// when the convergence test runs.  The small tridiagonal eigenproblem is solved
+// on the host: the lowest eigenvalue by bisection on the Sturm sequence count,
+// its eigenvector by inverse iteration with a partially pivoted tridiagonal LU.
+#include <chrono>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace hub {
+namespace {
+
+// Number of eigenvalues of T (diag a, off-diagonal b) smaller than x.
+int sturm_count(const double *a, const double *b, int m, double x, double pivmin)
+{
+    int cnt = 0;
+    double q = a[0] - x;
+    if (std::fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < m; ++i) {
+        q = (a[i] - x) - b[i - 1] * b[i - 1] / q;
+        if (std::fabs(q) < pivmin) q = -pivmin;
+        if (q < 0) ++cnt;
+    }
+    return cnt;
+}
+
+// Lowest eigenpair of the m x m symmetric tridiagonal matrix; y has unit norm.
+double tri_lowest(const double *a, const double *b, int m, std::vector<double> &y)
+{
+    y.assign(m, 0.0);
+    if (m == 1) {
+        y[0] = 1.0;
+        return a[0];
+    }
+    double tnorm = 0.0, bmax2 = 0.0;
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+        tnorm = std::max(tnorm, std::fabs(a[i]) + r);
+        if (i < m - 1) bmax2 = std::max(bmax2, b[i] * b[i]);
+    }
+    const double pivmin = DBL_MIN * std::max(1.0, bmax2);
+    lo -= 2.0 * DBL_EPSILON * tnorm + pivmin;
+    hi += 2.0 * DBL_EPSILON * tnorm + pivmin;
+    for (int it = 0; it < 400; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (hi - lo <= 2.0 * DBL_EPSILON * std::max(std::fabs(lo), std::fabs(hi)) + pivmin) break;
+        if (sturm_count(a, b, m, mid, pivmin) >= 1) hi = mid;
+        else lo = mid;
+    }
+    const double theta = 0.5 * (lo + hi);
+
+    // Inverse iteration: (T - theta I) z = r with partial pivoting.
+    std::vector<double> U0(m), U1(m), U2(m), L(m), r(m, 1.0);
+    std::vector<char> sw(m, 0);
+    const double tiny = DBL_EPSILON * std::max(tnorm, DBL_MIN);
+    double c0 = a[0] - theta, c1 = b[0], c2 = 0.0;
+    for (int i = 0; i < m - 1; ++i) {
+        const double n0 = b[i], n1 = a[i + 1] - theta, n2 = (i + 1 < m - 1) ? b[i + 1] : 0.0;
+        double p0, p1, p2, o0, o1, o2;
+        if (std::fabs(n0) > std::fabs(c0)) {
+            sw[i] = 1;
+            p0 = n0; p1 = n1; p2 = n2;
+            o0 = c0; o1 = c1; o2 = c2;
+        } else {
+            sw[i] = 0;
+            p0 = c0; p1 = c1; p2 = c2;
+            o0 = n0; o1 = n1; o2 = n2;
+        }
+        if (p0 == 0.0) p0 = tiny;
+        const double f = o0 / p0;
+        L[i] = f;
+        U0[i] = p0; U1[i] = p1; U2[i] = p2;
+        c0 = o1 - f * p1;
+        c1 = o2 - f * p2;
+        c2 = 0.0;
+    }
+    U0[m - 1] = (c0 == 0.0) ? tiny : c0;
+    U1[m - 1] = 0.0;
+    U2[m - 1] = 0.0;
+    std::vector<double> z(m);
+    for (int pass = 0; pass < 3; ++pass) {
+        for (int i = 0; i < m - 1; ++i) {
+            if (sw[i]) std::swap(r[i], r[i + 1]);
+            r[i + 1] -= L[i] * r[i];
+        }
+        for (int i = m - 1; i >= 0; --i) {
+            double s = r[i];
+            if (i + 1 < m) s -= U1[i] * z[i + 1];
+            if (i + 2 < m) s -= U2[i] * z[i + 2];
+            z[i] = s / U0[i];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm += z[i] * z[i];
+        nrm = std::sqrt(nrm);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+            for (int i = 0; i < m; ++i) z[i] = (i == 0) ? 1.0 : 0.0;
+            nrm = 1.0;
+        }
+        for (int i = 0; i < m; ++i) r[i] = z[i] / nrm;
+    }
+    y = r;
+    return theta;
+}
+
+struct DevMem {
+    std::vector<void *> ptrs;
+    ~DevMem()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    hub_status alloc(void **p, size_t bytes)
+    {
+        hipError_t e = hipMalloc(p, bytes == 0 ? 1 : bytes);
+        if (e != hipSuccess) {
+            set_error(std::string("workspace hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+            (void)hipGetLastError();
+            return HUB_ERR_OOM;
+        }
+        ptrs.push_back(*p);
+        return HUB_OK;
+    }
+};
+
+struct EventTimer {
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> ev;
+    int used = 0;
+    ~EventTimer()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    hub_status mark()
+    {
+        if (!on) return HUB_OK;
+        if (used == (int)ev.size()) {
+            hipEvent_t e;
+            HUB_HIP(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        HUB_HIP(hipEventRecord(ev[used++], st));
+        return HUB_OK;
+    }
+    double total_ms()
+    {
+        double t = 0.0;
+        for (int i = 0; i + 1 < used; i += 2) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) t += ms;
+        }
+        return t;
+    }
+};
+
+using clk = std::chrono::steady_clock;
+
+}  // namespace
+
+hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *e0_out, void *dev_psi,
+                        hipStream_t st, hub_lanczos_info *info)
+{
+    const auto t0 = clk::now();
+    const int dt = o->vec_dtype;
+    const size_t es = (dt == HUB_F64) ? 8 : 4;
+    const int64_t n = s->dim;
+    int max_iter = o->max_iter > 0 ? o->max_iter : 400;
+    if ((int64_t)max_iter > n) max_iter = (int)n;
+    const double tol = o->tol > 0 ? o->tol : (dt == HUB_F64 ? 1e-12 : 1e-7);
+    const int check_every = o->check_every > 0 ? o->check_every : 1;
+    const bool reorth = o->reorth != 0;
+    const bool want_vec = o->want_vector != 0 || o->refine != 0;
+
+    hub_lanczos_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    inf.true_residual = -1.0;
+    inf.matvec_bytes = matvec_bytes(s, dt);
+
+    DevMem mem;
+    EventTimer tm;
+    tm.on = o->time_kernels != 0;
+    tm.st = st;
+
+    const int kmax = max_iter + 1;
+    double *dscal = nullptr;  // alpha[kmax] beta[kmax+1] misc[16] ycoef[kmax]
+    HUB_TRY(mem.alloc((void **)&dscal, sizeof(double) * (size_t)(3 * kmax + 32)));
+    double *d_alpha = dscal, *d_beta = dscal + kmax, *d_misc = dscal + 2 * kmax + 1,
+           *d_y = dscal + 2 * kmax + 17;
+    HUB_HIP(hipMemsetAsync(dscal, 0, sizeof(double) * (size_t)(3 * kmax + 32), st));
+    double *partial = nullptr;
+    const size_t npart = (size_t)kRedGrid * (size_t)std::max(kmax, 2) + 2 * (size_t)kRedGrid;
+    HUB_TRY(mem.alloc((void **)&partial, sizeof(double) * npart));
+    void **dQ = nullptr;  // device array of vector pointers
+    HUB_TRY(mem.alloc((void **)&dQ, sizeof(void *) * (size_t)kmax));
+    double *d_coef = nullptr;  // Gram coefficients against the stored vectors
+    HUB_TRY(mem.alloc((void **)&d_coef, sizeof(double) * (size_t)kmax));
+
+    void *W = nullptr, *Va = nullptr, *Vb = nullptr;
+    HUB_TRY(mem.alloc(&W, es * (size_t)n));
+    std::vector<void *> Q;  // reorth: every Lanczos vector (append-only, never reallocated)
+    Q.reserve((size_t)kmax);
+    auto new_q = [&](void **p) -> hub_status {
+        HUB_TRY(mem.alloc(p, es * (size_t)n));
+        Q.push_back(*p);
+        return HUB_OK;
+    };
+    if (reorth) {
+        HUB_TRY(new_q(&Va));
+    } else {
+        HUB_TRY(mem.alloc(&Va, es * (size_t)n));
+        HUB_TRY(mem.alloc(&Vb, es * (size_t)n));
+    }
+
+    // start vector v0 = x / ||x|| in storage precision
+    auto make_start = [&](void *v) -> hub_status {
+        if (o->dev_start) {
+            HUB_TRY(launch_dot(HUB_F64, o->dev_start, o->dev_start, n, partial, d_misc, 1, st));
+            HUB_TRY(launch_convert(HUB_F64, o->dev_start, dt, v, n, d_misc, 1, st));
+        } else {
+            HUB_TRY(launch_start_vector(dt, o->seed, W, n, st));
+            HUB_TRY(launch_dot(dt, W, W, n, partial, d_misc, 1, st));
+            HUB_TRY(launch_convert(dt, W, dt, v, n, d_misc, 1, st));
+        }
+        return HUB_OK;
+    };
+    auto product = [&](const void *x, void *y) -> hub_status {
+        HUB_TRY(tm.mark());
+        HUB_TRY(launch_matvec(s, dt, x, y, st));
+        HUB_TRY(tm.mark());
+        inf.matvec_count++;
+        return HUB_OK;
+    };
+
+    HUB_TRY(make_start(Va));
+    void *v_prev = nullptr, *v = Va, *spare = Vb;
+
+    std::vector<double> ha(kmax), hb(kmax + 1), y;
+    int m_final = 0;
+    double theta = 0.0, res = 0.0;
+    bool converged = false, breakdown = false;
+    double t_e0 = -1.0;
+    double tmax = 0.0;
+
+    for (int k = 0; k < max_iter; ++k) {
+        HUB_TRY(product(v, W));
+        HUB_TRY(launch_lz_a(dt, W, v_prev, d_beta + k, v, n, partial, d_alpha + k, st));
+        if (reorth) {
+            HUB_TRY(launch_lz_b(dt, W, v, d_alpha + k, n, partial, nullptr, st));
+            HUB_HIP(hipMemcpyAsync(dQ, Q.data(), sizeof(void *) * Q.size(), hipMemcpyHostToDevice, st));
+            for (int pass = 0; pass < 2; ++pass)
+                HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st));
+            HUB_TRY(launch_dot(dt, W, W, n, partial, d_beta + k + 1, 1, st));
+        } else {
+            HUB_TRY(launch_lz_b(dt, W, v, d_alpha + k, n, partial, d_beta + k + 1, st));
+        }
+        const bool last = (k + 1 == max_iter);
+        if ((k + 1) % check_every == 0 || last) {
+            const int m = k + 1;
+            HUB_HIP(hipMemcpyAsync(ha.data(), d_alpha, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+            HUB_HIP(hipMemcpyAsync(hb.data(), d_beta, sizeof(double) * (m + 1), hipMemcpyDeviceToHost, st));
+            HUB_HIP(hipStreamSynchronize(st));
+            // first breakdown (invariant subspace) within the new steps
+            int mm = m;
+            for (int j = 0; j < m; ++j) {
+                tmax = std::max(tmax, std::fabs(ha[j]) + 2.0 * std::fabs(hb[j + 1]));
+                const double thr = 64.0 * ((dt == HUB_F64) ? DBL_EPSILON : FLT_EPSILON) * std::max(tmax, DBL_MIN);
+                if (!(hb[j + 1] > thr)) {
+                    mm = j + 1;
+                    breakdown = true;
+                    break;
+                }
+            }
+            theta = tri_lowest(ha.data(), hb.data() + 1, mm, y);
+            res = std::fabs(hb[mm]) * std::fabs(y[mm - 1]);
+            const double scale = std::fabs(theta) > 0 ? std::fabs(theta) : 1.0;
+            if (breakdown || res <= tol * scale) {
+                converged = true;
+                m_final = mm;
+                if (breakdown) res = 0.0;
+                t_e0 = std::chrono::duration<double>(clk::now() - t0).count();
+                break;
+            }
+            m_final = m;
+        }
+        if (last) break;
+        // v_{k+1} = w / beta_{k+1}
+        void *vn = nullptr;
+        if (reorth) {
+            HUB_TRY(new_q(&vn));
+        } else {
+            vn = v_prev ? v_prev : spare;
+        }
+        HUB_TRY(launch_lz_next(dt, W, vn, d_beta + k + 1, n, st));
+        if (!reorth && !v_prev) spare = nullptr;
+        v_prev = v;
+        v = vn;
+    }
+    inf.iters = m_final;
+    inf.converged = converged ? 1 : 0;
+    inf.breakdown = breakdown ? 1 : 0;
+    inf.e0_ritz = theta;
+    inf.e0_refined = theta;
+    inf.residual = res;
+    inf.seconds_to_e0 = t_e0;
+    double e0 = theta;
+
+    if (want_vec) {
+        const int m = m_final;
+        double *psi = (double *)dev_psi;
+        if (!psi) HUB_TRY(mem.alloc((void **)&psi, sizeof(double) * (size_t)n));
+        HUB_HIP(hipMemcpyAsync(d_y, y.data(), sizeof(double) * m, hipMemcpyHostToDevice, st));
+        if (reorth) {
+            HUB_HIP(hipMemcpyAsync(dQ, Q.data(), sizeof(void *) * Q.size(), hipMemcpyHostToDevice, st));
+            HUB_TRY(launch_psi_from_basis(dt, (const void *const *)dQ, m, d_y, psi, n, st));
+        } else {
+            // second pass over the same recurrence with the stored alpha / beta
+            void *a = Va, *b = Vb;
+            HUB_TRY(make_start(a));
+            HUB_TRY(launch_psi_acc(dt, psi, a, d_y, n, 1, st));
+            void *vp = nullptr, *vc = a, *sp = b;
+            for (int j = 0; j + 1 < m; ++j) {
+                HUB_TRY(product(vc, W));
+                HUB_TRY(launch_lz_replay(dt, W, vp, d_beta + j, vc, d_alpha + j, n, st));
+                void *vn = vp ? vp : sp;
+                HUB_TRY(launch_lz_next(dt, W, vn, d_beta + j + 1, n, st));
+                vp = vc;
+                vc = vn;
+                HUB_TRY(launch_psi_acc(dt, psi, vc, d_y + j + 1, n, 0, st));
+            }
+        }
+        HUB_TRY(launch_normalize_sign(psi, n, partial, d_misc, st));
+        if (o->refine) {
+            double *hpsi = nullptr;
+            if (dt == HUB_F64) {
+                hpsi = (double *)W;
+            } else {
+                HUB_TRY(mem.alloc((void **)&hpsi, sizeof(double) * (size_t)n));
+            }
+            HUB_TRY(launch_matvec(s, HUB_F64, psi, hpsi, st));
+            HUB_TRY(launch_dot(HUB_F64, psi, hpsi, n, partial, d_misc + 4, 0, st));
+            HUB_TRY(launch_residual(hpsi, psi, d_misc + 4, n, partial, d_misc + 5, st));
+            double h2[2];
+            HUB_HIP(hipMemcpyAsync(h2, d_misc + 4, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+            HUB_HIP(hipStreamSynchronize(st));
+            inf.e0_refined = h2[0];
+            inf.true_residual = h2[1];
+            e0 = h2[0];
+        }
+    }
+    HUB_HIP(hipStreamSynchronize(st));
+    if (tm.on) inf.matvec_ms = tm.total_ms();
+    inf.seconds = std::chrono::duration<double>(clk::now() - t0).count();
+    if (e0_out) *e0_out = e0;
+    if (info) *info = inf;
+    if (!converged) {
+        set_error("Lanczos did not converge within max_iter");
+        return HUB_ERR_NOT_CONVERGED;
+    }
+    return HUB_OK;
+}
+
+}  // namespace hub

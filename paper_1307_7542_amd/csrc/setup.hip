@@ -1,0 +1,289 @@
+// Sector set-up kernels: one-spin bases, ranks, hopping matrices H_sigma in CSR,
+// per-state on-site energy sums.
+//
+// Basis (Sec. II, Algorithm I of Appendix A): the states of N electrons on M
+// sites, as occupation integers in ascending order.  Instead of scanning 2^M
+// integers, lane r builds the r-th state directly by the combinatorial number
+// system: the ascending order of N-bit integers is the colexicographic order of
+// their set-bit positions b_1 < ... < b_N, and the position of such an integer is
+//     rank(x) = sum_{k=1..N} C(b_k, k).
+// Unrank picks, for k = N down to 1, the largest c with C(c, k) <= r.
+//
+// Hopping matrix (Sec. III A, Sec. IV A): for state p and a canonical bond (i, j)
+// with exactly one end occupied, the hopped state is l = p xor (2^i | 2^j), the
+// sign is esign = (-1)^(popcount of p strictly between i and j), and the stored
+// element is -t_ij * esign in column rank(l).  Rows are built in two passes
+// (count, exclusive scan, fill); within a row entries are placed by the numeric
+// order of the hopped states, which is their column order because rank is
+// monotone.
+#include "internal.h"
+
+namespace hub {
+namespace {
+
+__device__ __forceinline__ int64_t d_rank(uint32_t x, const uint64_t *__restrict__ C)
+{
+    int64_t r = 0;
+    int k = 1;
+    while (x) {
+        const int b = __builtin_ctz(x);
+        r += (int64_t)C[b * kBinomN + k];
+        ++k;
+        x &= x - 1u;
+    }
+    return r;
+}
+
+__global__ void k_unrank(uint32_t *__restrict__ basis, int64_t count, int M, int N,
+                         const uint64_t *__restrict__ C)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    uint64_t rem = (uint64_t)r;
+    uint32_t x = 0;
+    int c = M - 1;
+    for (int k = N; k >= 1; --k) {
+        while (C[c * kBinomN + k] > rem) --c;  // stops at c >= k-1 since C(k-1, k) = 0
+        x |= 1u << c;
+        rem -= C[c * kBinomN + k];
+        --c;
+    }
+    basis[r] = x;
+}
+
+__global__ void k_rank(const uint64_t *__restrict__ xs, int64_t n, int M, int N, const uint64_t *__restrict__ C,
+                       int64_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t x = xs[i];
+    const uint64_t lim = (M >= 32) ? (uint64_t)0xFFFFFFFFull : ((1ull << M) - 1ull);
+    if ((x & ~lim) != 0 || __popcll(x) != N) {
+        out[i] = -1;
+        return;
+    }
+    out[i] = d_rank((uint32_t)x, C);
+}
+
+__device__ __forceinline__ uint32_t between_mask(int i, int j)
+{
+    // bits strictly between i < j
+    const uint32_t below_j = (j >= 32) ? 0xFFFFFFFFu : ((1u << j) - 1u);
+    const uint32_t upto_i = (i >= 31) ? 0xFFFFFFFFu : ((1u << (i + 1)) - 1u);
+    return below_j & ~upto_i;
+}
+
+__global__ void k_csr_count(const uint32_t *__restrict__ basis, int64_t count, const int32_t *__restrict__ bi,
+                            const int32_t *__restrict__ bj, int nb, int32_t *__restrict__ rowlen)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    const uint32_t x = basis[p];
+    int n = 0;
+    for (int e = 0; e < nb; ++e) n += (int)(((x >> bi[e]) ^ (x >> bj[e])) & 1u);
+    rowlen[p] = n;
+}
+
+// Exclusive scan of rowlen into rp[0..count], in three kernels: per-block
+// inclusive scan with block totals, a single-block scan of the totals, and the
+// addition of the block offsets.
+constexpr int kScanBlock = 1024;
+
+__global__ void k_scan_local(const int32_t *__restrict__ in, int64_t n, int64_t *__restrict__ tmp,
+                             int64_t *__restrict__ block_sums)
+{
+    __shared__ int64_t s[kScanBlock];
+    const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    s[threadIdx.x] = (i < n) ? (int64_t)in[i] : 0;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        int64_t v = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+        __syncthreads();
+        s[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (i < n) tmp[i] = s[threadIdx.x];  // inclusive within the block
+    if (threadIdx.x == kScanBlock - 1) block_sums[blockIdx.x] = s[kScanBlock - 1];
+}
+
+__global__ void k_scan_sums(int64_t *__restrict__ block_sums, int64_t nblocks)
+{
+    // single block; sequential carry over chunks of kScanBlock
+    __shared__ int64_t s[kScanBlock];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nblocks; base += kScanBlock) {
+        const int64_t i = base + threadIdx.x;
+        s[threadIdx.x] = (i < nblocks) ? block_sums[i] : 0;
+        __syncthreads();
+        for (int off = 1; off < kScanBlock; off <<= 1) {
+            int64_t v = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+            __syncthreads();
+            s[threadIdx.x] += v;
+            __syncthreads();
+        }
+        const int64_t excl = carry + s[threadIdx.x] - ((i < nblocks) ? block_sums[i] : 0);
+        __syncthreads();
+        if (i < nblocks) block_sums[i] = excl;  // exclusive offset of block i
+        if (threadIdx.x == kScanBlock - 1) carry += s[kScanBlock - 1];
+        __syncthreads();
+    }
+}
+
+__global__ void k_scan_finish(const int32_t *__restrict__ in, const int64_t *__restrict__ tmp,
+                              const int64_t *__restrict__ block_off, int64_t n, int32_t *__restrict__ rp)
+{
+    const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    if (i < n) {
+        const int64_t incl = tmp[i] + block_off[blockIdx.x];
+        rp[i + 1] = (int32_t)incl;
+        if (i == 0) rp[0] = 0;
+        (void)in;
+    }
+}
+
+__global__ void k_csr_fill(const uint32_t *__restrict__ basis, int64_t count, const int32_t *__restrict__ bi,
+                           const int32_t *__restrict__ bj, const double *__restrict__ t, int nb,
+                           const uint64_t *__restrict__ C, const int32_t *__restrict__ rp,
+                           int32_t *__restrict__ col, double *__restrict__ val64, float *__restrict__ val32,
+                           int32_t *__restrict__ bond)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    const uint32_t x = basis[p];
+    const int base = rp[p];
+    for (int e = 0; e < nb; ++e) {
+        const int i = bi[e], j = bj[e];
+        if ((((x >> i) ^ (x >> j)) & 1u) == 0) continue;
+        const uint32_t l = x ^ ((1u << i) | (1u << j));
+        int pos = 0;
+        for (int e2 = 0; e2 < nb; ++e2) {
+            const int i2 = bi[e2], j2 = bj[e2];
+            if ((((x >> i2) ^ (x >> j2)) & 1u) == 0) continue;
+            pos += (int)((x ^ ((1u << i2) | (1u << j2))) < l);
+        }
+        const int between = __popc(x & between_mask(i, j));
+        const double v = (between & 1) ? t[e] : -t[e];  // -t * esign
+        col[base + pos] = (int32_t)d_rank(l, C);
+        val64[base + pos] = v;
+        val32[base + pos] = (float)v;
+        bond[base + pos] = e;
+    }
+}
+
+__global__ void k_site_energy(const uint32_t *__restrict__ basis, int64_t count, int M,
+                              const double *__restrict__ eps, double *__restrict__ e64, float *__restrict__ e32)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    const uint32_t x = basis[p];
+    double s = 0.0;
+    for (int i = 0; i < M; ++i)
+        if ((x >> i) & 1u) s += eps[i];
+    e64[p] = s;
+    e32[p] = (float)s;
+}
+
+__global__ void k_max_row(const int32_t *__restrict__ rp, int64_t count, int32_t *__restrict__ out)
+{
+    __shared__ int32_t s[256];
+    int32_t m = 0;
+    for (int64_t p = threadIdx.x; p < count; p += 256) m = max(m, rp[p + 1] - rp[p]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < (unsigned)off) s[threadIdx.x] = max(s[threadIdx.x], s[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+template <typename T>
+hub_status dalloc(hub_sector *s, T **p, size_t n)
+{
+    void *q = nullptr;
+    const size_t bytes = (n == 0 ? 1 : n) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? HUB_ERR_OOM : HUB_ERR_DEVICE;
+    }
+    s->owned.push_back(q);
+    *p = (T *)q;
+    return HUB_OK;
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+hub_status build_spin_tables(hub_sector *s, int spin, int N, hipStream_t st)
+{
+    SpinTables &T = s->spin[spin];
+    T.N = N;
+    // count = C(M, N) from the host copy of the table row
+    uint64_t C[kBinomN][kBinomN] = {};
+    for (int n = 0; n < kBinomN; ++n) {
+        C[n][0] = 1;
+        for (int k = 1; k <= n; ++k) C[n][k] = C[n - 1][k - 1] + (k <= n - 1 ? C[n - 1][k] : 0);
+    }
+    T.count = (int64_t)C[s->M][N];
+    const int64_t count = T.count;
+    if ((int64_t)count * (int64_t)(s->nb > 0 ? s->nb : 1) >= ((int64_t)1 << 31)) {
+        set_error("hopping matrix would exceed 2^31 entries");
+        return HUB_ERR_RANGE;
+    }
+    HUB_TRY(dalloc(s, &T.basis, count));
+    HUB_TRY(dalloc(s, &T.rp, count + 1));
+    HUB_TRY(dalloc(s, &T.e64, count));
+    HUB_TRY(dalloc(s, &T.e32, count));
+    int32_t *rowlen = nullptr;
+    int64_t *tmp = nullptr, *bsum = nullptr;
+    int32_t *dmax = nullptr;
+    const int64_t nblk = (count + kScanBlock - 1) / kScanBlock;
+    HUB_TRY(dalloc(s, &rowlen, count));
+    HUB_TRY(dalloc(s, &tmp, count));
+    HUB_TRY(dalloc(s, &bsum, nblk));
+    HUB_TRY(dalloc(s, &dmax, 1));
+
+    const int B = 256;
+    hipLaunchKernelGGL(k_unrank, dim3(grid_for(count, B)), dim3(B), 0, st, T.basis, count, s->M, N, s->d_binom);
+    hipLaunchKernelGGL(k_csr_count, dim3(grid_for(count, B)), dim3(B), 0, st, T.basis, count, s->d_bi, s->d_bj,
+                       s->nb, rowlen);
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, rowlen, count, tmp, bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, bsum, nblk);
+    hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, rowlen, tmp, bsum, count,
+                       T.rp);
+    HUB_HIP(hipGetLastError());
+    int32_t nnz32 = 0;
+    HUB_HIP(hipMemcpyAsync(&nnz32, T.rp + count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    T.nnz = nnz32;
+    HUB_TRY(dalloc(s, &T.col, T.nnz));
+    HUB_TRY(dalloc(s, &T.val64, T.nnz));
+    HUB_TRY(dalloc(s, &T.val32, T.nnz));
+    HUB_TRY(dalloc(s, &T.bond, T.nnz));
+    hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(count, B)), dim3(B), 0, st, T.basis, count, s->d_bi, s->d_bj,
+                       s->d_t, s->nb, s->d_binom, T.rp, T.col, T.val64, T.val32, T.bond);
+    hipLaunchKernelGGL(k_site_energy, dim3(grid_for(count, B)), dim3(B), 0, st, T.basis, count, s->M, s->d_eps,
+                       T.e64, T.e32);
+    hipLaunchKernelGGL(k_max_row, dim3(1), dim3(256), 0, st, T.rp, count, dmax);
+    HUB_HIP(hipGetLastError());
+    HUB_HIP(hipMemcpyAsync(&T.max_row, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    return HUB_OK;
+}
+
+hub_status rank_device(const hub_sector *s, int spin, const uint64_t *dx, int64_t n, int64_t *dout,
+                       hipStream_t st)
+{
+    if (n <= 0) return HUB_OK;
+    const int B = 256;
+    hipLaunchKernelGGL(k_rank, dim3(grid_for(n, B)), dim3(B), 0, st, dx, n, s->M, s->spin[spin].N, s->d_binom,
+                       dout);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+}  // namespace hub

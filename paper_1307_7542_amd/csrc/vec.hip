@@ -1,0 +1,470 @@
+// Vector kernels of the Lanczos iteration (Sec. IV): start vector, FP64
+// reductions, the three-term recurrence updates, Gram-Schmidt against stored
+// Lanczos vectors, and the assembly / normalisation of the eigenvector.
+//
+// Reductions are deterministic: a fixed number of blocks (a function of n
+// only) each reduce a contiguous stride pattern into one FP64 partial with an
+// LDS tree, and a single block sums the partials in a fixed order.  Repeating
+// a computation therefore reproduces it bit for bit, which the two-pass
+// eigenvector assembly relies on.
+//
+// Vectors of FP32 ("mixed") or FP64 storage; every scalar (alpha, beta, Gram
+// coefficients, norms) is FP64 and every update is evaluated in FP64 and
+// rounded once to the storage type.
+#include "internal.h"
+
+namespace hub {
+namespace {
+
+constexpr int RB = kRedBlock;
+
+__device__ __forceinline__ double block_sum(double v, double *s)
+{
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = RB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < (unsigned)off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    const double r = s[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double splitmix_entry(uint64_t seed, int64_t k)
+{
+    // SplitMix64 (Steele, Lea & Flood 2014) output for state seed + (k+1) gamma,
+    // top 53 bits as a uniform in [0, 1), mapped to [-1, 1).
+    uint64_t z = seed + (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return -1.0 + 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0));
+}
+
+template <typename T>
+__global__ void k_start(T *__restrict__ out, int64_t n, uint64_t seed)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (T)splitmix_entry(seed, i);
+}
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_dot(const T *__restrict__ x, const T *__restrict__ y, int64_t n,
+                                            double *__restrict__ partial)
+{
+    __shared__ double s[RB];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB)
+        acc += (double)x[i] * (double)y[i];
+    const double r = block_sum(acc, s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(RB) void k_final(const double *__restrict__ partial, int np, double *__restrict__ out,
+                                              int sqrt_result)
+{
+    __shared__ double s[RB];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += RB) acc += partial[i];
+    const double r = block_sum(acc, s);
+    if (threadIdx.x == 0) *out = sqrt_result ? sqrt(r) : r;
+}
+
+template <typename Ti, typename To>
+__global__ void k_convert(const Ti *__restrict__ x, To *__restrict__ y, int64_t n, const double *__restrict__ sc,
+                          int invert)
+{
+    // invert: divide by the scalar (a unit vector of one entry comes out as exactly +-1)
+    const double f = sc ? *sc : 1.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (To)(invert ? (double)x[i] / f : (double)x[i] * f);
+}
+
+// w <- w - beta * vprev ; partial alpha = <w, v>
+template <typename T>
+__global__ __launch_bounds__(RB) void k_lz_a(T *__restrict__ w, const T *__restrict__ vprev,
+                                             const double *__restrict__ beta, const T *__restrict__ v, int64_t n,
+                                             double *__restrict__ partial)
+{
+    __shared__ double s[RB];
+    const double bt = vprev ? *beta : 0.0;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
+        T wi = w[i];
+        if (vprev) {
+            wi = (T)((double)wi - bt * (double)vprev[i]);
+            w[i] = wi;
+        }
+        acc += (double)wi * (double)v[i];
+    }
+    const double r = block_sum(acc, s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// w <- w - alpha * v ; partial beta^2 = <w, w>
+template <typename T>
+__global__ __launch_bounds__(RB) void k_lz_b(T *__restrict__ w, const T *__restrict__ v,
+                                             const double *__restrict__ alpha, int64_t n,
+                                             double *__restrict__ partial)
+{
+    __shared__ double s[RB];
+    const double al = *alpha;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
+        const T wi = (T)((double)w[i] - al * (double)v[i]);
+        w[i] = wi;
+        acc += (double)wi * (double)wi;
+    }
+    const double r = block_sum(acc, s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+template <typename T>
+__global__ void k_lz_next(const T *__restrict__ w, T *__restrict__ vnext, const double *__restrict__ beta, int64_t n)
+{
+    const double bt = *beta;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        vnext[i] = (bt > 0.0) ? (T)((double)w[i] / bt) : (T)0;
+}
+
+// Second pass: the same two roundings as k_lz_a followed by k_lz_b.
+template <typename T>
+__global__ void k_lz_replay(T *__restrict__ w, const T *__restrict__ vprev, const double *__restrict__ beta,
+                            const T *__restrict__ v, const double *__restrict__ alpha, int64_t n)
+{
+    const double bt = vprev ? *beta : 0.0;
+    const double al = *alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        T wi = w[i];
+        if (vprev) wi = (T)((double)wi - bt * (double)vprev[i]);
+        w[i] = (T)((double)wi - al * (double)v[i]);
+    }
+}
+
+template <typename T>
+__global__ void k_psi_acc(double *__restrict__ psi, const T *__restrict__ v, const double *__restrict__ y, int64_t n,
+                          int first)
+{
+    const double c = *y;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        psi[i] = (first ? 0.0 : psi[i]) + c * (double)v[i];
+}
+
+// Gram coefficients c_j = <q_j, w> for the stored vectors, 8 at a time so w is
+// read once per group of 8.  partial layout: [block][j].
+constexpr int GJ = 8;
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_gram_dot(const T *const *__restrict__ Q, int k, const T *__restrict__ w,
+                                                 int64_t n, double *__restrict__ partial, int kstride)
+{
+    __shared__ double s[RB];
+    for (int j0 = 0; j0 < k; j0 += GJ) {
+        double acc[GJ];
+#pragma unroll
+        for (int u = 0; u < GJ; ++u) acc[u] = 0.0;
+        const int jn = min(GJ, k - j0);
+        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
+            const double wi = (double)w[i];
+#pragma unroll
+            for (int u = 0; u < GJ; ++u)
+                if (u < jn) acc[u] += (double)Q[j0 + u][i] * wi;
+        }
+        for (int u = 0; u < jn; ++u) {
+            const double r = block_sum(acc[u], s);
+            if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * kstride + j0 + u] = r;
+        }
+    }
+}
+
+__global__ void k_gram_final(const double *__restrict__ partial, int np, int k, int kstride,
+                             double *__restrict__ coef)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    double acc = 0.0;
+    for (int b = 0; b < np; ++b) acc += partial[(int64_t)b * kstride + j];
+    coef[j] = acc;
+}
+
+// w <- w - sum_j c_j q_j, evaluated in FP64 per element.
+template <typename T>
+__global__ void k_gram_update(const T *const *__restrict__ Q, int k, const double *__restrict__ coef,
+                              T *__restrict__ w, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc += coef[j] * (double)Q[j][i];
+        w[i] = (T)((double)w[i] - acc);
+    }
+}
+
+template <typename T>
+__global__ void k_psi_basis(const T *const *__restrict__ Q, int k, const double *__restrict__ y,
+                            double *__restrict__ psi, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc += y[j] * (double)Q[j][i];
+        psi[i] = acc;
+    }
+}
+
+// Per block: max |psi| and its lowest index; then sum of squares.
+__global__ __launch_bounds__(RB) void k_absmax(const double *__restrict__ x, int64_t n, double *__restrict__ pv,
+                                               int64_t *__restrict__ pi)
+{
+    __shared__ double sv[RB];
+    __shared__ int64_t si[RB];
+    double best = -1.0;
+    int64_t bi = 0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
+        const double a = fabs(x[i]);
+        if (a > best) { best = a; bi = i; }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = RB / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < (unsigned)off) {
+            const double a = sv[threadIdx.x + off];
+            const int64_t ai = si[threadIdx.x + off];
+            if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ai < si[threadIdx.x])) {
+                sv[threadIdx.x] = a;
+                si[threadIdx.x] = ai;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { pv[blockIdx.x] = sv[0]; pi[blockIdx.x] = si[0]; }
+}
+
+// scal[0] = sum of squares (already reduced), finds the sign of the entry with
+// the largest magnitude and stores scal[1] = sign / norm.
+__global__ void k_sign_scale(const double *__restrict__ x, const double *__restrict__ pv,
+                             const int64_t *__restrict__ pi, int np, double *__restrict__ scal)
+{
+    if (threadIdx.x != 0) return;
+    double best = -1.0;
+    int64_t bi = 0;
+    for (int b = 0; b < np; ++b)
+        if (pv[b] > best || (pv[b] == best && pi[b] < bi)) { best = pv[b]; bi = pi[b]; }
+    const double nrm = sqrt(scal[0]);
+    const double sg = (x[bi] < 0.0) ? -1.0 : 1.0;
+    scal[1] = (nrm > 0.0) ? sg / nrm : 0.0;
+}
+
+__global__ void k_scale_inplace(double *__restrict__ x, int64_t n, const double *__restrict__ f)
+{
+    const double c = *f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] *= c;
+}
+
+__global__ __launch_bounds__(RB) void k_resid(const double *__restrict__ hp, const double *__restrict__ p,
+                                              const double *__restrict__ e, int64_t n, double *__restrict__ partial)
+{
+    __shared__ double s[RB];
+    const double E = *e;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
+        const double r = hp[i] - E * p[i];
+        acc += r * r;
+    }
+    const double r = block_sum(acc, s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+inline unsigned ew_grid(int64_t n)
+{
+    const int64_t g = (n + 255) / 256;
+    return (unsigned)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
+}
+
+}  // namespace
+
+int red_grid(int64_t n)
+{
+    int64_t g = (n + (int64_t)RB * 4 - 1) / ((int64_t)RB * 4);
+    if (g < 1) g = 1;
+    if (g > kRedGrid) g = kRedGrid;
+    return (int)g;
+}
+
+#define HUB_DISPATCH(dtype, KERNEL, ...)                                                            \
+    do {                                                                                            \
+        if ((dtype) == HUB_F64) hipLaunchKernelGGL(KERNEL<double>, __VA_ARGS__);                    \
+        else hipLaunchKernelGGL(KERNEL<float>, __VA_ARGS__);                                       \
+    } while (0)
+
+hub_status launch_start_vector(int dtype, uint64_t seed, void *out, int64_t n, hipStream_t st)
+{
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_start<double>, dim3(ew_grid(n)), dim3(256), 0, st, (double *)out, n, seed);
+    else
+        hipLaunchKernelGGL(k_start<float>, dim3(ew_grid(n)), dim3(256), 0, st, (float *)out, n, seed);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_dot(int dtype, const void *x, const void *y, int64_t n, double *partial, double *out,
+                      int sqrt_result, hipStream_t st)
+{
+    const int G = red_grid(n);
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_dot<double>, dim3(G), dim3(RB), 0, st, (const double *)x, (const double *)y, n,
+                           partial);
+    else
+        hipLaunchKernelGGL(k_dot<float>, dim3(G), dim3(RB), 0, st, (const float *)x, (const float *)y, n, partial);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, G, out, sqrt_result);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_convert(int din, const void *x, int dout, void *y, int64_t n, const double *sc, int invert,
+                          hipStream_t st)
+{
+    const dim3 g(ew_grid(n)), b(256);
+    if (din == HUB_F64 && dout == HUB_F64)
+        hipLaunchKernelGGL((k_convert<double, double>), g, b, 0, st, (const double *)x, (double *)y, n, sc, invert);
+    else if (din == HUB_F64 && dout == HUB_F32)
+        hipLaunchKernelGGL((k_convert<double, float>), g, b, 0, st, (const double *)x, (float *)y, n, sc, invert);
+    else if (din == HUB_F32 && dout == HUB_F64)
+        hipLaunchKernelGGL((k_convert<float, double>), g, b, 0, st, (const float *)x, (double *)y, n, sc, invert);
+    else
+        hipLaunchKernelGGL((k_convert<float, float>), g, b, 0, st, (const float *)x, (float *)y, n, sc, invert);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_lz_a(int dtype, void *w, const void *vprev, const double *beta, const void *v, int64_t n,
+                       double *partial, double *alpha_out, hipStream_t st)
+{
+    const int G = red_grid(n);
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_lz_a<double>, dim3(G), dim3(RB), 0, st, (double *)w, (const double *)vprev, beta,
+                           (const double *)v, n, partial);
+    else
+        hipLaunchKernelGGL(k_lz_a<float>, dim3(G), dim3(RB), 0, st, (float *)w, (const float *)vprev, beta,
+                           (const float *)v, n, partial);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, G, alpha_out, 0);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_lz_b(int dtype, void *w, const void *v, const double *alpha, int64_t n, double *partial,
+                       double *beta_out, hipStream_t st)
+{
+    const int G = red_grid(n);
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_lz_b<double>, dim3(G), dim3(RB), 0, st, (double *)w, (const double *)v, alpha, n,
+                           partial);
+    else
+        hipLaunchKernelGGL(k_lz_b<float>, dim3(G), dim3(RB), 0, st, (float *)w, (const float *)v, alpha, n,
+                           partial);
+    if (beta_out) hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, G, beta_out, 1);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_lz_next(int dtype, const void *w, void *vnext, const double *beta, int64_t n, hipStream_t st)
+{
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_lz_next<double>, dim3(ew_grid(n)), dim3(256), 0, st, (const double *)w,
+                           (double *)vnext, beta, n);
+    else
+        hipLaunchKernelGGL(k_lz_next<float>, dim3(ew_grid(n)), dim3(256), 0, st, (const float *)w, (float *)vnext,
+                           beta, n);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_lz_replay(int dtype, void *w, const void *vprev, const double *beta, const void *v,
+                            const double *alpha, int64_t n, hipStream_t st)
+{
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_lz_replay<double>, dim3(ew_grid(n)), dim3(256), 0, st, (double *)w,
+                           (const double *)vprev, beta, (const double *)v, alpha, n);
+    else
+        hipLaunchKernelGGL(k_lz_replay<float>, dim3(ew_grid(n)), dim3(256), 0, st, (float *)w,
+                           (const float *)vprev, beta, (const float *)v, alpha, n);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_psi_acc(int dtype, double *psi, const void *v, const double *ycoef, int64_t n, int first,
+                          hipStream_t st)
+{
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_psi_acc<double>, dim3(ew_grid(n)), dim3(256), 0, st, psi, (const double *)v, ycoef, n,
+                           first);
+    else
+        hipLaunchKernelGGL(k_psi_acc<float>, dim3(ew_grid(n)), dim3(256), 0, st, psi, (const float *)v, ycoef, n,
+                           first);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+// coef must hold k doubles; partial must hold red_grid(n) * kmax doubles with kmax >= k.
+hub_status launch_gram(int dtype, const void *const *dQ, int k, void *w, int64_t n, double *partial, double *coef,
+                       hipStream_t st)
+{
+    if (k <= 0) return HUB_OK;
+    const int G = red_grid(n);
+    if (dtype == HUB_F64) {
+        hipLaunchKernelGGL(k_gram_dot<double>, dim3(G), dim3(RB), 0, st, (const double *const *)dQ, k,
+                           (const double *)w, n, partial, k);
+    } else {
+        hipLaunchKernelGGL(k_gram_dot<float>, dim3(G), dim3(RB), 0, st, (const float *const *)dQ, k,
+                           (const float *)w, n, partial, k);
+    }
+    hipLaunchKernelGGL(k_gram_final, dim3((k + 255) / 256), dim3(256), 0, st, partial, G, k, k, coef);
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_gram_update<double>, dim3(ew_grid(n)), dim3(256), 0, st, (const double *const *)dQ, k,
+                           coef, (double *)w, n);
+    else
+        hipLaunchKernelGGL(k_gram_update<float>, dim3(ew_grid(n)), dim3(256), 0, st, (const float *const *)dQ, k,
+                           coef, (float *)w, n);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_psi_from_basis(int dtype, const void *const *dQ, int k, const double *ycoef, double *psi,
+                                 int64_t n, hipStream_t st)
+{
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_psi_basis<double>, dim3(ew_grid(n)), dim3(256), 0, st, (const double *const *)dQ, k,
+                           ycoef, psi, n);
+    else
+        hipLaunchKernelGGL(k_psi_basis<float>, dim3(ew_grid(n)), dim3(256), 0, st, (const float *const *)dQ, k,
+                           ycoef, psi, n);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+// scal: 2 doubles of device scratch; partial: red_grid(n) doubles + red_grid(n) int64.
+hub_status launch_normalize_sign(double *psi, int64_t n, double *partial, double *scal, hipStream_t st)
+{
+    const int G = red_grid(n);
+    HUB_TRY(launch_dot(HUB_F64, psi, psi, n, partial, scal, 0, st));
+    double *pv = partial;
+    int64_t *pi = (int64_t *)(partial + kRedGrid);
+    hipLaunchKernelGGL(k_absmax, dim3(G), dim3(RB), 0, st, psi, n, pv, pi);
+    hipLaunchKernelGGL(k_sign_scale, dim3(1), dim3(64), 0, st, psi, pv, pi, G, scal);
+    hipLaunchKernelGGL(k_scale_inplace, dim3(ew_grid(n)), dim3(256), 0, st, psi, n, scal + 1);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_residual(const double *hpsi, const double *psi, const double *e, int64_t n, double *partial,
+                           double *out, hipStream_t st)
+{
+    const int G = red_grid(n);
+    hipLaunchKernelGGL(k_resid, dim3(G), dim3(RB), 0, st, hpsi, psi, e, n, partial);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, G, out, 1);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+}  // namespace hub

@@ -1,0 +1,90 @@
+"""CPU checks of the C ABI boundary: the library loads, exports every function
+declared in include/hubbard.h, and rejects bad arguments with status codes
+before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hubbard.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hub_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1307_7542_amd as hub
+    return hub.lib()
+
+
+def test_header_declares_expected_api():
+    names = declared_functions()
+    for n in ["hub_sector_create", "hub_matvec", "hub_ground_state", "hub_basis", "hub_hopping_csr",
+              "hub_rank", "hub_param_bilinear"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_function(L):
+    import paper_1307_7542_amd as hub
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert sorted(hub.EXPORTED) == declared_functions()
+
+
+def test_status_strings(L):
+    assert L.hub_status_str(0) == b"HUB_OK"
+    assert L.hub_status_str(2) == b"HUB_ERR_RANGE"
+    assert L.hub_status_str(99) == b"HUB_ERR_UNKNOWN"
+    assert b"gfx950" in L.hub_version()
+
+
+def _model(M, bonds, t, U=None):
+    import paper_1307_7542_amd as hub
+    bi = (ctypes.c_int32 * max(1, len(bonds)))(*[b[0] for b in bonds])
+    bj = (ctypes.c_int32 * max(1, len(bonds)))(*[b[1] for b in bonds])
+    tt = (ctypes.c_double * max(1, len(t)))(*t)
+    UU = (ctypes.c_double * max(1, M))(*(U if U is not None else [0.0] * max(1, M)))
+    m = hub._Model(M, len(bonds), ctypes.cast(bi, ctypes.c_void_p), ctypes.cast(bj, ctypes.c_void_p),
+                   ctypes.cast(tt, ctypes.c_void_p), ctypes.cast(UU, ctypes.c_void_p), None)
+    return m, (bi, bj, tt, UU)
+
+
+@pytest.mark.parametrize("M,n_up,n_dn,bonds,t,code", [
+    (0, 0, 0, [], [], 2),            # M out of range
+    (33, 1, 1, [], [], 2),
+    (4, 5, 1, [(0, 1)], [1.0], 2),   # N > M
+    (4, -1, 1, [(0, 1)], [1.0], 2),
+    (4, 2, 2, [(0, 4)], [1.0], 1),   # bond endpoint out of range
+    (4, 2, 2, [(2, 2)], [1.0], 1),   # i == j
+    (4, 2, 2, [(0, 1)], [float("nan")], 1),
+    (4, 2, 2, [(0, 1)], [float("inf")], 1),
+])
+def test_create_rejects_bad_input(L, M, n_up, n_dn, bonds, t, code):
+    m, keep = _model(M, bonds, t)
+    h = ctypes.c_void_p()
+    st = L.hub_sector_create(ctypes.byref(m), n_up, n_dn, ctypes.byref(h))
+    assert st == code
+    assert h.value is None
+    assert len(L.hub_last_error()) > 0
+
+
+def test_null_arguments(L):
+    h = ctypes.c_void_p()
+    assert L.hub_sector_create(None, 1, 1, ctypes.byref(h)) == 1
+    m, keep = _model(4, [(0, 1)], [1.0])
+    assert L.hub_sector_create(ctypes.byref(m), 1, 1, None) == 1
+    assert L.hub_matvec(None, 0, None, None, None) == 1
+    assert L.hub_sector_dims(None, None, None, None) == 1
+    L.hub_sector_destroy(None)
+
+
+def test_nonfinite_U_rejected(L):
+    m, keep = _model(3, [(0, 1)], [1.0], U=[1.0, float("nan"), 0.0])
+    h = ctypes.c_void_p()
+    assert L.hub_sector_create(ctypes.byref(m), 1, 1, ctypes.byref(h)) == 1

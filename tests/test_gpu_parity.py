@@ -1,0 +1,423 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bit-exact: bases, ranks, hopping-matrix columns, values (exact negations of t)
+and bond ids, start vectors.  Floating point: the product within
+1e-13 * sum_J |H_IJ x_J| (FP64) and 1e-5 * sum_J |H_IJ x_J| (FP32 with FP32
+accumulation, about 17 rounded terms per row); ground energies within 1e-10
+relative (FP64) and 1e-6 relative (mixed).
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def hub():
+    import torch
+    import paper_1307_7542_amd as hub
+    hub.lib()
+    torch.cuda.set_device(0)
+    return hub
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _nonuniform_models():
+    ms = [W.random_graph(7, 10, seed=s, site_U=True) for s in (101, 102)]
+    ms.append(W.aim_batch(4)[1])
+    return ms
+
+
+# ------------------------------------------------------------ bases ----
+
+@pytest.mark.parametrize("M", [1, 2, 3, 5, 8, 13, 16, 20])
+def test_basis_bit_exact(hub, M):
+    for N in sorted({0, 1, M // 3, M // 2, M - 1, M}):
+        if N < 0 or N > M:
+            continue
+        m = W.Model("chain", M, [], [], [1.0] * M, [0.0] * M, N, max(0, min(M, M - N)))
+        s = hub.Sector(m)
+        ref = oracle.enumerate_basis(M, N)
+        assert np.array_equal(s.basis(0), ref)
+        assert s.count_up == math.comb(M, N)
+        s.close()
+
+
+def test_basis_m32_edges(hub):
+    for N in (0, 1, 2, 31, 32):
+        m = W.Model("m32", 32, [], [], [0.0] * 32, [0.0] * 32, N, N)
+        s = hub.Sector(m)
+        ref = sorted(sum(1 << p for p in c) for c in itertools.combinations(range(32), N))
+        assert s.basis(0).tolist() == ref
+        s.close()
+
+
+def test_rank_bit_exact_and_invalid(hub):
+    M, N = 12, 5
+    m = W.Model("r", M, [], [], [0.0] * M, [0.0] * M, N, N)
+    s = hub.Sector(m)
+    basis = oracle.enumerate_basis(M, N)
+    rng = np.random.default_rng(3)
+    xs = np.concatenate([basis, rng.integers(0, 1 << 14, size=3000).astype(np.uint64),
+                         np.array([0, (1 << 12) - 1, 1 << 40, (1 << 64) - 1], dtype=np.uint64)])
+    got = s.rank(0, xs)
+    pos = {int(v): i for i, v in enumerate(basis)}
+    exp = np.array([pos.get(int(v), -1) for v in xs], dtype=np.int64)
+    assert np.array_equal(got, exp)
+    s.close()
+
+
+# ------------------------------------------------------ hopping CSR ----
+
+def _project_sigma(osec, spin):
+    """H_sigma read off the oracle's full H: entries whose other-spin part is
+    unchanged, taken at the first other-spin state."""
+    rp, col, val = osec.csr()
+    M = osec.m.M
+    cu, cd = osec.cu, osec.cd
+    rows = {}
+    if spin == 0:
+        for a in range(cu):
+            r = a  # b = 0
+            ent = []
+            for k in range(rp[r], rp[r + 1]):
+                c = int(col[k])
+                if c != r and c // cu == 0:
+                    ent.append((c % cu, val[k]))
+            rows[a] = ent
+        n = cu
+    else:
+        for b in range(cd):
+            r = b * cu  # a = 0
+            ent = []
+            for k in range(rp[r], rp[r + 1]):
+                c = int(col[k])
+                if c != r and c % cu == 0:
+                    ent.append((c // cu, val[k]))
+            rows[b] = ent
+        n = cd
+    del M
+    return [rows[i] for i in range(n)]
+
+
+@pytest.mark.parametrize("which", ["ring8", "rand7a", "rand7b", "aim", "square3x3", "ring6_32"])
+def test_hopping_csr_bit_exact(hub, which):
+    if which == "ring8":
+        m = W.config("ring8")
+    elif which == "rand7a":
+        m = W.random_graph(7, 12, seed=201).with_params(n_up=3, n_dn=4)
+    elif which == "rand7b":
+        m = W.random_graph(7, 21, seed=202).with_params(n_up=2, n_dn=5)
+    elif which == "aim":
+        m = W.aim_batch(3)[0]
+    elif which == "square3x3":
+        m = W.square_periodic(3, 3, n_up=4, n_dn=3)
+    else:
+        m = W.ring(6, n_up=3, n_dn=2)
+    s = hub.Sector(m)
+    osec = oracle.Sector(m)
+    bi, bj, tt = s.bonds()
+    for spin in (0, 1):
+        rp, col, val, bond = s.hopping_csr(spin)
+        ref = _project_sigma(osec, spin)
+        basis = s.basis(spin)
+        assert rp[0] == 0 and rp[-1] == len(col)
+        for p, ent in enumerate(ref):
+            got_c = col[rp[p]:rp[p + 1]].tolist()
+            got_v = val[rp[p]:rp[p + 1]].tolist()
+            assert got_c == [c for c, _ in ent], (spin, p)
+            assert got_v == [v for _, v in ent], (spin, p)
+            for k in range(rp[p], rp[p + 1]):
+                mask = int(basis[p]) ^ int(basis[col[k]])
+                e = bond[k]
+                assert mask == (1 << int(bi[e])) | (1 << int(bj[e]))
+        N = m.n_up if spin == 0 else m.n_dn
+        if m.n_sites > 2 and 0 < N < m.n_sites:
+            assert len(col) == 2 * len(bi) * math.comb(m.n_sites - 2, N - 1)
+    s.close()
+
+
+def test_shared_tables_when_sz0(hub):
+    m = W.config("ring8")
+    s = hub.Sector(m)
+    a = s.hopping_csr(0)
+    b = s.hopping_csr(1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    s.close()
+
+
+def test_duplicate_bonds_merged(hub):
+    m = W.ring(5, n_up=2, n_dn=2)
+    m2 = m.with_params()
+    m2.bonds = list(m.bonds) + [(1, 0), (3, 2)]
+    m2.t = list(m.t) + [0.25, -0.5]
+    s = hub.Sector(m2)
+    bi, bj, tt = s.bonds()
+    assert len(bi) == 5
+    assert tt[0] == 1.25 and tt[2] == 0.5
+    osec = oracle.Sector(m2)
+    rp, col, val, _ = s.hopping_csr(0)
+    ref = _project_sigma(osec, 0)
+    for p, ent in enumerate(ref):
+        assert col[rp[p]:rp[p + 1]].tolist() == [c for c, _ in ent]
+        np.testing.assert_allclose(val[rp[p]:rp[p + 1]], [v for _, v in ent], rtol=0, atol=1e-15)
+    s.close()
+
+
+# ---------------------------------------------------------- product ----
+
+def _row_abs(osec, x):
+    rp, col, val = osec.csr()
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.abs(val), col, rp), shape=(osec.dim, osec.dim))
+    return A @ np.abs(x)
+
+
+@pytest.mark.parametrize("which", ["ring8", "rand8", "aim", "square3x4", "ladder2x5", "ring10_odd", "dimn0"])
+def test_matvec_parity(hub, which):
+    import torch
+    if which == "ring8":
+        m = W.config("ring8")
+    elif which == "rand8":
+        m = W.random_graph(8, 14, seed=301, site_U=True).with_params(n_up=4, n_dn=3)
+    elif which == "aim":
+        m = W.aim_batch(8)[5]
+    elif which == "square3x4":
+        m = W.square_periodic(3, 4, n_up=4, n_dn=5)
+    elif which == "ladder2x5":
+        m = W.ladder(5, n_up=5, n_dn=4)
+    elif which == "ring10_odd":
+        m = W.ring(10, U=3.0, n_up=3, n_dn=6)
+    else:
+        m = W.ring(6, n_up=0, n_dn=3)
+    s = hub.Sector(m)
+    osec = oracle.Sector(m)
+    assert s.dim == osec.dim
+    x64 = s.start_vector(seed=77, normalize=False)
+    xr = oracle.start_vector(77, osec.dim)
+    assert np.array_equal(x64.cpu().numpy(), xr)
+    yr = oracle.spmv(osec.csr(), xr)
+    bound = _row_abs(osec, xr)
+    y64 = s.matvec(x64).cpu().numpy()
+    assert np.all(np.abs(y64 - yr) <= 1e-13 * bound + 1e-300)
+    x32 = x64.to(torch.float32)
+    y32 = s.matvec(x32).cpu().numpy().astype(np.float64)
+    yr32 = oracle.spmv(osec.csr(), x32.cpu().numpy().astype(np.float64))
+    assert np.all(np.abs(y32 - yr32) <= 1e-5 * bound + 1e-30)
+    # the diagonal alone
+    d = s.diagonal().cpu().numpy()
+    rp, col, val = osec.csr()
+    dr = np.array([val[rp[r]:rp[r + 1]][col[rp[r]:rp[r + 1]] == r].sum() for r in range(osec.dim)])
+    scale = np.sum(np.abs(m.U)) + 2 * np.sum(np.abs(m.eps)) + 1e-300
+    assert np.all(np.abs(d - dr) <= 1e-14 * scale)
+    s.close()
+
+
+def test_matvec_repeatable_bitwise(hub):
+    m = W.square_periodic(3, 4, n_up=5, n_dn=5)
+    s = hub.Sector(m)
+    x = s.start_vector(seed=5)
+    y1 = s.matvec(x).cpu().numpy()
+    y2 = s.matvec(x).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    s.close()
+
+
+def test_matvec_rejects_overlap(hub):
+    s = hub.Sector(W.config("ring8"))
+    x = s.start_vector(seed=1)
+    with pytest.raises(hub.HubError):
+        s.matvec(x, x)
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["ring14_u4", "square4x4"])
+def test_matvec_sampled_full_size(hub, name):
+    """Full-size workloads: rows sampled across the whole vector (first, last,
+    random) checked against the oracle's matrix-free rows on the same
+    SplitMix64 vector."""
+    m = W.config(name)
+    s = hub.Sector(m)
+    osec = oracle.Sector(m, explicit_keys=False)
+    x = s.start_vector(seed=4242, normalize=False)
+    rng = np.random.default_rng(9)
+    rows = np.unique(np.concatenate([[0, 1, s.dim - 1, s.dim - 2], rng.integers(0, s.dim, size=4000)]))
+    y = s.matvec(x)
+    yg = y[rows].cpu().numpy() if False else y.cpu().numpy()[rows]
+    yr = osec.apply_rows(rows, None, seed=4242)
+    assert np.max(np.abs(yg - yr)) <= 1e-12 * (np.max(np.abs(yr)) + 1)
+    import torch
+    y32 = s.matvec(x.to(torch.float32)).cpu().numpy()[rows].astype(np.float64)
+    assert np.max(np.abs(y32 - yr)) <= 2e-5 * (np.max(np.abs(yr)) + 1)
+    s.close()
+
+
+# ---------------------------------------------------------- Lanczos ----
+
+@pytest.mark.parametrize("which", ["ring8", "rand8", "aim0", "aim3", "dimer", "square3x3"])
+def test_ground_state_fp64_vs_dense(hub, which):
+    import torch
+    if which == "ring8":
+        m = W.config("ring8")
+    elif which == "rand8":
+        m = W.random_graph(8, 13, seed=401, site_U=True).with_params(n_up=4, n_dn=3)
+    elif which == "aim0":
+        m = W.aim_batch(1)[0]
+    elif which == "aim3":
+        m = W.aim_batch(4)[3]
+    elif which == "dimer":
+        m = W.dimer(U=4.0)
+    else:
+        m = W.square_periodic(3, 3, n_up=4, n_dn=4)
+    osec = oracle.Sector(m)
+    if osec.dim <= 5000:
+        w, v = np.linalg.eigh(osec.dense())
+        e_ref, psi_ref, gap = w[0], v[:, 0], w[1] - w[0] if len(w) > 1 else 1.0
+    else:
+        _, e_ref, psi_ref = oracle.ground_state(m, dense_max=0, tol=1e-13)
+        gap = 1.0
+    s = hub.Sector(m)
+    for reorth in (False, True):
+        gs = s.ground_state(dtype=0, reorth=reorth, refine=True, tol=1e-13)
+        assert abs(gs.e0 - e_ref) <= 1e-10 * abs(e_ref), (reorth, gs.e0, e_ref)
+        assert abs(gs.info["e0_ritz"] - e_ref) <= 1e-10 * abs(e_ref)
+        psi = gs.psi.cpu().numpy()
+        assert abs(np.linalg.norm(psi) - 1) < 1e-12
+        if gap > 1e-6:
+            assert abs(np.dot(psi, psi_ref)) >= 1 - 1e-10
+            assert np.allclose(psi, oracle.canonical_sign(psi_ref), atol=1e-6)
+    s.close()
+    del torch
+
+
+@pytest.mark.parametrize("which", ["ring8", "aim2", "rand9"])
+def test_ground_state_mixed(hub, which):
+    if which == "ring8":
+        m = W.config("ring8")
+    elif which == "aim2":
+        m = W.aim_batch(3)[2]
+    else:
+        m = W.random_graph(9, 15, seed=402).with_params(n_up=4, n_dn=4)
+    osec = oracle.Sector(m)
+    if osec.dim <= 5000:
+        e_ref = np.linalg.eigvalsh(osec.dense())[0]
+    else:
+        _, e_ref, _ = oracle.ground_state(m, dense_max=0, tol=1e-13, want_vector=False)
+    s = hub.Sector(m)
+    for reorth in (True, False):
+        gs = s.ground_state(dtype=1, reorth=reorth, refine=True)
+        assert abs(gs.info["e0_ritz"] - e_ref) <= 1e-6 * abs(e_ref)
+        assert abs(gs.e0 - e_ref) <= 1e-6 * abs(e_ref)
+    s.close()
+
+
+def test_degenerate_one_state_sectors(hub):
+    """dim = 1 (N = 0 or N = M for both spins): E0 = D exactly, breakdown at step 1."""
+    for n_up, n_dn, expect in [(0, 0, 0.0), (6, 6, 6 * 2.5), (6, 0, 0.0)]:
+        m = W.ring(6, U=2.5, n_up=n_up, n_dn=n_dn)
+        s = hub.Sector(m)
+        assert s.dim == 1
+        gs = s.ground_state(dtype=0)
+        assert gs.e0 == expect
+        assert gs.info["breakdown"] == 1
+        s.close()
+
+
+def test_t0_and_u0_closed_forms(hub):
+    m = W.ring(10, t=0.0, U=3.0, n_up=6, n_dn=7)
+    s = hub.Sector(m)
+    gs = s.ground_state(dtype=0, want_vector=False)
+    assert abs(gs.e0 - 3.0 * 3) < 1e-12
+    s.close()
+    m = W.ring(14, U=0.0, n_up=7, n_dn=7)
+    s = hub.Sector(m)
+    gs = s.ground_state(dtype=0, want_vector=False)
+    h = np.zeros((14, 14))
+    for (i, j), t in zip(m.bonds, m.t):
+        h[i, j] -= t
+        h[j, i] -= t
+    w = np.linalg.eigvalsh(h)
+    assert abs(gs.e0 - 2 * w[:7].sum()) <= 1e-10 * abs(gs.e0)
+    s.close()
+
+
+def test_table4_m14_m16(hub):
+    """Sec. V, Table IV, U=4: FP64 Lanczos on the GPU against the printed E_min
+    (values read as truncated at 10 decimals) and, for M=14, the oracle."""
+    g = _gold("table4_emin.json")
+    ov = _gold("oracle_values.json")["entries"]
+    for row in g["rows"]:
+        m = W.ring(row["M"], U=4.0, n_up=row["n_up"], n_dn=row["n_dn"])
+        s = hub.Sector(m)
+        assert s.dim == row["dim"]
+        gs = s.ground_state(dtype=0, want_vector=False, tol=1e-12)
+        assert row["E_min"] - 1e-10 < gs.e0 <= row["E_min"] + 1e-12, (row["M"], gs.e0)
+        if row["M"] == 14:
+            e_or = ov["ring14_u4"]["e0"]
+            assert abs(gs.e0 - e_or) <= 1e-10 * abs(e_or)
+        s.close()
+
+
+@pytest.mark.parametrize("name", ["ring14_u2", "ring14_u8", "square3x4_n5", "ladder2x6", "aim7", "aim40"])
+def test_ground_state_vs_stored_oracle(hub, name):
+    ov = _gold("oracle_values.json")["entries"][name]
+    if name.startswith("ring14"):
+        m = W.config(name)
+    elif name == "square3x4_n5":
+        m = W.square_periodic(3, 4, n_up=5, n_dn=5)
+    elif name == "ladder2x6":
+        m = W.ladder(6)
+    else:
+        m = W.aim_batch(64)[int(name[3:])]
+    s = hub.Sector(m)
+    assert s.dim == ov["dim"]
+    gs = s.ground_state(dtype=0, want_vector=False, tol=1e-12)
+    assert abs(gs.e0 - ov["e0"]) <= 1e-10 * abs(ov["e0"])
+    gm = s.ground_state(dtype=1, reorth=False, refine=True)
+    assert abs(gm.e0 - ov["e0"]) <= 1e-6 * abs(ov["e0"])
+    s.close()
+
+
+# ---------------------------------------------------------- adjoint ----
+
+@pytest.mark.parametrize("which", ["rand7", "aim5", "square3x3"])
+def test_param_bilinear_vs_oracle(hub, which):
+    import torch
+    if which == "rand7":
+        m = W.random_graph(7, 11, seed=501, site_U=True).with_params(n_up=3, n_dn=4)
+    elif which == "aim5":
+        m = W.aim_batch(6)[5]
+    else:
+        m = W.square_periodic(3, 3, n_up=4, n_dn=4)
+    s = hub.Sector(m)
+    osec = oracle.Sector(m)
+    g = s.start_vector(seed=1)
+    x = s.start_vector(seed=2)
+    db, dU, de = s.param_bilinear(g, x)
+    rdb, rdU, rde = osec.param_bilinear(oracle.start_vector(1, s.dim) / np.linalg.norm(oracle.start_vector(1, s.dim)),
+                                        oracle.start_vector(2, s.dim) / np.linalg.norm(oracle.start_vector(2, s.dim)))
+    np.testing.assert_allclose(db, rdb, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(dU, rdU, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(de, rde, rtol=1e-10, atol=1e-12)
+    # Hellmann-Feynman at the ground state and the Euler identity
+    gs = s.ground_state(dtype=0, tol=1e-13)
+    db, dU, de = s.param_bilinear(gs.psi, gs.psi)
+    euler = np.dot(m.t, db) + np.dot(m.U, dU) + np.dot(m.eps, de)
+    assert abs(euler - gs.e0) <= 1e-9 * abs(gs.e0)
+    s.close()
+    del torch
