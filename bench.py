@@ -1,18 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the Kronecker-sum Hubbard ground-state path on one MI355X.
 
-One step = the whole hot path on one synthetic sector, inputs (the model
-parameters) already on the host, everything else done on the GPU:
-  1. sector set-up: bases, H_up / H_dn in CSR, site-energy tables;
-  2. FP64 plain Lanczos to E0 with tol 1e-12 (reference E0);
-  3. FP64 plain Lanczos to the mixed-path tolerance (1e-7);
-  4. mixed Lanczos (FP32 vectors and products, FP64 scalars), plain
-     recurrence, eigenvector by second pass, FP64 refinement;
-  5. mixed Lanczos with full reorthogonalisation (FP64 Gram coefficients),
-     eigenvector from the stored basis, FP64 refinement.
+Workload (default): periodic chain M=14, t=1, N_up=N_dn=7 (dim 3432^2 =
+11,778,624), U in {2, 4, 8} -- the chain of the paper's Table IV.
+One step = the whole hot path for the three U values, model parameters on the
+host, everything else on the GPU:
+  1. sector set-up: bases, H_up = H_dn in CSR and sliced ELL, site energies;
+  2. plain FP64 Lanczos to E0 (Ritz residual <= 1e-12 |E0|);
+  3. mixed Lanczos: FP32 vectors and products, FP64 alpha/beta, full
+     reorthogonalisation with FP64 coefficients, FP64 tridiagonal solve,
+     eigenvector from the stored basis, FP64 refinement (Rayleigh quotient);
+  4. mixed Lanczos without reorthogonalisation (eigenvector by second pass,
+     FP64 refinement).
 Every product launch inside the timed steps is bracketed by HIP events on the
-stream it runs on; the roofline entry uses the average launch duration of the
-dominant product kernel.  Prints one JSON line.
+stream it runs on (the caller's current stream).  Prints one JSON line.
 """
 import argparse
 import json
@@ -24,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+TABLE4_M14_U4 = -8.0883491038  # Sec. V, Table IV (printed digits)
 
 
 def parse():
@@ -31,65 +33,104 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="square4x4",
-                    help="square4x4 (4x4 torus, N=7/7), ring14_u4, ladder2x9, ring8")
-    ap.add_argument("--skip-reorth", action="store_true", help="leave out step 5")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--matvec-only", type=int, default=0,
-                    help="if > 0: only time this many back-to-back products per dtype (profiling runs)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 4x4-torus product timing")
+    ap.add_argument("--copy-reference", type=int, default=0,
+                    help="profiling aid: copy a buffer of this many MiB three times (counter calibration)")
+    ap.add_argument("--matvec-only", type=str, default="",
+                    help="profiling aid: 'workload:count' times count back-to-back products per dtype")
     return ap.parse_args()
+
+
+def product_timing(hub, torch, model, reps=10):
+    """Average event time of back-to-back products on the current stream."""
+    sec = hub.Sector(model)
+    out = {}
+    for dt, name in ((hub.F32, "f32"), (hub.F64, "f64")):
+        x = sec.start_vector(seed=1, dtype=dt)
+        y = sec.empty(dt)
+        sec.matvec(x, y)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            sec.matvec(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        b = sec.matvec_bytes(dt)
+        out[name] = {"avg_ms": ms, "bytes_per_launch": b, "GBps": b / ms / 1e6, "frac": b / ms / 1e6 / HBM_PEAK_GBPS}
+        del x, y
+    out["dim"] = sec.dim
+    sec.close()
+    return out
 
 
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described "
-                                   "but not implemented", "n_gpus": max(args.gpus, world)}))
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the "
+                                   "design notes but not implemented", "n_gpus": max(args.gpus, world)}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1307_7542_amd as hub
     import workloads as W
 
     torch.cuda.set_device(0)
-    model = W.config(args.workload)
     F64, F32 = hub.F64, hub.F32
 
-    if args.matvec_only > 0:
-        sec = hub.Sector(model)
+    if args.copy_reference:
+        n = args.copy_reference * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copied {args.copy_reference} MiB x3", flush=True)
+        return
+
+    if args.matvec_only:
+        name, cnt = args.matvec_only.split(":")
+        sec = hub.Sector(W.config(name))
         for dt in (F32, F64):
             x = sec.start_vector(seed=1, dtype=dt)
             y = sec.empty(dt)
-            for _ in range(args.matvec_only):
+            for _ in range(int(cnt)):
                 sec.matvec(x, y)
             torch.cuda.synchronize()
-            print(f"matvec dtype={'f32' if dt == F32 else 'f64'} launches={args.matvec_only}", flush=True)
+            print(f"{name} matvec dtype={'f32' if dt == F32 else 'f64'} launches={cnt}", flush=True)
         sec.close()
         return
 
+    Us = (2, 4, 8)
+    models = {U: W.config(f"ring14_u{U}") for U in Us}
+
     def one_step():
         rec = {}
-        t0 = time.perf_counter()
-        sec = hub.Sector(model)
-        torch.cuda.synchronize()
-        rec["setup_s"] = time.perf_counter() - t0
-        g_ref = sec.ground_state(dtype=F64, want_vector=False, tol=1e-12, time_kernels=True)
-        g64 = sec.ground_state(dtype=F64, want_vector=False, tol=1e-7, time_kernels=True)
-        gmx = sec.ground_state(dtype=F32, reorth=False, refine=True, tol=1e-7, time_kernels=True)
-        runs = {"fp64_ref": g_ref, "fp64_tol1e-7": g64, "mixed_plain": gmx}
-        if not args.skip_reorth:
-            gro = sec.ground_state(dtype=F32, reorth=True, refine=True, tol=1e-7, time_kernels=True)
-            runs["mixed_reorth"] = gro
-        torch.cuda.synchronize()
-        rec["step_s"] = time.perf_counter() - t0
-        rec["runs"] = {k: {"e0": v.e0, **v.info} for k, v in runs.items()}
-        rec["dim"] = sec.dim
-        rec["bytes"] = {"f64": sec.matvec_bytes(F64), "f32": sec.matvec_bytes(F32)}
-        sec.close()
+        for U, model in models.items():
+            r = {}
+            t0 = time.perf_counter()
+            sec = hub.Sector(model)
+            torch.cuda.synchronize()
+            r["setup_s"] = time.perf_counter() - t0
+            runs = {
+                "fp64_plain": sec.ground_state(dtype=F64, want_vector=False, tol=1e-12, time_kernels=True),
+                "mixed_reorth": sec.ground_state(dtype=F32, reorth=True, refine=True, tol=1e-7,
+                                                 time_kernels=True),
+                "mixed_plain": sec.ground_state(dtype=F32, reorth=False, refine=True, tol=1e-7,
+                                                time_kernels=True),
+            }
+            torch.cuda.synchronize()
+            r["runs"] = {k: {"e0": v.e0, **v.info} for k, v in runs.items()}
+            r["bytes"] = {"f64": sec.matvec_bytes(F64), "f32": sec.matvec_bytes(F32)}
+            r["dim"] = sec.dim
+            sec.close()
+            rec[U] = r
         return rec
 
     for _ in range(args.warmup):
@@ -100,28 +141,49 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
 
-    # product statistics over the timed steps
     agg = {"f64": [0.0, 0], "f32": [0.0, 0]}
     total_bytes = 0
-    for r in recs:
-        for k, v in r["runs"].items():
-            key = "f64" if k.startswith("fp64") else "f32"
-            agg[key][0] += v["matvec_ms"]
-            agg[key][1] += v["matvec_count"]
-            total_bytes += v["matvec_count"] * r["bytes"][key]
+    for rec in recs:
+        for U, r in rec.items():
+            for k, v in r["runs"].items():
+                key = "f64" if k.startswith("fp64") else "f32"
+                agg[key][0] += v["matvec_ms"]
+                agg[key][1] += v["matvec_count"]
+                total_bytes += v["matvec_count"] * r["bytes"][key]
     last = recs[-1]
+    b0 = last[Us[0]]["bytes"]
     kern = {}
     for key in ("f64", "f32"):
         ms, cnt = agg[key]
         if cnt:
-            avg_ms = ms / cnt
-            gbps = last["bytes"][key] / (avg_ms * 1e-3) / 1e9
-            kern[key] = {"avg_ms": avg_ms, "launches": cnt, "GBps": gbps, "total_ms": ms}
+            avg = ms / cnt
+            kern[key] = {"avg_ms": avg, "launches": cnt, "total_ms": ms, "bytes_per_launch": b0[key],
+                         "GBps": b0[key] / (avg * 1e-3) / 1e9}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
-    e_ref = last["runs"]["fp64_ref"]["e0"]
 
-    def rel(e):
-        return abs(e - e_ref) / abs(e_ref)
+    oracle_e0 = {}
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "oracle_values.json")) as f:
+            ov = json.load(f)["entries"]
+        oracle_e0 = {U: ov[f"ring14_u{U}"]["e0"] for U in Us}
+    except (OSError, KeyError, ValueError):
+        pass
+
+    per_U = {}
+    for U in Us:
+        r = last[U]
+        e_ref = r["runs"]["fp64_plain"]["e0"]
+        per_U[f"U={U}"] = {
+            "e0_fp64": e_ref,
+            "e0_oracle": oracle_e0.get(U),
+            "rel_err_fp64_vs_oracle": (abs(e_ref - oracle_e0[U]) / abs(oracle_e0[U])) if U in oracle_e0 else None,
+            "time_to_e0_s": {k: v["seconds_to_e0"] for k, v in r["runs"].items()},
+            "solve_s": {k: v["seconds"] for k, v in r["runs"].items()},
+            "iters": {k: v["iters"] for k, v in r["runs"].items()},
+            "rel_err_vs_fp64": {k: abs(v["e0"] - e_ref) / abs(e_ref) for k, v in r["runs"].items()},
+            "rel_err_ritz_vs_fp64": {k: abs(v["e0_ritz"] - e_ref) / abs(e_ref) for k, v in r["runs"].items()},
+            "setup_s": r["setup_s"],
+        }
 
     out = {
         "metric": "H·v GB/s & %HBM peak; Lanczos time-to-E0 mixed vs FP64 at |ΔE0|≤1e-6",
@@ -136,30 +198,44 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32",
         "data": "synthetic",
-        "config": {"workload": model.name, "sites": model.n_sites, "bonds": model.n_bonds,
-                   "n_up": model.n_up, "n_dn": model.n_dn, "dim": last["dim"],
-                   "t": "uniform(0.9,1.1) seed 1307" if args.workload == "square4x4" else "see workloads",
-                   "U": model.U[0], "start_seed": 7542},
+        "config": {"workload": "ring14 (periodic chain M=14, t=1, U in {2,4,8}, N_up=N_dn=7)",
+                   "dim": last[Us[0]]["dim"], "start_seed": 7542, "vector_bytes_f32": last[Us[0]]["dim"] * 4,
+                   "note": "vectors (47 MB FP32 / 94 MB FP64) fit in the 256 MB MALL"},
         "roofline": {"bound": "hbm", "achieved": kern[dom]["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": kern[dom]["GBps"] / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": f"k_kron<{'double' if dom == 'f64' else 'float'}>",
-                     "bytes_per_launch": last["bytes"][dom], "avg_launch_ms": kern[dom]["avg_ms"]},
+                     "kernel": f"k_kron_fused<{'double' if dom == 'f64' else 'float'}>",
+                     "bytes_per_launch": kern[dom]["bytes_per_launch"], "avg_launch_ms": kern[dom]["avg_ms"]},
         "products": kern,
-        "time_to_e0_s": {k: v["seconds_to_e0"] for k, v in last["runs"].items()},
-        "solve_s": {k: v["seconds"] for k, v in last["runs"].items()},
-        "iters": {k: v["iters"] for k, v in last["runs"].items()},
-        "e0": {k: v["e0"] for k, v in last["runs"].items()},
-        "rel_err_vs_fp64": {k: rel(v["e0"]) for k, v in last["runs"].items()},
-        "rel_err_ritz_vs_fp64": {k: rel(v["e0_ritz"]) for k, v in last["runs"].items()},
-        "setup_s": last["setup_s"],
+        "per_U": per_U,
+        "table4_check": {"U": 4, "printed_E_min": TABLE4_M14_U4,
+                         "e0_fp64": last[4]["runs"]["fp64_plain"]["e0"]},
         "paper_context": {"note": "one intel i7 (model, cores, precision unstated); not like-for-like",
-                          "table3_4x4_n7_offdiag_generation_s": {"two_spin": 146.02, "one_spin": 14.24},
-                          "table4_ring14_lanczos_s_one_spin": 702.15,
+                          "table4_ring14_lanczos_s": {"two_spin_binary_search": 3459.85,
+                                                      "one_spin_binary_search": 702.15,
+                                                      "one_spin_stored_index": 701.42},
+                          "table2_ring14_offdiag_generation_s": {"two_spin": 5.02, "one_spin": 0.55},
                           "generation_speedup_claim": "1/9 to 1/11"},
     }
-
+    # HBM traffic of the dominant product from the committed counter run, only
+    # while the product source is unchanged since the counters were taken
+    try:
+        import hashlib
+        with open(os.path.join(ROOT, "profiles", "k_kron_fused_counters.json")) as f:
+            cj = json.load(f)
+        with open(os.path.join(ROOT, "paper_1307_7542_amd", "csrc", "matvec.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        ent = cj["kernels"].get(f"ring14_u4:{dom}")
+        if ent and cj.get("matvec_source_sha256") == sha:
+            out["roofline"]["traffic"] = ent["traffic_bytes"]
+            out["roofline"]["traffic_note"] = ("FETCH_SIZE x %.3f + WRITE_SIZE x %.3f per launch (copy-kernel "
+                                               "calibration), U=4" % (cj["calibration"]["fetch_scale"],
+                                                                      cj["calibration"]["write_scale"]))
+    except (OSError, KeyError, ValueError):
+        pass
+    if not args.no_extra:
+        out["products_square4x4"] = product_timing(hub, torch, W.config("square4x4"))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(model, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(models[4], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
@@ -175,8 +251,9 @@ def cpu_baseline(model, target_s):
     rows = np.sort(rng.integers(0, osec.dim, size=n))
     t = time.perf_counter()
     osec.apply_rows(rows, None, seed=7542)
-    dt = time.perf_counter() - t
-    rate = n / dt
+    rate = n / (time.perf_counter() - t)
+    dt = 0.0
+    n2 = n
     for _ in range(3):
         n2 = int(min(osec.dim, max(n, rate * target_s)))
         rows = np.sort(rng.integers(0, osec.dim, size=n2))
@@ -187,8 +264,9 @@ def cpu_baseline(model, target_s):
         if dt >= 0.6 * target_s or n2 == osec.dim:
             break
     return {"value": rate * 16 / 1e9, "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n2} random rows of one FP64 product (two-spin matrix-free rows, binary-search "
-                      f"indexing), {dt:.1f} s; GB/s = rows/s x 16 B (8 B read + 8 B written per element)",
+            "sample": f"{n2} random rows of one FP64 product, ring14 U=4 (two-spin matrix-free rows with "
+                      f"binary-search indexing), {dt:.1f} s; GB/s = rows/s x 16 B (8 B read + 8 B written per "
+                      f"element)",
             "rows_per_s": rate, "full_product_s_extrapolated": osec.dim / rate}
 
 

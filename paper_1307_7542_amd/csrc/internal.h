@@ -31,6 +31,17 @@ struct SpinTables {
     double *e64 = nullptr;       // [count] sum_i eps_i n_i (FP64, ascending i)
     float *e32 = nullptr;        // [count] FP32 copy
     int32_t max_row = 0;         // longest row of H_sigma
+    // Sliced ELL copy of H_sigma for the product: rows in slices of 64 (one
+    // wavefront), each slice padded to its longest row and stored entry-major,
+    // so lane r of a wavefront reads entry k of row 64*s + r at
+    // sl_off[s] + 64*k + r (padding: column = the row itself, value 0).
+    int64_t nslices = 0;
+    int32_t *sl_off = nullptr;   // [nslices + 1] entry offsets (multiples of 64)
+    int32_t *ell_col = nullptr;  // [sl_off[nslices]]
+    float *ell_v32 = nullptr;
+    double *ell_v64 = nullptr;
+    uint2 *ell_pk32 = nullptr;   // packed {column, FP32 value bits}: one 8-byte load per entry
+    uint4 *ell_pk64 = nullptr;   // packed {column, 0, FP64 value low, high}: one 16-byte load
 };
 
 }  // namespace hub
@@ -58,7 +69,6 @@ struct hub_sector {
     size_t lds_max = 65536;           // dynamic LDS a workgroup may request
     int cu_count = 256;
     std::vector<void *> owned;        // every device allocation, freed by destroy
-    int32_t *col_order = nullptr;     // processing order of the columns (down index) in the product
 };
 
 namespace hub {
@@ -94,7 +104,8 @@ hub_status launch_lz_replay(int dtype, void *w, const void *vprev, const double 
 hub_status launch_psi_acc(int dtype, double *psi, const void *v, const double *ycoef, int64_t n, int first,
                           hipStream_t st);
 hub_status launch_gram(int dtype, const void *const *dQ, int k, void *w, int64_t n, double *partial,
-                       double *coef, hipStream_t st);
+                       double *coef, hipStream_t st, const int *skip);
+hub_status launch_dgks_flag(const double *before, const double *after, int *flag, hipStream_t st);
 hub_status launch_psi_from_basis(int dtype, const void *const *dQ, int k, const double *ycoef, double *psi,
                                  int64_t n, hipStream_t st);
 hub_status launch_normalize_sign(double *psi, int64_t n, double *partial, double *scal, hipStream_t st);

@@ -203,6 +203,8 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     HUB_TRY(mem.alloc((void **)&dQ, sizeof(void *) * (size_t)kmax));
     double *d_coef = nullptr;  // Gram coefficients against the stored vectors
     HUB_TRY(mem.alloc((void **)&d_coef, sizeof(double) * (size_t)kmax));
+    int *d_flag = nullptr;  // skip flag of the second Gram-Schmidt pass
+    HUB_TRY(mem.alloc((void **)&d_flag, sizeof(int) * 4));
 
     void *W = nullptr, *Va = nullptr, *Vb = nullptr;
     HUB_TRY(mem.alloc(&W, es * (size_t)n));
@@ -254,10 +256,14 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         HUB_TRY(product(v, W));
         HUB_TRY(launch_lz_a(dt, W, v_prev, d_beta + k, v, n, partial, d_alpha + k, st));
         if (reorth) {
-            HUB_TRY(launch_lz_b(dt, W, v, d_alpha + k, n, partial, nullptr, st));
+            // classical Gram-Schmidt against every stored vector; the second pass
+            // runs only when the first removed more than 1 - 1/sqrt(2) of the norm
+            HUB_TRY(launch_lz_b(dt, W, v, d_alpha + k, n, partial, d_misc + 8, st));
             HUB_HIP(hipMemcpyAsync(dQ, Q.data(), sizeof(void *) * Q.size(), hipMemcpyHostToDevice, st));
-            for (int pass = 0; pass < 2; ++pass)
-                HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st));
+            HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, nullptr));
+            HUB_TRY(launch_dot(dt, W, W, n, partial, d_misc + 9, 1, st));
+            HUB_TRY(launch_dgks_flag(d_misc + 8, d_misc + 9, d_flag, st));
+            HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, d_flag));
             HUB_TRY(launch_dot(dt, W, W, n, partial, d_beta + k + 1, 1, st));
         } else {
             HUB_TRY(launch_lz_b(dt, W, v, d_alpha + k, n, partial, d_beta + k + 1, st));

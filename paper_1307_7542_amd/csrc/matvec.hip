@@ -7,15 +7,28 @@
 // from the bit patterns (the doubly occupied sites of Sec. III B) and never
 // stored.
 //
-// Work decomposition: one workgroup per output column b.  The column V[:, b]
-// is staged in LDS once; each lane then owns rows a and forms
-//   - the diagonal term from the two occupation integers,
-//   - the H_up term by gathering inside the LDS column along row a of H_up,
-//   - the H_dn term by reading whole neighbouring columns V[:, l] (coalesced
-//     along a; the row of H_dn is the same for the whole workgroup, so its
-//     indices and values are scalar loads).
-// Columns whose LDS footprint exceeds the per-workgroup limit gather the H_up
-// term from global memory (L2) instead.
+// The two terms want orthogonal access patterns.  In column-major storage the
+// H_dn term combines whole neighbouring columns (coalesced, with a row of H_dn
+// that is uniform over a workgroup), while the H_up term gathers inside one
+// column along a different row of H_up for every lane.  Three schedules:
+//
+//   fused   : one workgroup per TB output columns; the TB input columns are
+//             staged in LDS for the H_up gathers, the H_dn neighbour columns
+//             are read through L2 / MALL.  One HBM pass when the neighbour
+//             columns hit in cache.
+//   two-pass: (1) Z = V H_dn^T on row tiles that every workgroup of one XCD
+//             sweeps together, so the tile stays in that XCD's L2 while its
+//             ~deg_dn re-reads happen; (2) Y = Z + H_up V + D o V on LDS column
+//             panels.  Two HBM passes over V, bounded cache footprint.
+//   csr     : plain per-column kernel over CSR rows (fallback when a column
+//             does not fit in LDS).
+//
+// H_up is read from its sliced-ELL copy: lane r of a wavefront owns row
+// 64*s + r of slice s and loads entry k, packed {column, value}, from a
+// coalesced address.
+#include <cstdlib>
+#include <type_traits>
+
 #include "internal.h"
 
 namespace hub {
@@ -24,7 +37,7 @@ namespace {
 template <typename T>
 struct MvArgs {
     const T *__restrict__ x;
-    T *__restrict__ y;
+    T *y;  // may alias the intermediate of the two-pass product
     int32_t cu, cd;
     const int32_t *__restrict__ up_rp;
     const int32_t *__restrict__ up_col;
@@ -36,12 +49,26 @@ struct MvArgs {
     const uint32_t *__restrict__ dn_basis;
     const T *__restrict__ e_up;
     const T *__restrict__ e_dn;
-    const T *__restrict__ Us;   // per-site U (non-uniform case)
-    const int32_t *__restrict__ order;  // column processing order or null
+    const T *__restrict__ Us;  // per-site U (non-uniform case)
     T U;
     int32_t uniform;
     uint32_t umask;
 };
+
+template <typename T>
+using Pk = typename std::conditional<sizeof(T) == 8, uint4, uint2>::type;
+
+__device__ __forceinline__ void unpack(uint2 e, int &c, float &v)
+{
+    c = (int)e.x;
+    v = __uint_as_float(e.y);
+}
+
+__device__ __forceinline__ void unpack(uint4 e, int &c, double &v)
+{
+    c = (int)e.x;
+    v = __hiloint2double((int)e.w, (int)e.z);
+}
 
 template <typename T>
 __device__ __forceinline__ T diag_u(const MvArgs<T> &A, uint32_t both)
@@ -57,33 +84,244 @@ __device__ __forceinline__ T diag_u(const MvArgs<T> &A, uint32_t both)
     return d;
 }
 
-template <typename T, bool USE_LDS, int BS>
-__global__ __launch_bounds__(BS) void k_kron(MvArgs<T> A)
+template <typename T, int TB>
+struct Vec {
+    T v[TB];
+};
+
+// acc[t] += sum_k val_k * xs[col_k * TB + t] over the sliced-ELL row, 4 entries in flight.
+template <typename T, int TB>
+__device__ __forceinline__ void up_term(T (&acc)[TB], const T *xs, const Pk<T> *__restrict__ ell, int o0, int len)
+{
+    int k = 0;
+    for (; k + 4 <= len; k += 4) {
+        int c0, c1, c2, c3;
+        T v0, v1, v2, v3;
+        unpack(ell[o0 + 64 * k], c0, v0);
+        unpack(ell[o0 + 64 * (k + 1)], c1, v1);
+        unpack(ell[o0 + 64 * (k + 2)], c2, v2);
+        unpack(ell[o0 + 64 * (k + 3)], c3, v3);
+        const Vec<T, TB> x0 = *reinterpret_cast<const Vec<T, TB> *>(xs + c0 * TB);
+        const Vec<T, TB> x1 = *reinterpret_cast<const Vec<T, TB> *>(xs + c1 * TB);
+        const Vec<T, TB> x2 = *reinterpret_cast<const Vec<T, TB> *>(xs + c2 * TB);
+        const Vec<T, TB> x3 = *reinterpret_cast<const Vec<T, TB> *>(xs + c3 * TB);
+#pragma unroll
+        for (int t = 0; t < TB; ++t) acc[t] += (v0 * x0.v[t] + v1 * x1.v[t]) + (v2 * x2.v[t] + v3 * x3.v[t]);
+    }
+    for (; k < len; ++k) {
+        int c0;
+        T v0;
+        unpack(ell[o0 + 64 * k], c0, v0);
+        const Vec<T, TB> x0 = *reinterpret_cast<const Vec<T, TB> *>(xs + c0 * TB);
+#pragma unroll
+        for (int t = 0; t < TB; ++t) acc[t] += v0 * x0.v[t];
+    }
+}
+
+// sum_k H_dn[b, k] x[a + col_k * cu] over row b of H_dn (uniform over the wavefront).
+template <typename T>
+__device__ __forceinline__ T dn_term(const MvArgs<T> &A, int ks, int ke, const T *__restrict__ xa)
+{
+    const int64_t cu = A.cu;
+    T s = (T)0;
+    int k = ks;
+    for (; k + 4 <= ke; k += 4) {
+        const int64_t l0 = A.dn_col[k], l1 = A.dn_col[k + 1], l2 = A.dn_col[k + 2], l3 = A.dn_col[k + 3];
+        const T y0 = xa[l0 * cu], y1 = xa[l1 * cu], y2 = xa[l2 * cu], y3 = xa[l3 * cu];
+        s += (A.dn_val[k] * y0 + A.dn_val[k + 1] * y1) + (A.dn_val[k + 2] * y2 + A.dn_val[k + 3] * y3);
+    }
+    for (; k < ke; ++k) s += A.dn_val[k] * xa[(int64_t)A.dn_col[k] * cu];
+    return s;
+}
+
+// Block -> tile with every XCD (workgroup i runs on XCD i mod 8) owning a
+// contiguous range of tiles; returns -1 for the padding blocks.
+__device__ __forceinline__ int xcd_tile(int ntiles)
+{
+    const int per = (ntiles + 7) >> 3;
+    const int t = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    return t < ntiles ? t : -1;
+}
+
+template <typename T, int TB>
+__device__ __forceinline__ void stage_columns(const MvArgs<T> &A, T *xs, int b0, int bs)
+{
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+        const int b = b0 + t;
+        const T *__restrict__ xb = A.x + (int64_t)min(b, A.cd - 1) * A.cu;
+        for (int a = threadIdx.x; a < A.cu; a += bs) xs[a * TB + t] = (b < A.cd) ? xb[a] : (T)0;
+    }
+}
+
+// ---- fused ------------------------------------------------------------
+// Each lane owns R rows (a, a + BS, ...) at once so the H_dn neighbour reads
+// of all R rows are in flight together.
+template <typename T, int TB, int BS, int R>
+__global__ __launch_bounds__(BS) void k_kron_fused(MvArgs<T> A, const int32_t *__restrict__ sl_off,
+                                                   const Pk<T> *__restrict__ ell, int ntiles)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *xs = reinterpret_cast<T *>(smem_raw);
-    const int b = A.order ? A.order[blockIdx.x] : (int)blockIdx.x;
+    const int tile = xcd_tile(ntiles);
+    if (tile < 0) return;
+    const int cu = A.cu, cd = A.cd;
+    const int b0 = tile * TB;
+    stage_columns<T, TB>(A, xs, b0, BS);
+    __syncthreads();
+    int ds[TB], de[TB];
+    uint32_t dnb[TB];
+    T edn[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+        const int b = min(b0 + t, cd - 1);
+        ds[t] = A.dn_rp[b];
+        de[t] = (b0 + t < cd) ? A.dn_rp[b + 1] : ds[t];
+        dnb[t] = A.dn_basis[b];
+        edn[t] = A.e_dn[b];
+    }
+    const int lane = threadIdx.x & 63;
+    const int64_t cu64 = cu;
+    for (int a0 = threadIdx.x; a0 < cu; a0 += BS * R) {
+        T acc[R][TB];
+        int as[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int a = min(a0 + j * BS, cu - 1);
+            as[j] = a;
+            const uint32_t ua = A.up_basis[a];
+            const T eua = A.e_up[a];
+            const Vec<T, TB> xa = *reinterpret_cast<const Vec<T, TB> *>(xs + a * TB);
+#pragma unroll
+            for (int t = 0; t < TB; ++t) acc[j][t] = (diag_u(A, ua & dnb[t]) + eua + edn[t]) * xa.v[t];
+            const int s = a >> 6;
+            up_term<T, TB>(acc[j], xs, ell, sl_off[s] * 64 + lane, sl_off[s + 1] - sl_off[s]);
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            int k = ds[t];
+            for (; k + 4 <= de[t]; k += 4) {
+                T y[4][R];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int j = 0; j < R; ++j) y[u][j] = A.x[(int64_t)A.dn_col[k + u] * cu64 + as[j]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int j = 0; j < R; ++j) acc[j][t] += A.dn_val[k + u] * y[u][j];
+            }
+            for (; k < de[t]; ++k)
+#pragma unroll
+                for (int j = 0; j < R; ++j) acc[j][t] += A.dn_val[k] * A.x[(int64_t)A.dn_col[k] * cu64 + as[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (a0 + j * BS < cu)
+#pragma unroll
+                for (int t = 0; t < TB; ++t)
+                    if (b0 + t < cd) A.y[(int64_t)(b0 + t) * cu64 + a0 + j * BS] = acc[j][t];
+    }
+}
+
+// ---- two-pass, pass 1: Z = V H_dn^T on XCD-cooperative row tiles --------
+// A tile is TA = 128 B / sizeof(T) rows (one cache line per column), so two
+// tiles in flight stay well inside one XCD's 4 MB L2 for count_dn ~ 10^4.  A
+// wavefront covers 64 / TA output columns of the tile; each group of TA lanes
+// walks its own row of H_dn with 8 neighbour reads in flight.
+template <typename T, int BS, bool NT>
+__global__ __launch_bounds__(BS) void k_kron_dn_tiles(MvArgs<T> A, T *z, int ntiles, int per_xcd)
+{
+    constexpr int TA = 128 / (int)sizeof(T);
+    constexpr int CPW = 64 / TA;                // output columns per wavefront
+    constexpr int CPB = (BS / 64) * CPW;        // output columns per workgroup step
+    const int64_t cu = A.cu;
+    const int cd = A.cd;
+    const int xcd = blockIdx.x & 7;
+    const int r = blockIdx.x >> 3;  // rank of this workgroup within its XCD
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sub = lane / TA, row = lane % TA;
+    const int cols_per = (cd + per_xcd - 1) / per_xcd;
+    const int c0 = r * cols_per, c1 = min(cd, c0 + cols_per);
+    for (int tile = xcd; tile < ntiles; tile += 8) {
+        const int a = tile * TA + row;
+        const bool live = a < cu;
+        const T *__restrict__ xa = A.x + (live ? a : 0);
+        for (int b = c0 + wave * CPW + sub; b < c1; b += CPB) {
+            const int ks = A.dn_rp[b], ke = A.dn_rp[b + 1];
+            T acc = (T)0;
+            int k = ks;
+            for (; k + 8 <= ke; k += 8) {
+                T y[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) y[u] = xa[(int64_t)A.dn_col[k + u] * cu];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += A.dn_val[k + u] * y[u];
+            }
+            for (; k < ke; ++k) acc += A.dn_val[k] * xa[(int64_t)A.dn_col[k] * cu];
+            if (live) {
+                if (NT) __builtin_nontemporal_store(acc, z + (int64_t)b * cu + a);
+                else z[(int64_t)b * cu + a] = acc;
+            }
+        }
+    }
+}
+
+// ---- two-pass, pass 2: Y = Z + H_up V + D o V on LDS column panels --------
+template <typename T, int TB, int BS>
+__global__ __launch_bounds__(BS) void k_kron_up_panels(MvArgs<T> A, const T *z, const int32_t *__restrict__ sl_off,
+                                                       const Pk<T> *__restrict__ ell, int ntiles)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *xs = reinterpret_cast<T *>(smem_raw);
+    const int tile = xcd_tile(ntiles);
+    if (tile < 0) return;
+    const int cu = A.cu, cd = A.cd;
+    const int b0 = tile * TB;
+    stage_columns<T, TB>(A, xs, b0, BS);
+    __syncthreads();
+    uint32_t dnb[TB];
+    T edn[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+        const int b = min(b0 + t, cd - 1);
+        dnb[t] = A.dn_basis[b];
+        edn[t] = A.e_dn[b];
+    }
+    const int lane = threadIdx.x & 63;
+    for (int a = threadIdx.x; a < cu; a += BS) {
+        const uint32_t ua = A.up_basis[a];
+        const T eua = A.e_up[a];
+        const Vec<T, TB> xa = *reinterpret_cast<const Vec<T, TB> *>(xs + a * TB);
+        T acc[TB];
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            const int b = min(b0 + t, cd - 1);
+            acc[t] = z[(int64_t)b * cu + a] + (diag_u(A, ua & dnb[t]) + eua + edn[t]) * xa.v[t];
+        }
+        const int s = a >> 6;
+        up_term<T, TB>(acc, xs, ell, sl_off[s] * 64 + lane, sl_off[s + 1] - sl_off[s]);
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+            if (b0 + t < cd) A.y[(int64_t)(b0 + t) * cu + a] = acc[t];
+    }
+}
+
+// ---- fallback: CSR rows, H_up gathered from global memory ----------------
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_kron_csr(MvArgs<T> A)
+{
+    const int b = (int)blockIdx.x;
     const int cu = A.cu;
     const T *__restrict__ xb = A.x + (int64_t)b * cu;
-    T *__restrict__ yb = A.y + (int64_t)b * cu;
-    if (USE_LDS) {
-        for (int i = threadIdx.x; i < cu; i += BS) xs[i] = xb[i];
-        __syncthreads();
-    }
     const int ds = A.dn_rp[b], de = A.dn_rp[b + 1];
     const uint32_t dnb = A.dn_basis[b];
     const T edn = A.e_dn[b];
     for (int a = threadIdx.x; a < cu; a += BS) {
-        const T xa = USE_LDS ? xs[a] : xb[a];
-        const T d = diag_u(A, A.up_basis[a] & dnb) + A.e_up[a] + edn;
-        T acc = d * xa;
-        const int us = A.up_rp[a], ue = A.up_rp[a + 1];
-        for (int k = us; k < ue; ++k) {
-            const int l = A.up_col[k];
-            acc += A.up_val[k] * (USE_LDS ? xs[l] : xb[l]);
-        }
-        for (int k = ds; k < de; ++k) acc += A.dn_val[k] * A.x[(int64_t)A.dn_col[k] * cu + a];
-        yb[a] = acc;
+        T acc = (diag_u(A, A.up_basis[a] & dnb) + A.e_up[a] + edn) * xb[a];
+        for (int k = A.up_rp[a]; k < A.up_rp[a + 1]; ++k) acc += A.up_val[k] * xb[A.up_col[k]];
+        acc += dn_term(A, ds, de, A.x + a);
+        A.y[(int64_t)b * cu + a] = acc;
     }
 }
 
@@ -113,7 +351,6 @@ MvArgs<T> make_args(const hub_sector *s, const void *x, void *y)
     A.dn_col = D.col;
     A.up_basis = U.basis;
     A.dn_basis = D.basis;
-    A.order = s->col_order;
     A.uniform = s->uniformU;
     A.umask = s->umask;
     if constexpr (sizeof(T) == 8) {
@@ -134,22 +371,100 @@ MvArgs<T> make_args(const hub_sector *s, const void *x, void *y)
 }
 
 template <typename T>
+const Pk<T> *ell_of(const SpinTables &U)
+{
+    if constexpr (sizeof(T) == 8) return (const Pk<T> *)U.ell_pk64;
+    else return (const Pk<T> *)U.ell_pk32;
+}
+
+template <typename K>
+hub_status allow_lds(K kernel, size_t bytes)
+{
+    HUB_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return HUB_OK;
+}
+
+template <typename T, int TB, int BS, int R = 4>
+hub_status launch_fused(const hub_sector *s, const MvArgs<T> &A, hipStream_t st)
+{
+    const SpinTables &U = s->spin[0];
+    const size_t lds = (size_t)A.cu * TB * sizeof(T);
+    static bool attr = false;
+    if (!attr) {
+        HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R>, s->lds_max));
+        attr = true;
+    }
+    const int ntiles = (A.cd + TB - 1) / TB;
+    const unsigned grid = 8u * (unsigned)((ntiles + 7) / 8);
+    hipLaunchKernelGGL((k_kron_fused<T, TB, BS, R>), dim3(grid), dim3(BS), lds, st, A, U.sl_off, ell_of<T>(U),
+                       ntiles);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+template <typename T, int TB, int BS>
+hub_status launch_two_pass(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int occ, int nt)
+{
+    constexpr int BSD = 256;
+    const SpinTables &U = s->spin[0];
+    const int ntiles_d = (A.cu + (128 / (int)sizeof(T)) - 1) / (128 / (int)sizeof(T));
+    const int per_xcd = (s->cu_count / 8) * occ;
+    if (nt)
+        hipLaunchKernelGGL((k_kron_dn_tiles<T, BSD, true>), dim3(8 * per_xcd), dim3(BSD), 0, st, A, A.y, ntiles_d,
+                           per_xcd);
+    else
+        hipLaunchKernelGGL((k_kron_dn_tiles<T, BSD, false>), dim3(8 * per_xcd), dim3(BSD), 0, st, A, A.y, ntiles_d,
+                           per_xcd);
+    const size_t lds = (size_t)A.cu * TB * sizeof(T);
+    static bool attr = false;
+    if (!attr) {
+        HUB_TRY(allow_lds(k_kron_up_panels<T, TB, BS>, s->lds_max));
+        attr = true;
+    }
+    const int ntiles = (A.cd + TB - 1) / TB;
+    const unsigned grid = 8u * (unsigned)((ntiles + 7) / 8);
+    hipLaunchKernelGGL((k_kron_up_panels<T, TB, BS>), dim3(grid), dim3(BS), lds, st, A, (const T *)A.y, U.sl_off,
+                       ell_of<T>(U), ntiles);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+int env_int(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    return v ? atoi(v) : dflt;
+}
+
+// Schedule selection: environment overrides (HUB_MATVEC_IMPL 1 csr, 2 fused,
+// 3 two-pass; HUB_MATVEC_TB; HUB_MATVEC_BS 512/1024; HUB_DN_OCC; HUB_DN_NT),
+// otherwise the fused schedule with one column per workgroup.
+template <typename T>
 hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
 {
-    constexpr int BS = 512;
     MvArgs<T> A = make_args<T>(s, x, y);
-    const size_t lds = (size_t)A.cu * sizeof(T);
-    if (lds <= s->lds_max) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            HUB_HIP(hipFuncSetAttribute((const void *)k_kron<T, true, BS>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)s->lds_max));
-            attr_set = true;
-        }
-        hipLaunchKernelGGL((k_kron<T, true, BS>), dim3((unsigned)A.cd), dim3(BS), lds, st, A);
-    } else {
-        hipLaunchKernelGGL((k_kron<T, false, BS>), dim3((unsigned)A.cd), dim3(BS), 0, st, A);
+    const size_t col_bytes = (size_t)A.cu * sizeof(T);
+    static const int impl = env_int("HUB_MATVEC_IMPL", 2);
+    static const int tb = env_int("HUB_MATVEC_TB", 1);
+    static const int bs = env_int("HUB_MATVEC_BS", 0);
+    static const int occ = env_int("HUB_DN_OCC", 4);
+    static const int nt = env_int("HUB_DN_NT", 1);
+    const bool fits = col_bytes <= s->lds_max;
+    const bool fits2 = 2 * col_bytes <= s->lds_max;
+    // one workgroup per CU when the panel takes more than half the LDS: use 16 waves
+    const bool big = (bs == 1024) || (bs == 0 && 2 * col_bytes * (tb >= 2 && fits2 ? 2 : 1) > s->lds_max);
+    if (impl == 3 && fits) {
+        if (tb >= 2 && fits2)
+            return big ? launch_two_pass<T, 2, 1024>(s, A, st, occ, nt) : launch_two_pass<T, 2, 512>(s, A, st, occ, nt);
+        return big ? launch_two_pass<T, 1, 1024>(s, A, st, occ, nt) : launch_two_pass<T, 1, 512>(s, A, st, occ, nt);
     }
+    static const int rows = env_int("HUB_FUSED_R", 4);
+    if (impl == 2 && fits) {
+        if (tb >= 2 && fits2) return big ? launch_fused<T, 2, 1024, 2>(s, A, st) : launch_fused<T, 2, 512, 2>(s, A, st);
+        if (rows >= 4) return big ? launch_fused<T, 1, 1024, 4>(s, A, st) : launch_fused<T, 1, 512, 4>(s, A, st);
+        if (rows >= 2) return big ? launch_fused<T, 1, 1024, 2>(s, A, st) : launch_fused<T, 1, 512, 2>(s, A, st);
+        return big ? launch_fused<T, 1, 1024, 1>(s, A, st) : launch_fused<T, 1, 512, 1>(s, A, st);
+    }
+    hipLaunchKernelGGL((k_kron_csr<T, 512>), dim3((unsigned)A.cd), dim3(512), 0, st, A);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }

@@ -199,6 +199,48 @@ __global__ void k_max_row(const int32_t *__restrict__ rp, int64_t count, int32_t
     if (threadIdx.x == 0) *out = s[0];
 }
 
+__global__ void k_slice_len(const int32_t *__restrict__ rp, int64_t count, int64_t nslices, int32_t *__restrict__ len)
+{
+    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= nslices) return;
+    int m = 0;
+    const int64_t r1 = min(count, (sl + 1) * 64);
+    for (int64_t r = sl * 64; r < r1; ++r) m = max(m, rp[r + 1] - rp[r]);
+    len[sl] = m;
+}
+
+__global__ void k_sell_fill(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                            const double *__restrict__ val, int64_t count, const int32_t *__restrict__ sp,
+                            int32_t *__restrict__ ecol, float *__restrict__ e32, double *__restrict__ e64,
+                            uint2 *__restrict__ pk32, uint4 *__restrict__ pk64)
+{
+    // one lane per (padded) row of a slice
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sl = r / 64, lane = r % 64;
+    const int64_t base = 64 * (int64_t)sp[sl];
+    const int len = sp[sl + 1] - sp[sl];
+    const int rl = (r < count) ? rp[r + 1] - rp[r] : 0;
+    const int r0 = (r < count) ? rp[r] : 0;
+    for (int k = 0; k < len; ++k) {
+        const int64_t o = base + 64 * (int64_t)k + lane;
+        int32_t c;
+        double v;
+        if (k < rl) {
+            c = col[r0 + k];
+            v = val[r0 + k];
+        } else {
+            c = (r < count) ? (int32_t)r : 0;
+            v = 0.0;
+        }
+        ecol[o] = c;
+        e64[o] = v;
+        e32[o] = (float)v;
+        pk32[o] = make_uint2((uint32_t)c, __float_as_uint((float)v));
+        const unsigned long long vb = (unsigned long long)__double_as_longlong(v);
+        pk64[o] = make_uint4((uint32_t)c, 0u, (uint32_t)(vb & 0xFFFFFFFFull), (uint32_t)(vb >> 32));
+    }
+}
+
 template <typename T>
 hub_status dalloc(hub_sector *s, T **p, size_t n)
 {
@@ -271,6 +313,40 @@ hub_status build_spin_tables(hub_sector *s, int spin, int N, hipStream_t st)
     hipLaunchKernelGGL(k_max_row, dim3(1), dim3(256), 0, st, T.rp, count, dmax);
     HUB_HIP(hipGetLastError());
     HUB_HIP(hipMemcpyAsync(&T.max_row, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipStreamSynchronize(st));
+
+    // sliced ELL copy (slices of 64 rows)
+    T.nslices = (count + 63) / 64;
+    const int64_t ns = T.nslices;
+    int32_t *slen = nullptr, *sp = nullptr;
+    int64_t *stmp = nullptr, *ssum = nullptr;
+    const int64_t snblk = (ns + kScanBlock - 1) / kScanBlock;
+    HUB_TRY(dalloc(s, &slen, ns));
+    HUB_TRY(dalloc(s, &sp, ns + 1));
+    HUB_TRY(dalloc(s, &stmp, ns));
+    HUB_TRY(dalloc(s, &ssum, snblk));
+    hipLaunchKernelGGL(k_slice_len, dim3(grid_for(ns, B)), dim3(B), 0, st, T.rp, count, ns, slen);
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)snblk), dim3(kScanBlock), 0, st, slen, ns, stmp, ssum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, ssum, snblk);
+    hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)snblk), dim3(kScanBlock), 0, st, slen, stmp, ssum, ns, sp);
+    HUB_HIP(hipGetLastError());
+    int32_t slots = 0;
+    HUB_HIP(hipMemcpyAsync(&slots, sp + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    if ((int64_t)slots * 64 >= ((int64_t)1 << 31)) {
+        set_error("sliced hopping matrix would exceed 2^31 entries");
+        return HUB_ERR_RANGE;
+    }
+    const int64_t nell = 64 * (int64_t)slots;
+    T.sl_off = sp;  // in units of 64 entries
+    HUB_TRY(dalloc(s, &T.ell_col, nell));
+    HUB_TRY(dalloc(s, &T.ell_v32, nell));
+    HUB_TRY(dalloc(s, &T.ell_v64, nell));
+    HUB_TRY(dalloc(s, &T.ell_pk32, nell));
+    HUB_TRY(dalloc(s, &T.ell_pk64, nell));
+    hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)ns), dim3(64), 0, st, T.rp, T.col, T.val64, count, sp, T.ell_col,
+                       T.ell_v32, T.ell_v64, T.ell_pk32, T.ell_pk64);
+    HUB_HIP(hipGetLastError());
     HUB_HIP(hipStreamSynchronize(st));
     return HUB_OK;
 }

@@ -151,53 +151,89 @@ __global__ void k_psi_acc(double *__restrict__ psi, const T *__restrict__ v, con
         psi[i] = (first ? 0.0 : psi[i]) + c * (double)v[i];
 }
 
-// Gram coefficients c_j = <q_j, w> for the stored vectors, 8 at a time so w is
-// read once per group of 8.  partial layout: [block][j].
+// Gram coefficients c_j = <q_j, w> for the stored vectors, GJ at a time so w
+// is read once per group.  Each wavefront reduces its GJ sums with lane
+// shuffles (fixed butterfly order), then one barrier combines the wavefronts.
+// partial layout: [block][j].  A non-null `skip` pointing at a non-zero flag
+// turns the launch into a no-op (second Gram-Schmidt pass not needed).
 constexpr int GJ = 8;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
 
 template <typename T>
 __global__ __launch_bounds__(RB) void k_gram_dot(const T *const *__restrict__ Q, int k, const T *__restrict__ w,
-                                                 int64_t n, double *__restrict__ partial, int kstride)
+                                                 int64_t n, double *__restrict__ partial, int kstride,
+                                                 const int *__restrict__ skip)
 {
-    __shared__ double s[RB];
+    if (skip && *skip) return;
+    __shared__ double s[RB / 64][GJ];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int j0 = 0; j0 < k; j0 += GJ) {
         double acc[GJ];
 #pragma unroll
         for (int u = 0; u < GJ; ++u) acc[u] = 0.0;
         const int jn = min(GJ, k - j0);
+        const T *q[GJ];
+#pragma unroll
+        for (int u = 0; u < GJ; ++u) q[u] = Q[j0 + (u < jn ? u : 0)];
         for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
             const double wi = (double)w[i];
 #pragma unroll
             for (int u = 0; u < GJ; ++u)
-                if (u < jn) acc[u] += (double)Q[j0 + u][i] * wi;
+                if (u < jn) acc[u] += (double)q[u][i] * wi;
         }
-        for (int u = 0; u < jn; ++u) {
-            const double r = block_sum(acc[u], s);
-            if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * kstride + j0 + u] = r;
+#pragma unroll
+        for (int u = 0; u < GJ; ++u) {
+            const double r = wave_sum(acc[u]);
+            if (lane == 0) s[wave][u] = r;
         }
+        __syncthreads();
+        if (threadIdx.x < (unsigned)jn) {
+            double r = 0.0;
+#pragma unroll
+            for (int v = 0; v < RB / 64; ++v) r += s[v][threadIdx.x];
+            partial[(int64_t)blockIdx.x * kstride + j0 + threadIdx.x] = r;
+        }
+        __syncthreads();
     }
 }
 
-__global__ void k_gram_final(const double *__restrict__ partial, int np, int k, int kstride,
-                             double *__restrict__ coef)
+// One block per coefficient: fixed-order tree over the block partials.
+__global__ __launch_bounds__(RB) void k_gram_final(const double *__restrict__ partial, int np, int k, int kstride,
+                                                   double *__restrict__ coef, const int *__restrict__ skip)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= k) return;
+    if (skip && *skip) return;
+    __shared__ double s[RB];
+    const int j = blockIdx.x;
     double acc = 0.0;
-    for (int b = 0; b < np; ++b) acc += partial[(int64_t)b * kstride + j];
-    coef[j] = acc;
+    for (int b = threadIdx.x; b < np; b += RB) acc += partial[(int64_t)b * kstride + j];
+    const double r = block_sum(acc, s);
+    if (threadIdx.x == 0) coef[j] = r;
 }
 
 // w <- w - sum_j c_j q_j, evaluated in FP64 per element.
 template <typename T>
 __global__ void k_gram_update(const T *const *__restrict__ Q, int k, const double *__restrict__ coef,
-                              T *__restrict__ w, int64_t n)
+                              T *__restrict__ w, int64_t n, const int *__restrict__ skip)
 {
+    if (skip && *skip) return;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double acc = 0.0;
         for (int j = 0; j < k; ++j) acc += coef[j] * (double)Q[j][i];
         w[i] = (T)((double)w[i] - acc);
     }
+}
+
+// flag = 1 when the first pass kept more than 1/sqrt(2) of the norm (a second
+// classical Gram-Schmidt pass would not change w to working precision).
+__global__ void k_dgks_flag(const double *__restrict__ before, const double *__restrict__ after, int *__restrict__ flag)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *flag = (*after > 0.70710678118654752 * *before) ? 1 : 0;
 }
 
 template <typename T>
@@ -408,24 +444,31 @@ hub_status launch_psi_acc(int dtype, double *psi, const void *v, const double *y
 
 // coef must hold k doubles; partial must hold red_grid(n) * kmax doubles with kmax >= k.
 hub_status launch_gram(int dtype, const void *const *dQ, int k, void *w, int64_t n, double *partial, double *coef,
-                       hipStream_t st)
+                       hipStream_t st, const int *skip)
 {
     if (k <= 0) return HUB_OK;
     const int G = red_grid(n);
     if (dtype == HUB_F64) {
         hipLaunchKernelGGL(k_gram_dot<double>, dim3(G), dim3(RB), 0, st, (const double *const *)dQ, k,
-                           (const double *)w, n, partial, k);
+                           (const double *)w, n, partial, k, skip);
     } else {
         hipLaunchKernelGGL(k_gram_dot<float>, dim3(G), dim3(RB), 0, st, (const float *const *)dQ, k,
-                           (const float *)w, n, partial, k);
+                           (const float *)w, n, partial, k, skip);
     }
-    hipLaunchKernelGGL(k_gram_final, dim3((k + 255) / 256), dim3(256), 0, st, partial, G, k, k, coef);
+    hipLaunchKernelGGL(k_gram_final, dim3(k), dim3(RB), 0, st, partial, G, k, k, coef, skip);
     if (dtype == HUB_F64)
         hipLaunchKernelGGL(k_gram_update<double>, dim3(ew_grid(n)), dim3(256), 0, st, (const double *const *)dQ, k,
-                           coef, (double *)w, n);
+                           coef, (double *)w, n, skip);
     else
         hipLaunchKernelGGL(k_gram_update<float>, dim3(ew_grid(n)), dim3(256), 0, st, (const float *const *)dQ, k,
-                           coef, (float *)w, n);
+                           coef, (float *)w, n, skip);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_dgks_flag(const double *before, const double *after, int *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dgks_flag, dim3(1), dim3(64), 0, st, before, after, flag);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
