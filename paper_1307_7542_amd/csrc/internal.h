@@ -42,6 +42,12 @@ struct SpinTables {
     double *ell_v64 = nullptr;
     uint2 *ell_pk32 = nullptr;   // packed {column, FP32 value bits}: one 8-byte load per entry
     uint4 *ell_pk64 = nullptr;   // packed {column, 0, FP64 value low, high}: one 16-byte load
+    // Compact entries {column : 24 bits, code : 8 bits}, value = code_v[code] with
+    // code = 2*bond + (esign < 0) and code 255 = padding (value 0).  Built when
+    // count < 2^24 and the sector has at most 127 bonds.
+    uint32_t *ell_c32 = nullptr;
+    double *code_v64 = nullptr;  // [256]
+    float *code_v32 = nullptr;   // [256]
 };
 
 }  // namespace hub

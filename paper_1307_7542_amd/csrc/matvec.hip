@@ -118,6 +118,33 @@ __device__ __forceinline__ void up_term(T (&acc)[TB], const T *xs, const Pk<T> *
     }
 }
 
+// Same with compact entries {column : 24, code : 8}; the values come from the
+// per-code table `tab` held in LDS (code 255 = padding, value 0).
+template <typename T, int TB>
+__device__ __forceinline__ void up_term_c(T (&acc)[TB], const T *xs, const T *tab,
+                                          const uint32_t *__restrict__ ell, int o0, int len)
+{
+    int k = 0;
+    for (; k + 4 <= len; k += 4) {
+        const uint32_t e0 = ell[o0 + 64 * k], e1 = ell[o0 + 64 * (k + 1)];
+        const uint32_t e2 = ell[o0 + 64 * (k + 2)], e3 = ell[o0 + 64 * (k + 3)];
+        const T v0 = tab[e0 >> 24], v1 = tab[e1 >> 24], v2 = tab[e2 >> 24], v3 = tab[e3 >> 24];
+        const Vec<T, TB> x0 = *reinterpret_cast<const Vec<T, TB> *>(xs + (e0 & 0xFFFFFFu) * TB);
+        const Vec<T, TB> x1 = *reinterpret_cast<const Vec<T, TB> *>(xs + (e1 & 0xFFFFFFu) * TB);
+        const Vec<T, TB> x2 = *reinterpret_cast<const Vec<T, TB> *>(xs + (e2 & 0xFFFFFFu) * TB);
+        const Vec<T, TB> x3 = *reinterpret_cast<const Vec<T, TB> *>(xs + (e3 & 0xFFFFFFu) * TB);
+#pragma unroll
+        for (int t = 0; t < TB; ++t) acc[t] += (v0 * x0.v[t] + v1 * x1.v[t]) + (v2 * x2.v[t] + v3 * x3.v[t]);
+    }
+    for (; k < len; ++k) {
+        const uint32_t e0 = ell[o0 + 64 * k];
+        const T v0 = tab[e0 >> 24];
+        const Vec<T, TB> x0 = *reinterpret_cast<const Vec<T, TB> *>(xs + (e0 & 0xFFFFFFu) * TB);
+#pragma unroll
+        for (int t = 0; t < TB; ++t) acc[t] += v0 * x0.v[t];
+    }
+}
+
 // sum_k H_dn[b, k] x[a + col_k * cu] over row b of H_dn (uniform over the wavefront).
 template <typename T>
 __device__ __forceinline__ T dn_term(const MvArgs<T> &A, int ks, int ke, const T *__restrict__ xa)
@@ -157,16 +184,20 @@ __device__ __forceinline__ void stage_columns(const MvArgs<T> &A, T *xs, int b0,
 // ---- fused ------------------------------------------------------------
 // Each lane owns R rows (a, a + BS, ...) at once so the H_dn neighbour reads
 // of all R rows are in flight together.
-template <typename T, int TB, int BS, int R>
+template <typename T, int TB, int BS, int R, bool CF>
 __global__ __launch_bounds__(BS) void k_kron_fused(MvArgs<T> A, const int32_t *__restrict__ sl_off,
-                                                   const Pk<T> *__restrict__ ell, int ntiles)
+                                                   const Pk<T> *__restrict__ ell, const uint32_t *__restrict__ ellc,
+                                                   const T *__restrict__ code_v, int ntiles)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *xs = reinterpret_cast<T *>(smem_raw);
+    T *tab = reinterpret_cast<T *>(smem_raw);       // 256 code values (compact format)
+    T *xs = tab + (CF ? 256 : 0);
     const int tile = xcd_tile(ntiles);
     if (tile < 0) return;
     const int cu = A.cu, cd = A.cd;
     const int b0 = tile * TB;
+    if (CF)
+        for (int i = threadIdx.x; i < 256; i += BS) tab[i] = code_v[i];
     stage_columns<T, TB>(A, xs, b0, BS);
     __syncthreads();
     int ds[TB], de[TB];
@@ -195,7 +226,8 @@ __global__ __launch_bounds__(BS) void k_kron_fused(MvArgs<T> A, const int32_t *_
 #pragma unroll
             for (int t = 0; t < TB; ++t) acc[j][t] = (diag_u(A, ua & dnb[t]) + eua + edn[t]) * xa.v[t];
             const int s = a >> 6;
-            up_term<T, TB>(acc[j], xs, ell, sl_off[s] * 64 + lane, sl_off[s + 1] - sl_off[s]);
+            if (CF) up_term_c<T, TB>(acc[j], xs, tab, ellc, sl_off[s] * 64 + lane, sl_off[s + 1] - sl_off[s]);
+            else up_term<T, TB>(acc[j], xs, ell, sl_off[s] * 64 + lane, sl_off[s + 1] - sl_off[s]);
         }
 #pragma unroll
         for (int t = 0; t < TB; ++t) {
@@ -385,19 +417,34 @@ hub_status allow_lds(K kernel, size_t bytes)
 }
 
 template <typename T, int TB, int BS, int R = 4>
-hub_status launch_fused(const hub_sector *s, const MvArgs<T> &A, hipStream_t st)
+hub_status launch_fused(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, bool cf)
 {
     const SpinTables &U = s->spin[0];
+    const int ntiles = (A.cd + TB - 1) / TB;
+    const unsigned grid = 8u * (unsigned)((ntiles + 7) / 8);
+    if (cf && U.ell_c32) {
+        const size_t lds = (size_t)(A.cu * TB + 256) * sizeof(T);
+        static bool attr = false;
+        if (!attr) {
+            HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, true>, s->lds_max));
+            attr = true;
+        }
+        const T *cv;
+        if constexpr (sizeof(T) == 8) cv = (const T *)U.code_v64;
+        else cv = (const T *)U.code_v32;
+        hipLaunchKernelGGL((k_kron_fused<T, TB, BS, R, true>), dim3(grid), dim3(BS), lds, st, A, U.sl_off,
+                           ell_of<T>(U), U.ell_c32, cv, ntiles);
+        HUB_HIP(hipGetLastError());
+        return HUB_OK;
+    }
     const size_t lds = (size_t)A.cu * TB * sizeof(T);
     static bool attr = false;
     if (!attr) {
-        HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R>, s->lds_max));
+        HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, false>, s->lds_max));
         attr = true;
     }
-    const int ntiles = (A.cd + TB - 1) / TB;
-    const unsigned grid = 8u * (unsigned)((ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_kron_fused<T, TB, BS, R>), dim3(grid), dim3(BS), lds, st, A, U.sl_off, ell_of<T>(U),
-                       ntiles);
+    hipLaunchKernelGGL((k_kron_fused<T, TB, BS, R, false>), dim3(grid), dim3(BS), lds, st, A, U.sl_off,
+                       ell_of<T>(U), (const uint32_t *)nullptr, (const T *)nullptr, ntiles);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
@@ -435,34 +482,41 @@ int env_int(const char *name, int dflt)
     return v ? atoi(v) : dflt;
 }
 
-// Schedule selection: environment overrides (HUB_MATVEC_IMPL 1 csr, 2 fused,
-// 3 two-pass; HUB_MATVEC_TB; HUB_MATVEC_BS 512/1024; HUB_DN_OCC; HUB_DN_NT),
-// otherwise the fused schedule with one column per workgroup.
+// Schedule selection.  Environment overrides for measurement: HUB_MATVEC_IMPL
+// (1 csr, 2 fused, 3 two-pass), HUB_MATVEC_TB, HUB_MATVEC_BS (512 / 1024),
+// HUB_FUSED_R, HUB_ELL_FMT (0 packed, 1 compact), HUB_DN_OCC, HUB_DN_NT.
+// Default (measured on the ring M=14 and the 4x4 torus): fused, compact
+// entries, 1024-thread workgroups, two columns per workgroup when they fit in
+// half of the LDS, otherwise one.
 template <typename T>
 hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
 {
     MvArgs<T> A = make_args<T>(s, x, y);
     const size_t col_bytes = (size_t)A.cu * sizeof(T);
     static const int impl = env_int("HUB_MATVEC_IMPL", 2);
-    static const int tb = env_int("HUB_MATVEC_TB", 1);
-    static const int bs = env_int("HUB_MATVEC_BS", 0);
+    static const int tb_env = env_int("HUB_MATVEC_TB", 0);
+    static const int bs_env = env_int("HUB_MATVEC_BS", 0);
     static const int occ = env_int("HUB_DN_OCC", 4);
     static const int nt = env_int("HUB_DN_NT", 1);
-    const bool fits = col_bytes <= s->lds_max;
-    const bool fits2 = 2 * col_bytes <= s->lds_max;
-    // one workgroup per CU when the panel takes more than half the LDS: use 16 waves
-    const bool big = (bs == 1024) || (bs == 0 && 2 * col_bytes * (tb >= 2 && fits2 ? 2 : 1) > s->lds_max);
+    static const int rows = env_int("HUB_FUSED_R", 4);
+    static const bool cf = env_int("HUB_ELL_FMT", 1) != 0;
+    const size_t extra = 256 * sizeof(T);
+    const size_t half = s->lds_max / 2;
+    int tb = tb_env;
+    if (tb <= 0) tb = (2 * col_bytes + extra <= half) ? 2 : 1;
+    while (tb > 1 && tb * col_bytes + extra > s->lds_max) tb >>= 1;
+    const bool fits = col_bytes + extra <= s->lds_max;
+    const bool big = bs_env != 512;
     if (impl == 3 && fits) {
-        if (tb >= 2 && fits2)
+        if (tb >= 2)
             return big ? launch_two_pass<T, 2, 1024>(s, A, st, occ, nt) : launch_two_pass<T, 2, 512>(s, A, st, occ, nt);
         return big ? launch_two_pass<T, 1, 1024>(s, A, st, occ, nt) : launch_two_pass<T, 1, 512>(s, A, st, occ, nt);
     }
-    static const int rows = env_int("HUB_FUSED_R", 4);
     if (impl == 2 && fits) {
-        if (tb >= 2 && fits2) return big ? launch_fused<T, 2, 1024, 2>(s, A, st) : launch_fused<T, 2, 512, 2>(s, A, st);
-        if (rows >= 4) return big ? launch_fused<T, 1, 1024, 4>(s, A, st) : launch_fused<T, 1, 512, 4>(s, A, st);
-        if (rows >= 2) return big ? launch_fused<T, 1, 1024, 2>(s, A, st) : launch_fused<T, 1, 512, 2>(s, A, st);
-        return big ? launch_fused<T, 1, 1024, 1>(s, A, st) : launch_fused<T, 1, 512, 1>(s, A, st);
+        if (tb >= 4) return big ? launch_fused<T, 4, 1024, 1>(s, A, st, cf) : launch_fused<T, 4, 512, 1>(s, A, st, cf);
+        if (tb >= 2) return big ? launch_fused<T, 2, 1024, 2>(s, A, st, cf) : launch_fused<T, 2, 512, 2>(s, A, st, cf);
+        if (rows >= 4) return big ? launch_fused<T, 1, 1024, 4>(s, A, st, cf) : launch_fused<T, 1, 512, 4>(s, A, st, cf);
+        return big ? launch_fused<T, 1, 1024, 1>(s, A, st, cf) : launch_fused<T, 1, 512, 1>(s, A, st, cf);
     }
     hipLaunchKernelGGL((k_kron_csr<T, 512>), dim3((unsigned)A.cd), dim3(512), 0, st, A);
     HUB_HIP(hipGetLastError());

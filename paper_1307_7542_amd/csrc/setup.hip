@@ -16,6 +16,8 @@
 // (count, exclusive scan, fill); within a row entries are placed by the numeric
 // order of the hopped states, which is their column order because rank is
 // monotone.
+#include <vector>
+
 #include "internal.h"
 
 namespace hub {
@@ -210,9 +212,10 @@ __global__ void k_slice_len(const int32_t *__restrict__ rp, int64_t count, int64
 }
 
 __global__ void k_sell_fill(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                            const double *__restrict__ val, int64_t count, const int32_t *__restrict__ sp,
+                            const double *__restrict__ val, const int32_t *__restrict__ bond,
+                            const double *__restrict__ t, int64_t count, const int32_t *__restrict__ sp,
                             int32_t *__restrict__ ecol, float *__restrict__ e32, double *__restrict__ e64,
-                            uint2 *__restrict__ pk32, uint4 *__restrict__ pk64)
+                            uint2 *__restrict__ pk32, uint4 *__restrict__ pk64, uint32_t *__restrict__ c32)
 {
     // one lane per (padded) row of a slice
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -225,13 +228,17 @@ __global__ void k_sell_fill(const int32_t *__restrict__ rp, const int32_t *__res
         const int64_t o = base + 64 * (int64_t)k + lane;
         int32_t c;
         double v;
+        uint32_t code = 255u;
         if (k < rl) {
             c = col[r0 + k];
             v = val[r0 + k];
+            const int e = bond[r0 + k];
+            code = 2u * (uint32_t)e + ((v == t[e] && v != 0.0) ? 1u : 0u);  // val = -t esign
         } else {
             c = (r < count) ? (int32_t)r : 0;
             v = 0.0;
         }
+        if (c32) c32[o] = ((uint32_t)c & 0xFFFFFFu) | (code << 24);
         ecol[o] = c;
         e64[o] = v;
         e32[o] = (float)v;
@@ -344,8 +351,24 @@ hub_status build_spin_tables(hub_sector *s, int spin, int N, hipStream_t st)
     HUB_TRY(dalloc(s, &T.ell_v64, nell));
     HUB_TRY(dalloc(s, &T.ell_pk32, nell));
     HUB_TRY(dalloc(s, &T.ell_pk64, nell));
-    hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)ns), dim3(64), 0, st, T.rp, T.col, T.val64, count, sp, T.ell_col,
-                       T.ell_v32, T.ell_v64, T.ell_pk32, T.ell_pk64);
+    const bool compact = count < (1 << 24) && s->nb <= 127;
+    if (compact) {
+        HUB_TRY(dalloc(s, &T.ell_c32, nell));
+        HUB_TRY(dalloc(s, &T.code_v64, 256));
+        HUB_TRY(dalloc(s, &T.code_v32, 256));
+        std::vector<double> cv(256, 0.0);
+        std::vector<float> cf(256, 0.0f);
+        for (int e = 0; e < s->nb; ++e) {
+            cv[2 * e] = -s->t[e];  // esign = +1
+            cv[2 * e + 1] = s->t[e];
+            cf[2 * e] = (float)cv[2 * e];
+            cf[2 * e + 1] = (float)cv[2 * e + 1];
+        }
+        HUB_HIP(hipMemcpy(T.code_v64, cv.data(), 256 * sizeof(double), hipMemcpyHostToDevice));
+        HUB_HIP(hipMemcpy(T.code_v32, cf.data(), 256 * sizeof(float), hipMemcpyHostToDevice));
+    }
+    hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)ns), dim3(64), 0, st, T.rp, T.col, T.val64, T.bond, s->d_t, count,
+                       sp, T.ell_col, T.ell_v32, T.ell_v64, T.ell_pk32, T.ell_pk64, T.ell_c32);
     HUB_HIP(hipGetLastError());
     HUB_HIP(hipStreamSynchronize(st));
     return HUB_OK;
