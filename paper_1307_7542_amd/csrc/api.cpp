@@ -1,6 +1,7 @@
 // C ABI of libhubbard: argument validation, sector construction, host copies,
 // and dispatch to the HIP kernels.  No entry point aborts or throws.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -168,6 +169,21 @@ hub_status create(const hub_model *m, int32_t n_up, int32_t n_dn, hub_sector **o
     }
     const int64_t cu = s->spin[0].count, cd = s->spin[1].count;
     if (cu > INT32_MAX || cd > INT32_MAX) return fail(HUB_ERR_RANGE, "one-spin dimension exceeds 2^31");
+    // columns that do not fit in one workgroup's LDS get row-chunked tables;
+    // HUB_CHUNK_ROWS=<n> forces them (chunks of n rows) for testing
+    const char *force = getenv("HUB_CHUNK_ROWS");
+    const int force_rows = force ? atoi(force) : 0;
+    for (int dt : {HUB_F64, HUB_F32}) {
+        const size_t es = (dt == HUB_F64) ? 8 : 4;
+        if (!s->spin[0].ell_c32) break;
+        if (force_rows > 0) {
+            HUB_TRY(build_chunked_tables(s, HUB_SPIN_UP, dt, force_rows, st));
+            s->force_chunked = true;
+        } else if ((size_t)(cu + 256) * es > s->lds_max) {
+            const int rows = (int)((s->lds_max / es - 256) / 64 * 64);
+            HUB_TRY(build_chunked_tables(s, HUB_SPIN_UP, dt, rows, st));
+        }
+    }
     s->dim = cu * cd;
     HUB_HIP(hipDeviceSynchronize());
     guard.s = nullptr;

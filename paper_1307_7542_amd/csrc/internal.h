@@ -48,6 +48,14 @@ struct SpinTables {
     uint32_t *ell_c32 = nullptr;
     double *code_v64 = nullptr;  // [256]
     float *code_v32 = nullptr;   // [256]
+    // Row-chunked compact copies for columns larger than the LDS: chunk p holds,
+    // for every row, the entries whose column lies in [p*chunk_rows, (p+1)*chunk_rows)
+    // (a contiguous sub-range of the sorted CSR row), columns relative to the chunk.
+    int nchunks[2] = {0, 0};        // per dtype (0: FP64, 1: FP32)
+    int chunk_rows[2] = {0, 0};
+    int32_t *ch_off[2] = {nullptr, nullptr};   // [nchunks * (nslices + 1)] entry offsets / 64
+    int64_t *ch_base[2] = {nullptr, nullptr};  // host-side copy not needed; device [nchunks]
+    uint32_t *ch_ell[2] = {nullptr, nullptr};
 };
 
 }  // namespace hub
@@ -73,6 +81,7 @@ struct hub_sector {
     double *d_U64 = nullptr;          // [M] per-site U
     float *d_U32 = nullptr;           // [M]
     size_t lds_max = 65536;           // dynamic LDS a workgroup may request
+    bool force_chunked = false;       // use the row-chunked product even when a column fits
     int cu_count = 256;
     std::vector<void *> owned;        // every device allocation, freed by destroy
 };
@@ -81,6 +90,7 @@ namespace hub {
 
 // ---- setup (setup.hip) -------------------------------------------------
 hub_status build_spin_tables(hub_sector *s, int spin, int N, hipStream_t st);
+hub_status build_chunked_tables(hub_sector *s, int spin, int dtype, int chunk_rows, hipStream_t st);
 hub_status rank_device(const hub_sector *s, int spin, const uint64_t *dx, int64_t n, int64_t *dout,
                        hipStream_t st);
 

@@ -256,6 +256,77 @@ __global__ __launch_bounds__(BS) void k_kron_fused(MvArgs<T> A, const int32_t *_
     }
 }
 
+// ---- row-chunked fused product (columns larger than the LDS) -------------
+// One workgroup per output column b.  The column is processed in P row
+// chunks: phase p stages V[chunk p, b] in LDS and adds, for every row, the
+// H_up entries whose column lies in chunk p; phase 0 also adds the diagonal and
+// the H_dn term.  Y[:, b] is written in phase 0 and updated in place by the
+// later phases of the same workgroup (the column is still in L2 by then).
+template <typename T, int BS, int R>
+__global__ __launch_bounds__(BS) void k_kron_chunked(MvArgs<T> A, const int32_t *__restrict__ ch_off,
+                                                     const int64_t *__restrict__ ch_base,
+                                                     const uint32_t *__restrict__ ch_ell, const T *__restrict__ code_v,
+                                                     int nchunks, int chunk_rows, int nslices)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *tab = reinterpret_cast<T *>(smem_raw);
+    T *xs = tab + 256;
+    const int tile = xcd_tile(A.cd);
+    if (tile < 0) return;
+    const int cu = A.cu;
+    const int b = tile;
+    const int64_t cu64 = cu;
+    const T *__restrict__ xb = A.x + (int64_t)b * cu;
+    T *yb = A.y + (int64_t)b * cu;
+    for (int i = threadIdx.x; i < 256; i += BS) tab[i] = code_v[i];
+    const int ds = A.dn_rp[b], de = A.dn_rp[b + 1];
+    const uint32_t dnb = A.dn_basis[b];
+    const T edn = A.e_dn[b];
+    const int lane = threadIdx.x & 63;
+    for (int p = 0; p < nchunks; ++p) {
+        const int r0 = p * chunk_rows;
+        const int r1 = min(cu, r0 + chunk_rows);
+        __syncthreads();  // previous phase done with xs
+        for (int i = r0 + threadIdx.x; i < r1; i += BS) xs[i - r0] = xb[i];
+        __syncthreads();
+        const int32_t *off = ch_off + (int64_t)p * (nslices + 1);
+        const uint32_t *ell = ch_ell + ch_base[p];
+        for (int a0 = threadIdx.x; a0 < cu; a0 += BS * R) {
+            T acc[R][1];
+            int as[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int a = min(a0 + j * BS, cu - 1);
+                as[j] = a;
+                if (p == 0) acc[j][0] = (diag_u(A, A.up_basis[a] & dnb) + A.e_up[a] + edn) * xb[a];
+                else acc[j][0] = yb[a];
+                const int s = a >> 6;
+                up_term_c<T, 1>(acc[j], xs, tab, ell, off[s] * 64 + lane, off[s + 1] - off[s]);
+            }
+            if (p == 0) {
+                int k = ds;
+                for (; k + 4 <= de; k += 4) {
+                    T y[4][R];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int j = 0; j < R; ++j) y[u][j] = A.x[(int64_t)A.dn_col[k + u] * cu64 + as[j]];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int j = 0; j < R; ++j) acc[j][0] += A.dn_val[k + u] * y[u][j];
+                }
+                for (; k < de; ++k)
+#pragma unroll
+                    for (int j = 0; j < R; ++j) acc[j][0] += A.dn_val[k] * A.x[(int64_t)A.dn_col[k] * cu64 + as[j]];
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (a0 + j * BS < cu) yb[a0 + j * BS] = acc[j][0];
+        }
+    }
+}
+
 // ---- two-pass, pass 1: Z = V H_dn^T on XCD-cooperative row tiles --------
 // A tile is TA = 128 B / sizeof(T) rows (one cache line per column), so two
 // tiles in flight stay well inside one XCD's 4 MB L2 for count_dn ~ 10^4.  A
@@ -511,6 +582,25 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
         if (tb >= 2)
             return big ? launch_two_pass<T, 2, 1024>(s, A, st, occ, nt) : launch_two_pass<T, 2, 512>(s, A, st, occ, nt);
         return big ? launch_two_pass<T, 1, 1024>(s, A, st, occ, nt) : launch_two_pass<T, 1, 512>(s, A, st, occ, nt);
+    }
+    const int di = (sizeof(T) == 8) ? 0 : 1;
+    const SpinTables &U = s->spin[0];
+    if (impl != 1 && (!fits || s->force_chunked) && U.ch_ell[di]) {
+        constexpr int BSC = 1024;
+        const size_t lds = (size_t)(U.chunk_rows[di] + 256) * sizeof(T);
+        static bool attr = false;
+        if (!attr) {
+            HUB_TRY(allow_lds(k_kron_chunked<T, BSC, 4>, s->lds_max));
+            attr = true;
+        }
+        const T *cv;
+        if constexpr (sizeof(T) == 8) cv = (const T *)U.code_v64;
+        else cv = (const T *)U.code_v32;
+        const unsigned grid = 8u * (unsigned)((A.cd + 7) / 8);
+        hipLaunchKernelGGL((k_kron_chunked<T, BSC, 4>), dim3(grid), dim3(BSC), lds, st, A, U.ch_off[di],
+                           U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di], (int)U.nslices);
+        HUB_HIP(hipGetLastError());
+        return HUB_OK;
     }
     if (impl == 2 && fits) {
         if (tb >= 4) return big ? launch_fused<T, 4, 1024, 1>(s, A, st, cf) : launch_fused<T, 4, 512, 1>(s, A, st, cf);

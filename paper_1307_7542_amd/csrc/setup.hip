@@ -16,6 +16,7 @@
 // (count, exclusive scan, fill); within a row entries are placed by the numeric
 // order of the hopped states, which is their column order because rank is
 // monotone.
+#include <algorithm>
 #include <vector>
 
 #include "internal.h"
@@ -248,6 +249,56 @@ __global__ void k_sell_fill(const int32_t *__restrict__ rp, const int32_t *__res
     }
 }
 
+// Per row: the sub-range of its (column-sorted) CSR entries with column in [c_lo, c_hi).
+__global__ void k_chunk_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t count,
+                             int c_lo, int c_hi, int32_t *__restrict__ rstart, int32_t *__restrict__ rlen)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    int k0 = rp[r], k1 = rp[r + 1];
+    int s0 = k1, s1 = k1;
+    for (int k = k0; k < k1; ++k) {
+        if (col[k] >= c_lo && s0 == k1) s0 = k;
+        if (col[k] >= c_hi) { s1 = k; break; }
+    }
+    if (s0 > s1) s0 = s1;
+    rstart[r] = s0;
+    rlen[r] = s1 - s0;
+}
+
+__global__ void k_slice_max(const int32_t *__restrict__ len, int64_t count, int64_t nslices, int32_t *__restrict__ out)
+{
+    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= nslices) return;
+    int m = 0;
+    const int64_t r1 = min(count, (sl + 1) * 64);
+    for (int64_t r = sl * 64; r < r1; ++r) m = max(m, len[r]);
+    out[sl] = m;
+}
+
+__global__ void k_chunk_fill(const int32_t *__restrict__ rstart, const int32_t *__restrict__ rlen,
+                             const int32_t *__restrict__ col, const double *__restrict__ val,
+                             const int32_t *__restrict__ bond, const double *__restrict__ t, int64_t count,
+                             const int32_t *__restrict__ sp, int c_lo, uint32_t *__restrict__ out)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t sl = r / 64, lane = r % 64;
+    const int64_t base = 64 * (int64_t)sp[sl];
+    const int len = sp[sl + 1] - sp[sl];
+    const int rl = (r < count) ? rlen[r] : 0;
+    const int r0 = (r < count) ? rstart[r] : 0;
+    for (int k = 0; k < len; ++k) {
+        uint32_t e = 255u << 24;  // padding: column 0 of the chunk, value 0
+        if (k < rl) {
+            const double v = val[r0 + k];
+            const int b = bond[r0 + k];
+            const uint32_t code = 2u * (uint32_t)b + ((v == t[b] && v != 0.0) ? 1u : 0u);
+            e = ((uint32_t)(col[r0 + k] - c_lo) & 0xFFFFFFu) | (code << 24);
+        }
+        out[base + 64 * (int64_t)k + lane] = e;
+    }
+}
+
 template <typename T>
 hub_status dalloc(hub_sector *s, T **p, size_t n)
 {
@@ -371,6 +422,79 @@ hub_status build_spin_tables(hub_sector *s, int spin, int N, hipStream_t st)
                        sp, T.ell_col, T.ell_v32, T.ell_v64, T.ell_pk32, T.ell_pk64, T.ell_c32);
     HUB_HIP(hipGetLastError());
     HUB_HIP(hipStreamSynchronize(st));
+    return HUB_OK;
+}
+
+hub_status build_chunked_tables(hub_sector *s, int spin, int dtype, int chunk_rows, hipStream_t st)
+{
+    SpinTables &T = s->spin[spin];
+    const int di = (dtype == HUB_F64) ? 0 : 1;
+    if (T.ch_ell[di]) return HUB_OK;
+    if (!T.ell_c32) {
+        set_error("row-chunked product needs the compact entry format (count < 2^24, <= 127 bonds)");
+        return HUB_ERR_UNSUPPORTED;
+    }
+    const int64_t count = T.count, ns = T.nslices;
+    const int P = (int)((count + chunk_rows - 1) / chunk_rows);
+    int32_t *rstart = nullptr, *rlen = nullptr, *slen = nullptr, *offs = nullptr;
+    int64_t *stmp = nullptr, *ssum = nullptr;
+    const int64_t snblk = (ns + kScanBlock - 1) / kScanBlock;
+    HUB_TRY(dalloc(s, &rstart, count));
+    HUB_TRY(dalloc(s, &rlen, count));
+    HUB_TRY(dalloc(s, &slen, ns));
+    HUB_TRY(dalloc(s, &offs, (size_t)P * (ns + 1)));
+    HUB_TRY(dalloc(s, &stmp, ns));
+    HUB_TRY(dalloc(s, &ssum, snblk));
+    std::vector<int64_t> base(P + 1, 0);
+    const int B = 256;
+    for (int p = 0; p < P; ++p) {
+        const int c_lo = p * chunk_rows;
+        const int c_hi = (int)std::min<int64_t>(count, (int64_t)(p + 1) * chunk_rows);
+        int32_t *sp = offs + (size_t)p * (ns + 1);
+        hipLaunchKernelGGL(k_chunk_rows, dim3(grid_for(count, B)), dim3(B), 0, st, T.rp, T.col, count, c_lo, c_hi,
+                           rstart, rlen);
+        hipLaunchKernelGGL(k_slice_max, dim3(grid_for(ns, B)), dim3(B), 0, st, rlen, count, ns, slen);
+        hipLaunchKernelGGL(k_scan_local, dim3((unsigned)snblk), dim3(kScanBlock), 0, st, slen, ns, stmp, ssum);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, ssum, snblk);
+        hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)snblk), dim3(kScanBlock), 0, st, slen, stmp, ssum, ns, sp);
+        HUB_HIP(hipGetLastError());
+        int32_t slots = 0;
+        HUB_HIP(hipMemcpyAsync(&slots, sp + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HUB_HIP(hipStreamSynchronize(st));
+        base[p + 1] = base[p] + 64 * (int64_t)slots;
+    }
+    if (base[P] >= ((int64_t)1 << 31)) {
+        set_error("row-chunked hopping matrix would exceed 2^31 entries");
+        return HUB_ERR_RANGE;
+    }
+    uint32_t *ell = nullptr;
+    int64_t *dbase = nullptr;
+    HUB_TRY(dalloc(s, &ell, (size_t)base[P]));
+    HUB_TRY(dalloc(s, &dbase, P));
+    HUB_HIP(hipMemcpy(dbase, base.data(), sizeof(int64_t) * P, hipMemcpyHostToDevice));
+    for (int p = 0; p < P; ++p) {
+        const int c_lo = p * chunk_rows;
+        const int c_hi = (int)std::min<int64_t>(count, (int64_t)(p + 1) * chunk_rows);
+        hipLaunchKernelGGL(k_chunk_rows, dim3(grid_for(count, B)), dim3(B), 0, st, T.rp, T.col, count, c_lo, c_hi,
+                           rstart, rlen);
+        hipLaunchKernelGGL(k_chunk_fill, dim3((unsigned)ns), dim3(64), 0, st, rstart, rlen, T.col, T.val64, T.bond,
+                           s->d_t, count, offs + (size_t)p * (ns + 1), c_lo, ell + base[p]);
+    }
+    HUB_HIP(hipGetLastError());
+    HUB_HIP(hipStreamSynchronize(st));
+    T.nchunks[di] = P;
+    T.chunk_rows[di] = chunk_rows;
+    T.ch_off[di] = offs;
+    T.ch_base[di] = dbase;
+    T.ch_ell[di] = ell;
+    if (s->shared_spin && spin == 0) {
+        SpinTables &D = s->spin[1];
+        D.nchunks[di] = P;
+        D.chunk_rows[di] = chunk_rows;
+        D.ch_off[di] = offs;
+        D.ch_base[di] = dbase;
+        D.ch_ell[di] = ell;
+    }
     return HUB_OK;
 }
 

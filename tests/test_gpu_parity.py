@@ -434,3 +434,29 @@ def test_param_bilinear_vs_oracle(hub, which):
     assert abs(euler - gs.e0) <= 1e-9 * abs(gs.e0)
     s.close()
     del torch
+
+
+@pytest.mark.parametrize("chunk", [64, 200, 1000])
+def test_matvec_row_chunked_parity(hub, chunk, monkeypatch):
+    """The row-chunked product (used when a column exceeds the LDS) forced on
+    small sectors with several chunks and a ragged last chunk."""
+    import torch
+    monkeypatch.setenv("HUB_CHUNK_ROWS", str(chunk))
+    for m in (W.square_periodic(3, 4, n_up=5, n_dn=4), W.random_graph(10, 17, seed=303, site_U=True)):
+        s = hub.Sector(m)
+        osec = oracle.Sector(m)
+        xr = oracle.start_vector(5, osec.dim)
+        yr = oracle.spmv(osec.csr(), xr)
+        bound = _row_abs(osec, xr)
+        x64 = s.start_vector(seed=5, normalize=False)
+        y64 = s.matvec(x64).cpu().numpy()
+        assert np.all(np.abs(y64 - yr) <= 1e-13 * bound + 1e-300)
+        x32 = x64.to(torch.float32)
+        y32 = s.matvec(x32).cpu().numpy().astype(np.float64)
+        yr32 = oracle.spmv(osec.csr(), x32.cpu().numpy().astype(np.float64))
+        assert np.all(np.abs(y32 - yr32) <= 1e-5 * bound + 1e-30)
+        gs = s.ground_state(dtype=hub.F64, want_vector=False, tol=1e-12)
+        e_ref = np.linalg.eigvalsh(osec.dense())[0] if osec.dim <= 4000 else None
+        if e_ref is not None:
+            assert abs(gs.e0 - e_ref) <= 1e-10 * abs(e_ref)
+        s.close()
