@@ -220,6 +220,54 @@ hub_status hub_ground_state(const hub_sector *sec, const hub_lanczos_opts *opts,
 hub_status hub_param_bilinear(const hub_sector *sec, const void *dev_g, const void *dev_x, double *dbond,
                               double *dU, double *deps, void *stream);
 
+/*
+ * Batches of independent sectors, e.g. the impurity problems an exact-
+ * diagonalisation DMFT solver diagonalises at every step (Sec. VIII).  One
+ * product launch covers every sector of the batch (work items are column tiles
+ * of all sectors); batch vectors are the concatenation of the sector vectors in
+ * batch order (offsets from hub_batch_offsets).  The sectors are borrowed and
+ * must outlive the batch.  The first product of each dtype times a few tile
+ * shapes (columns per workgroup, workgroup size) on the batch itself and keeps
+ * the fastest.  Errors of hub_batch_create: INVALID_ARG (NULL, count <= 0,
+ * sectors on different devices), UNSUPPORTED (a sector whose FP64 up-spin
+ * column does not fit in the LDS, or without 4-byte product entries), OOM.
+ */
+typedef struct hub_batch hub_batch;
+
+hub_status hub_batch_create(const hub_sector *const *sectors, int32_t count, hub_batch **out);
+void hub_batch_destroy(hub_batch *batch);
+
+/* offsets[0..count]: start of each sector's slice in a batch vector; offsets[count] = total length. */
+hub_status hub_batch_offsets(const hub_batch *batch, int64_t *offsets);
+
+/* y = H x for every sector of the batch, one launch (after tuning).  Device
+ * vectors of the total length, no overlap.  Asynchronous on `stream`. */
+hub_status hub_batch_matvec(hub_batch *batch, int32_t dtype, const void *dev_x, void *dev_y, void *stream);
+
+typedef struct hub_batch_info {
+    int32_t steps;            /* lockstep Lanczos steps taken (max over sectors) */
+    int32_t graph_replays;    /* steps executed by replaying the captured step graph */
+    int32_t tile_columns;     /* tuned columns per workgroup of the product */
+    int32_t block_size;       /* tuned workgroup size of the product */
+    double seconds;           /* wall time of the call */
+    double tune_seconds;      /* part of it spent tuning (first call per dtype) */
+} hub_batch_info;
+
+/*
+ * Lowest eigenvalue of every sector of the batch by the plain Lanczos
+ * recurrence (Sec. IV) run in lockstep: per-sector alpha / beta in FP64 on the
+ * device, converged sectors masked out, one step captured once as a HIP graph
+ * and replayed.  opts as for hub_ground_state except reorth (must be 0:
+ * UNSUPPORTED) and dev_start (must be NULL: UNSUPPORTED); refine without
+ * dev_psi is INVALID_ARG.
+ * e0[count] receives the Ritz values (or FP64 Rayleigh quotients with refine),
+ * iters[count] (may be NULL) the steps per sector.  dev_psi: NULL or an FP64
+ * batch vector receiving the unit-norm ground states (sign as in
+ * hub_ground_state).  Synchronous.  NOT_CONVERGED if any sector hit max_iter.
+ */
+hub_status hub_batch_ground_state(hub_batch *batch, const hub_lanczos_opts *opts, double *e0, int32_t *iters,
+                                  void *dev_psi, void *stream, hub_batch_info *info);
+
 /* Algorithmic bytes of one product in `dtype`: read x, write y, plus the tables. */
 hub_status hub_matvec_bytes(const hub_sector *sec, int32_t dtype, int64_t *bytes);
 

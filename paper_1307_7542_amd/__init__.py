@@ -26,7 +26,8 @@ EXPORTED = [
     "hub_sector_create", "hub_sector_destroy", "hub_sector_dims", "hub_sector_bonds", "hub_basis",
     "hub_rank", "hub_hopping_nnz", "hub_hopping_csr", "hub_diagonal", "hub_start_vector",
     "hub_matvec", "hub_ground_state", "hub_param_bilinear", "hub_matvec_bytes", "hub_status_str",
-    "hub_last_error", "hub_version",
+    "hub_last_error", "hub_version", "hub_batch_create", "hub_batch_destroy", "hub_batch_offsets",
+    "hub_batch_matvec", "hub_batch_ground_state",
 ]
 
 
@@ -92,6 +93,11 @@ def lib():
             "hub_ground_state": (i32, [P, P, P, P, P, P]),
             "hub_param_bilinear": (i32, [P, P, P, P, P, P, P]),
             "hub_matvec_bytes": (i32, [P, i32, P]),
+            "hub_batch_create": (i32, [P, i32, P]),
+            "hub_batch_destroy": (None, [P]),
+            "hub_batch_offsets": (i32, [P, P]),
+            "hub_batch_matvec": (i32, [P, i32, P, P, P]),
+            "hub_batch_ground_state": (i32, [P, P, P, P, P, P, P]),
             "hub_status_str": (ctypes.c_char_p, [i32]),
             "hub_last_error": (ctypes.c_char_p, []),
             "hub_version": (ctypes.c_char_p, []),
@@ -281,6 +287,71 @@ class Sector:
         _check(lib().hub_param_bilinear(self._h, _dev_ptr(g, F64, self.dim, "g"), _dev_ptr(x, F64, self.dim, "x"),
                                         _ptr(db), _ptr(dU), _ptr(de), _stream(stream)), "hub_param_bilinear")
         return db[:nb], dU, de
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int32), ("graph_replays", ctypes.c_int32), ("tile_columns", ctypes.c_int32),
+        ("block_size", ctypes.c_int32), ("seconds", ctypes.c_double), ("tune_seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Batch:
+    """Independent sectors solved together (one product launch for all of
+    them, lockstep Lanczos replayed from a captured HIP graph).  Batch vectors
+    concatenate the sector vectors in order; `offsets` gives the slices."""
+
+    def __init__(self, sectors: Sequence[Sector]):
+        self.sectors = list(sectors)  # keep them alive
+        arr = (ctypes.c_void_p * len(self.sectors))(*[s._h.value for s in self.sectors])
+        h = ctypes.c_void_p()
+        _check(lib().hub_batch_create(arr, len(self.sectors), ctypes.byref(h)), "hub_batch_create")
+        self._h = h
+        off = np.zeros(len(self.sectors) + 1, dtype=np.int64)
+        _check(lib().hub_batch_offsets(h, _ptr(off)), "hub_batch_offsets")
+        self.offsets = off
+        self.total = int(off[-1])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hub_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self, dtype: int = F64):
+        torch = _torch()
+        return torch.empty(self.total, dtype=torch.float64 if dtype == F64 else torch.float32, device="cuda")
+
+    def matvec(self, x, y=None, stream=None):
+        torch = _torch()
+        dtype = F64 if x.dtype == torch.float64 else F32
+        y = self.empty(dtype) if y is None else y
+        _check(lib().hub_batch_matvec(self._h, dtype, _dev_ptr(x, dtype, self.total, "x"),
+                                      _dev_ptr(y, dtype, self.total, "y"), _stream(stream)), "hub_batch_matvec")
+        return y
+
+    def ground_state(self, *, dtype: int = F64, want_vector: bool = False, refine: bool = False,
+                     max_iter: int = 400, tol: float = 0.0, seed: int = 7542, check_every: int = 5,
+                     stream=None, allow_not_converged: bool = False):
+        want = want_vector or refine
+        psi = self.empty(F64) if want else None
+        o = LanczosOpts(max_iter, tol, seed, None, dtype, 0, int(want_vector), int(refine), check_every, 0)
+        e0 = np.zeros(len(self.sectors))
+        it = np.zeros(len(self.sectors), dtype=np.int32)
+        info = BatchInfo()
+        allow = (HUB_OK, HUB_ERR_NOT_CONVERGED) if allow_not_converged else (HUB_OK,)
+        _check(lib().hub_batch_ground_state(self._h, ctypes.byref(o), _ptr(e0), _ptr(it),
+                                            _dev_ptr(psi, F64, self.total, "psi") if want else None,
+                                            _stream(stream), ctypes.byref(info)), "hub_batch_ground_state", allow)
+        return e0, it, psi, info.as_dict()
 
 
 def version() -> str:

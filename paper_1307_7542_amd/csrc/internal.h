@@ -133,6 +133,7 @@ hub_status param_bilinear(const hub_sector *s, const double *g, const double *x,
                           double *deps, hipStream_t st);
 
 // ---- Lanczos (lanczos.cpp) ---------------------------------------------
+double tri_lowest(const double *a, const double *b, int m, std::vector<double> &y);
 hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *e0_out, void *dev_psi,
                         hipStream_t st, hub_lanczos_info *info);
 

@@ -30,6 +30,8 @@ int sturm_count(const double *a, const double *b, int m, double x, double pivmin
     return cnt;
 }
 
+}  // namespace
+
 // Lowest eigenpair of the m x m symmetric tridiagonal matrix; y has unit norm.
 double tri_lowest(const double *a, const double *b, int m, std::vector<double> &y)
 {
@@ -111,6 +113,8 @@ double tri_lowest(const double *a, const double *b, int m, std::vector<double> &
     y = r;
     return theta;
 }
+
+namespace {
 
 struct DevMem {
     std::vector<void *> ptrs;
