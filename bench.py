@@ -68,6 +68,76 @@ def product_timing(hub, torch, model, reps=10):
     return out
 
 
+def batch_timing(hub, torch, count=64):
+    """The synthetic impurity-model batch (one DMFT step's exact-diagonalisation
+    solves): one batched FP64 solve and one FP32 solve with FP64 refinement,
+    against the same sectors solved one after another; plus one batched product."""
+    import workloads as W
+    models = W.aim_batch(count)
+    secs = [hub.Sector(m) for m in models]
+    batch = hub.Batch(secs)
+    kw = dict(tol=1e-12, max_iter=400, check_every=5)
+    batch.ground_state(dtype=hub.F64, **kw)  # tunes the product tiles
+    batch.ground_state(dtype=hub.F32, tol=1e-7, refine=True, max_iter=400, check_every=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e_b, it_b, _, info = batch.ground_state(dtype=hub.F64, **kw)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    e_m, _, _, _ = batch.ground_state(dtype=hub.F32, tol=1e-7, refine=True, max_iter=400, check_every=5)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    e_s = [s.ground_state(dtype=hub.F64, want_vector=False, **kw).e0 for s in secs]
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    x = batch.empty(hub.F64)
+    x.fill_(1.0)
+    y = batch.empty(hub.F64)
+    batch.matvec(x, y)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        batch.matvec(x, y)
+    ev1.record()
+    torch.cuda.synchronize()
+    mv_ms = ev0.elapsed_time(ev1) / 10
+    mv_bytes = sum(s.matvec_bytes(hub.F64) for s in secs)
+    out = {"sectors": count, "total_dim": batch.total, "max_dim": int(max(s.dim for s in secs)),
+           "batch_fp64_s": t_b, "batch_f32_refined_s": t_m, "sequential_fp64_s": t_s,
+           "batch_speedup_fp64": t_s / t_b, "steps": info["steps"], "graph_replays": info["graph_replays"],
+           "max_iters": int(it_b.max()), "tile_columns": info["tile_columns"], "block_size": info["block_size"],
+           "max_abs_diff_batch_vs_sequential": float(max(abs(a - b) for a, b in zip(e_b, e_s))),
+           "max_abs_diff_refined_vs_fp64": float(max(abs(a - b) for a, b in zip(e_m, e_b))),
+           "product_f64_ms": mv_ms, "product_f64_GBps": mv_bytes / mv_ms / 1e6}
+    del x, y
+    batch.close()
+    for s in secs:
+        s.close()
+    return out
+
+
+def greens_timing(hub, torch, model, steps=150):
+    """Zero-temperature G_up(0, z) on the ring: ground state, then the particle
+    and hole continued fractions (N+1 and N-1 sectors built inside the call)."""
+    import numpy as np
+    sec = hub.Sector(model)
+    gs = sec.ground_state(dtype=hub.F64, tol=1e-13, want_vector=True, max_iter=600)
+    z = 0.5 * float(model.U[0]) + 1j * np.pi * (2 * np.arange(32) + 1) / 10.0
+    sec.greens_function(gs.e0, gs.psi, 0, 0, z[:1], max_steps=8)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, info, _ = sec.greens_function(gs.e0, gs.psi, 0, 0, z, max_steps=steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"site": 0, "spin": "up", "max_steps": steps, "seconds": dt, "steps_particle": info["steps_particle"],
+           "steps_hole": info["steps_hole"], "sum_rule": info["norm2_particle"] + info["norm2_hole"],
+           "max_abs_re_G_at_U/2+iw": float(np.max(np.abs(g.real)))}
+    sec.close()
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -234,6 +304,8 @@ def main():
         pass
     if not args.no_extra:
         out["products_square4x4"] = product_timing(hub, torch, W.config("square4x4"))
+        out["aim_batch64"] = batch_timing(hub, torch)
+        out["greens_ring14_u4"] = greens_timing(hub, torch, models[4])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(models[4], args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -268,6 +268,58 @@ typedef struct hub_batch_info {
 hub_status hub_batch_ground_state(hub_batch *batch, const hub_lanczos_opts *opts, double *e0, int32_t *iters,
                                   void *dev_psi, void *stream, hub_batch_info *info);
 
+/*
+ * Zero-temperature one-particle Green's function (Sec. VII A, the second
+ * equation labelled count8):
+ *   G_s(p, z) = <psi0| c_ps (z + E0 - H)^-1 c+_ps |psi0> + <psi0| c+_ps (z - E0 + H)^-1 c_ps |psi0>
+ * for site p (0-based, bit p of the occupation integers) and spin s (0 up,
+ * 1 down), at complex z (e.g. i w_n).  Operator ordering: all up creation
+ * operators (ascending site) left of all down ones, as in the kets of Sec. II,
+ * so c+_ps carries (-1)^(occupied spin-s sites below p), times (-1)^N_up for
+ * s = down.
+ */
+
+/* y = c+_{site,spin} x (create != 0, dst has one more spin-`spin` particle) or
+ * y = c_{site,spin} x (create == 0, one fewer) between two sectors of the same
+ * lattice.  FP64 device vectors (x: src dim, y: dst dim, no overlap); every
+ * element of y is written (exact sign flips and copies, zeros elsewhere).
+ * INVALID_ARG if the sectors do not differ by exactly that particle or the
+ * site / spin is out of range.  Synchronises `stream` before returning. */
+hub_status hub_apply_fermion(const hub_sector *src, const hub_sector *dst, int32_t site, int32_t spin, int32_t create,
+                             const void *dev_x, void *dev_y, void *stream);
+
+/* Continued-fraction coefficients of <f|(w - H)^-1|f> = norm2 / (w - a0 - b1^2 / (w - a1 - ...)):
+ * plain FP64 Lanczos (Sec. IV) from v0 = f / |f| (dev_f: FP64 device vector of
+ * the sector, not modified) for min(max_steps, dim) steps or up to the first
+ * breakdown.  Host outputs: alpha[0..max_steps] (a0..a_{m-1}, rest 0),
+ * beta[0..max_steps] (beta[0] = 0, b1..b_{m-1}, rest 0), *norm2 = <f|f>,
+ * *steps = m (0 when f = 0).  Synchronous. */
+hub_status hub_lanczos_coefficients(const hub_sector *sec, const void *dev_f, int32_t max_steps, double *alpha,
+                                    double *beta, double *norm2, int32_t *steps, void *stream);
+
+/* out[i] = norm2 / (w_i - a0 - b1^2 / (w_i - a1 - ... / (w_i - a_{steps-1}))), complex w
+ * as (re, im) arrays; 0 when steps == 0.  Host only. */
+hub_status hub_continued_fraction(const double *alpha, const double *beta, int32_t steps, double norm2, int32_t nz,
+                                  const double *w_re, const double *w_im, double *out_re, double *out_im);
+
+typedef struct hub_gf_info {
+    int32_t steps_particle;   /* Lanczos steps of the c+ part (0 if the N+1 sector is empty) */
+    int32_t steps_hole;       /* Lanczos steps of the c part (0 if N = 0) */
+    double norm2_particle;    /* <psi0| c c+ |psi0> */
+    double norm2_hole;        /* <psi0| c+ c |psi0>; the two add up to <psi0|psi0> */
+    double seconds;
+} hub_gf_info;
+
+/* G_s(p, z) at nz points from the ground state (e0, dev_psi: FP64 device vector
+ * of `sec`, normalised) of `sec`.  Builds the (N_s + 1) and (N_s - 1) sectors
+ * of the same lattice internally, applies c+ / c and runs
+ * hub_lanczos_coefficients on each (max_steps each).  coef: NULL or
+ * 4 * (max_steps + 1) doubles receiving alpha / beta of the particle part,
+ * then alpha / beta of the hole part.  Synchronous. */
+hub_status hub_greens_function(const hub_sector *sec, double e0, const void *dev_psi, int32_t site, int32_t spin,
+                               int32_t max_steps, int32_t nz, const double *z_re, const double *z_im, double *g_re,
+                               double *g_im, double *coef, hub_gf_info *info, void *stream);
+
 /* Algorithmic bytes of one product in `dtype`: read x, write y, plus the tables. */
 hub_status hub_matvec_bytes(const hub_sector *sec, int32_t dtype, int64_t *bytes);
 

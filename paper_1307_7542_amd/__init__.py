@@ -27,7 +27,8 @@ EXPORTED = [
     "hub_rank", "hub_hopping_nnz", "hub_hopping_csr", "hub_diagonal", "hub_start_vector",
     "hub_matvec", "hub_ground_state", "hub_param_bilinear", "hub_matvec_bytes", "hub_status_str",
     "hub_last_error", "hub_version", "hub_batch_create", "hub_batch_destroy", "hub_batch_offsets",
-    "hub_batch_matvec", "hub_batch_ground_state",
+    "hub_batch_matvec", "hub_batch_ground_state", "hub_apply_fermion", "hub_lanczos_coefficients",
+    "hub_continued_fraction", "hub_greens_function",
 ]
 
 
@@ -98,6 +99,10 @@ def lib():
             "hub_batch_offsets": (i32, [P, P]),
             "hub_batch_matvec": (i32, [P, i32, P, P, P]),
             "hub_batch_ground_state": (i32, [P, P, P, P, P, P, P]),
+            "hub_apply_fermion": (i32, [P, P, i32, i32, i32, P, P, P]),
+            "hub_lanczos_coefficients": (i32, [P, P, i32, P, P, P, P, P]),
+            "hub_continued_fraction": (i32, [P, P, i32, ctypes.c_double, i32, P, P, P, P]),
+            "hub_greens_function": (i32, [P, ctypes.c_double, P, i32, i32, i32, i32, P, P, P, P, P, P, P]),
             "hub_status_str": (ctypes.c_char_p, [i32]),
             "hub_last_error": (ctypes.c_char_p, []),
             "hub_version": (ctypes.c_char_p, []),
@@ -278,6 +283,41 @@ class Sector:
                                       _stream(stream), ctypes.byref(info)), "hub_ground_state", allow)
         return GroundState(e0.value, psi if want else None, info.as_dict())
 
+    # ------------------------------------------------ Green's function
+    def apply_fermion(self, dst: "Sector", site: int, spin: int, create: bool, x, y=None, stream=None):
+        """y = c+_{site,spin} x (create) or c_{site,spin} x into sector `dst` (FP64)."""
+        y = dst.empty(F64) if y is None else y
+        _check(lib().hub_apply_fermion(self._h, dst._h, int(site), int(spin), int(bool(create)),
+                                       _dev_ptr(x, F64, self.dim, "x"), _dev_ptr(y, F64, dst.dim, "y"),
+                                       _stream(stream)), "hub_apply_fermion")
+        return y
+
+    def lanczos_coefficients(self, f, max_steps: int, stream=None):
+        """(alpha, beta, norm2, steps) of <f|(w - H)^-1|f> by plain FP64 Lanczos."""
+        a = np.zeros(max_steps + 1)
+        b = np.zeros(max_steps + 1)
+        n2 = ctypes.c_double()
+        m = ctypes.c_int32()
+        _check(lib().hub_lanczos_coefficients(self._h, _dev_ptr(f, F64, self.dim, "f"), int(max_steps), _ptr(a),
+                                              _ptr(b), ctypes.byref(n2), ctypes.byref(m), _stream(stream)),
+               "hub_lanczos_coefficients")
+        return a, b, n2.value, m.value
+
+    def greens_function(self, e0: float, psi, site: int, spin: int, z, max_steps: int = 200, stream=None):
+        """Zero-temperature G_spin(site, z) at complex points z; returns
+        (G, info, coefficients [alpha_p, beta_p, alpha_h, beta_h])."""
+        z = np.atleast_1d(np.asarray(z, dtype=np.complex128))
+        zr = np.ascontiguousarray(z.real)
+        zi = np.ascontiguousarray(z.imag)
+        gr = np.zeros(len(z))
+        gi = np.zeros(len(z))
+        coef = np.zeros((4, max_steps + 1))
+        info = GfInfo()
+        _check(lib().hub_greens_function(self._h, float(e0), _dev_ptr(psi, F64, self.dim, "psi"), int(site),
+                                         int(spin), int(max_steps), len(z), _ptr(zr), _ptr(zi), _ptr(gr), _ptr(gi),
+                                         _ptr(coef), ctypes.byref(info), _stream(stream)), "hub_greens_function")
+        return gr + 1j * gi, info.as_dict(), coef
+
     def param_bilinear(self, g, x, stream=None):
         """(dbond, dU, deps) = g^T (dH/dtheta) x for canonical bonds, U_i and eps_i."""
         nb = len(self.bonds()[0])
@@ -287,6 +327,30 @@ class Sector:
         _check(lib().hub_param_bilinear(self._h, _dev_ptr(g, F64, self.dim, "g"), _dev_ptr(x, F64, self.dim, "x"),
                                         _ptr(db), _ptr(dU), _ptr(de), _stream(stream)), "hub_param_bilinear")
         return db[:nb], dU, de
+
+
+class GfInfo(ctypes.Structure):
+    _fields_ = [
+        ("steps_particle", ctypes.c_int32), ("steps_hole", ctypes.c_int32), ("norm2_particle", ctypes.c_double),
+        ("norm2_hole", ctypes.c_double), ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def continued_fraction(alpha, beta, steps: int, norm2: float, w) -> np.ndarray:
+    """<f|(w - H)^-1|f> from Lanczos coefficients, at complex points w."""
+    w = np.atleast_1d(np.asarray(w, dtype=np.complex128))
+    wr = np.ascontiguousarray(w.real)
+    wi = np.ascontiguousarray(w.imag)
+    orr = np.zeros(len(w))
+    oi = np.zeros(len(w))
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    _check(lib().hub_continued_fraction(_ptr(a), _ptr(b), int(steps), float(norm2), len(w), _ptr(wr), _ptr(wi),
+                                        _ptr(orr), _ptr(oi)), "hub_continued_fraction")
+    return orr + 1j * oi
 
 
 class BatchInfo(ctypes.Structure):

@@ -134,6 +134,8 @@ hub_status param_bilinear(const hub_sector *s, const double *g, const double *x,
 
 // ---- Lanczos (lanczos.cpp) ---------------------------------------------
 double tri_lowest(const double *a, const double *b, int m, std::vector<double> &y);
+hub_status lanczos_coefficients(const hub_sector *s, const double *f, int max_steps, double *alpha, double *beta,
+                                double *norm2, int32_t *steps, hipStream_t st);
 hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *e0_out, void *dev_psi,
                         hipStream_t st, hub_lanczos_info *info);
 

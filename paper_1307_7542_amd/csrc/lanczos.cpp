@@ -4,6 +4,7 @@
 // when the convergence test runs.  The small tridiagonal eigenproblem is solved
 // on the host: the lowest eigenvalue by bisection on the Sturm sequence count,
 // its eigenvector by inverse iteration with a partially pivoted tridiagonal LU.
+#include <algorithm>
 #include <chrono>
 #include <cfloat>
 #include <cmath>
@@ -375,6 +376,78 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         set_error("Lanczos did not converge within max_iter");
         return HUB_ERR_NOT_CONVERGED;
     }
+    return HUB_OK;
+}
+
+// Continued-fraction coefficients of <f|(w - H)^-1|f> (Sec. VII A): the plain
+// FP64 recurrence from v0 = f / |f|, run for min(max_steps, dim) steps or to the
+// first breakdown (beta below 64 eps of the running |T| bound, checked every
+// 16 steps).  alpha[0..m-1], beta[1..m-1] (beta[0] = 0), norm2 = <f|f>.
+hub_status lanczos_coefficients(const hub_sector *s, const double *f, int max_steps, double *alpha, double *beta,
+                                double *norm2, int32_t *steps, hipStream_t st)
+{
+    const int64_t n = s->dim;
+    int kmax = max_steps;
+    if ((int64_t)kmax > n) kmax = (int)n;
+    DevMem mem;
+    double *dscal = nullptr;  // alpha[kmax] beta[kmax + 1] norm[2]
+    HUB_TRY(mem.alloc((void **)&dscal, sizeof(double) * (size_t)(2 * kmax + 4)));
+    HUB_HIP(hipMemsetAsync(dscal, 0, sizeof(double) * (size_t)(2 * kmax + 4), st));
+    double *d_alpha = dscal, *d_beta = dscal + kmax, *d_norm = dscal + 2 * kmax + 1;
+    double *partial = nullptr;
+    HUB_TRY(mem.alloc((void **)&partial, sizeof(double) * (size_t)kRedGrid * 2));
+    void *W = nullptr, *Va = nullptr, *Vb = nullptr;
+    HUB_TRY(mem.alloc(&W, sizeof(double) * (size_t)n));
+    HUB_TRY(mem.alloc(&Va, sizeof(double) * (size_t)n));
+    HUB_TRY(mem.alloc(&Vb, sizeof(double) * (size_t)n));
+    HUB_TRY(launch_dot(HUB_F64, f, f, n, partial, d_norm, 0, st));
+    double nf = 0.0;
+    HUB_HIP(hipMemcpyAsync(&nf, d_norm, sizeof(double), hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    *norm2 = nf;
+    *steps = 0;
+    for (int j = 0; j <= max_steps; ++j) alpha[j] = beta[j] = 0.0;
+    if (!(nf > 0.0)) return HUB_OK;
+    HUB_TRY(launch_dot(HUB_F64, f, f, n, partial, d_norm + 1, 1, st));
+    HUB_TRY(launch_convert(HUB_F64, f, HUB_F64, Va, n, d_norm + 1, 1, st));
+    void *v_prev = nullptr, *v = Va, *spare = Vb;
+    std::vector<double> ha(kmax), hb(kmax + 1);
+    int m = kmax;
+    double tmax = 0.0;
+    for (int k = 0; k < kmax; ++k) {
+        HUB_TRY(launch_matvec(s, HUB_F64, v, W, st));
+        HUB_TRY(launch_lz_a(HUB_F64, W, v_prev, d_beta + k, v, n, partial, d_alpha + k, st));
+        HUB_TRY(launch_lz_b(HUB_F64, W, v, d_alpha + k, n, partial, d_beta + k + 1, st));
+        const bool last = (k + 1 == kmax);
+        if ((k + 1) % 16 == 0 || last) {
+            const int mm = k + 1;
+            HUB_HIP(hipMemcpyAsync(ha.data(), d_alpha, sizeof(double) * mm, hipMemcpyDeviceToHost, st));
+            HUB_HIP(hipMemcpyAsync(hb.data(), d_beta, sizeof(double) * (mm + 1), hipMemcpyDeviceToHost, st));
+            HUB_HIP(hipStreamSynchronize(st));
+            bool brk = false;
+            tmax = 0.0;
+            for (int j = 0; j < mm; ++j) {
+                tmax = std::max(tmax, std::fabs(ha[j]) + 2.0 * std::fabs(hb[j + 1]));
+                if (!(hb[j + 1] > 64.0 * DBL_EPSILON * std::max(tmax, DBL_MIN))) {
+                    m = j + 1;
+                    brk = true;
+                    break;
+                }
+            }
+            if (brk) break;
+        }
+        if (last) break;
+        void *vn = v_prev ? v_prev : spare;
+        HUB_TRY(launch_lz_next(HUB_F64, W, vn, d_beta + k + 1, n, st));
+        v_prev = v;
+        v = vn;
+    }
+    HUB_HIP(hipMemcpyAsync(ha.data(), d_alpha, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipMemcpyAsync(hb.data(), d_beta, sizeof(double) * (m + 1), hipMemcpyDeviceToHost, st));
+    HUB_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < m; ++j) alpha[j] = ha[j];
+    for (int j = 1; j < m; ++j) beta[j] = hb[j];
+    *steps = m;
     return HUB_OK;
 }
 

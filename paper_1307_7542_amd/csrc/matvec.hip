@@ -370,6 +370,49 @@ __global__ __launch_bounds__(BS) void k_kron_dn_tiles(MvArgs<T> A, T *z, int nti
     }
 }
 
+// Pass 1 in dispatch order: workgroup g takes (row tile, column chunk) with
+// the tiles of XCD g mod 8 in increasing order and the chunks of one tile
+// consecutive.  Workgroups are dispatched in index order, so the ones resident
+// on an XCD at any moment share one or two row tiles (TA rows of every
+// column), which stay in that XCD's L2 while the neighbour reads hit them.
+template <typename T, int BS, bool NT>
+__global__ __launch_bounds__(BS) void k_kron_dn_otiles(MvArgs<T> A, T *z, int ntiles, int nchunks, int chunk_cols)
+{
+    constexpr int TA = 128 / (int)sizeof(T);
+    constexpr int CPW = 64 / TA;
+    constexpr int CPB = (BS / 64) * CPW;
+    const int64_t cu = A.cu;
+    const int cd = A.cd;
+    const int xcd = blockIdx.x & 7;
+    const int r = blockIdx.x >> 3;
+    const int tile = (r / nchunks) * 8 + xcd;
+    if (tile >= ntiles) return;
+    const int chunk = r - (r / nchunks) * nchunks;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sub = lane / TA, row = lane % TA;
+    const int c0 = chunk * chunk_cols, c1 = min(cd, c0 + chunk_cols);
+    const int a = tile * TA + row;
+    const bool live = a < cu;
+    const T *__restrict__ xa = A.x + (live ? a : 0);
+    for (int b = c0 + wave * CPW + sub; b < c1; b += CPB) {
+        const int ks = A.dn_rp[b], ke = A.dn_rp[b + 1];
+        T acc = (T)0;
+        int k = ks;
+        for (; k + 8 <= ke; k += 8) {
+            T y[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) y[u] = xa[(int64_t)A.dn_col[k + u] * cu];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += A.dn_val[k + u] * y[u];
+        }
+        for (; k < ke; ++k) acc += A.dn_val[k] * xa[(int64_t)A.dn_col[k] * cu];
+        if (live) {
+            if (NT) __builtin_nontemporal_store(acc, z + (int64_t)b * cu + a);
+            else z[(int64_t)b * cu + a] = acc;
+        }
+    }
+}
+
 // ---- two-pass, pass 2: Y = Z + H_up V + D o V on LDS column panels --------
 template <typename T, int TB, int BS>
 __global__ __launch_bounds__(BS) void k_kron_up_panels(MvArgs<T> A, const T *z, const int32_t *__restrict__ sl_off,
@@ -520,6 +563,12 @@ hub_status launch_fused(const hub_sector *s, const MvArgs<T> &A, hipStream_t st,
     return HUB_OK;
 }
 
+int env_int(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    return v ? atoi(v) : dflt;
+}
+
 template <typename T, int TB, int BS>
 hub_status launch_two_pass(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int occ, int nt)
 {
@@ -527,7 +576,19 @@ hub_status launch_two_pass(const hub_sector *s, const MvArgs<T> &A, hipStream_t 
     const SpinTables &U = s->spin[0];
     const int ntiles_d = (A.cu + (128 / (int)sizeof(T)) - 1) / (128 / (int)sizeof(T));
     const int per_xcd = (s->cu_count / 8) * occ;
-    if (nt)
+    static const int ordered = env_int("HUB_DN_ORDER", 1);
+    static const int chunk_env = env_int("HUB_DN_CH", 256);
+    if (ordered) {
+        const int chunk_cols = std::max(1, chunk_env);
+        const int nchunks = (A.cd + chunk_cols - 1) / chunk_cols;
+        const unsigned grid = 8u * (unsigned)((ntiles_d + 7) / 8) * (unsigned)nchunks;
+        if (nt)
+            hipLaunchKernelGGL((k_kron_dn_otiles<T, BSD, true>), dim3(grid), dim3(BSD), 0, st, A, A.y, ntiles_d,
+                               nchunks, chunk_cols);
+        else
+            hipLaunchKernelGGL((k_kron_dn_otiles<T, BSD, false>), dim3(grid), dim3(BSD), 0, st, A, A.y, ntiles_d,
+                               nchunks, chunk_cols);
+    } else if (nt)
         hipLaunchKernelGGL((k_kron_dn_tiles<T, BSD, true>), dim3(8 * per_xcd), dim3(BSD), 0, st, A, A.y, ntiles_d,
                            per_xcd);
     else
@@ -545,12 +606,6 @@ hub_status launch_two_pass(const hub_sector *s, const MvArgs<T> &A, hipStream_t 
                        ell_of<T>(U), ntiles);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
-}
-
-int env_int(const char *name, int dflt)
-{
-    const char *v = getenv(name);
-    return v ? atoi(v) : dflt;
 }
 
 // Schedule selection.  Environment overrides for measurement: HUB_MATVEC_IMPL

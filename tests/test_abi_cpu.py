@@ -88,3 +88,19 @@ def test_nonfinite_U_rejected(L):
     m, keep = _model(3, [(0, 1)], [1.0], U=[1.0, float("nan"), 0.0])
     h = ctypes.c_void_p()
     assert L.hub_sector_create(ctypes.byref(m), 1, 1, ctypes.byref(h)) == 1
+
+
+def test_continued_fraction_host_entry_point():
+    """hub_continued_fraction runs on the host: compare with the oracle's own
+    continued fraction on random coefficients, and check the empty fraction."""
+    import numpy as np
+    import oracle.greens as og
+    import paper_1307_7542_amd as hub
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=40)
+    b = np.concatenate([[0.0], rng.uniform(0.2, 1.5, size=39)])
+    w = rng.normal(size=16) + 1j * rng.uniform(0.05, 2.0, size=16)
+    got = hub.continued_fraction(a, b, 40, 0.8, w)
+    ref = og.continued_fraction(a, b[1:], 0.8, w)
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=0)
+    assert np.all(hub.continued_fraction(a, b, 0, 0.8, w) == 0)
