@@ -138,6 +138,22 @@ def greens_timing(hub, torch, model, steps=150):
     return out
 
 
+def k0_timing(hub, torch, model):
+    """The same ring in its k = 0 translation block (Sec. VI): FP64 solve time and
+    product time beside the full sector."""
+    sec = hub.Sector(model, translation=1)
+    g = sec.ground_state(dtype=hub.F64, tol=1e-12, want_vector=False, max_iter=600)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = sec.ground_state(dtype=hub.F64, tol=1e-12, want_vector=False, max_iter=600, time_kernels=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"dim_k0": sec.dim, "e0_k0": g.e0, "iters": g.info["iters"], "solve_s": dt,
+           "product_ms": g.info["matvec_ms"] / max(1, g.info["matvec_count"])}
+    sec.close()
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -306,6 +322,7 @@ def main():
         out["products_square4x4"] = product_timing(hub, torch, W.config("square4x4"))
         out["aim_batch64"] = batch_timing(hub, torch)
         out["greens_ring14_u4"] = greens_timing(hub, torch, models[4])
+        out["k0_ring14_u4"] = k0_timing(hub, torch, models[4])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(models[4], args.cpu_seconds)
     print(json.dumps(out), flush=True)

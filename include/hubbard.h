@@ -269,6 +269,30 @@ hub_status hub_batch_ground_state(hub_batch *batch, const hub_lanczos_opts *opts
                                   void *dev_psi, void *stream, hub_batch_info *info);
 
 /*
+ * Translation symmetry, k = 0 (Sec. VI).  For a lattice invariant under the
+ * cyclic relabelling site i -> i - shift (mod M) (every bond maps to a bond
+ * with the same t; U and eps uniform; shift divides M; M / shift <= 32), the
+ * sector's k = 0 block.  Translation T lowers every bit position of an
+ * occupation integer by `shift`; with shift = 1 this is the convention of
+ * Tables V and VI (representative = smallest integer of its cycle, 1001 one
+ * translation from 0011).  Vectors of such a sector are laid out as
+ * phi[i + b R] = sqrt(P_i) psi(R_i, b): R_i the up-spin representatives in
+ * ascending order (hub_k0_layout), P_i their periods, b every down-spin basis
+ * state in Algorithm I order, psi the full two-spin amplitude of the k = 0
+ * state.  Euclidean products of phi equal the full-space ones.  The sector
+ * then works with hub_sector_dims (dim = R * count_dn), hub_start_vector
+ * (projected onto k = 0), hub_matvec and hub_ground_state; hub_diagonal,
+ * hub_param_bilinear, batches and the Green's-function calls return
+ * UNSUPPORTED.  INVALID_ARG if the model is not translation invariant.
+ */
+hub_status hub_sector_create_k0(const hub_model *model, int32_t n_up, int32_t n_dn, int32_t shift, hub_sector **out);
+
+/* *n_reps = R; reps[R] (may be NULL) the up representatives (ascending),
+ * periods[R] (may be NULL) their periods in units of the translation.
+ * INVALID_ARG for a sector made without translation symmetry. */
+hub_status hub_k0_layout(const hub_sector *sec, int64_t *n_reps, uint64_t *reps, int32_t *periods);
+
+/*
  * Zero-temperature one-particle Green's function (Sec. VII A, the second
  * equation labelled count8):
  *   G_s(p, z) = <psi0| c_ps (z + E0 - H)^-1 c+_ps |psi0> + <psi0| c+_ps (z - E0 + H)^-1 c_ps |psi0>

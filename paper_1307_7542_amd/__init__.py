@@ -28,7 +28,7 @@ EXPORTED = [
     "hub_matvec", "hub_ground_state", "hub_param_bilinear", "hub_matvec_bytes", "hub_status_str",
     "hub_last_error", "hub_version", "hub_batch_create", "hub_batch_destroy", "hub_batch_offsets",
     "hub_batch_matvec", "hub_batch_ground_state", "hub_apply_fermion", "hub_lanczos_coefficients",
-    "hub_continued_fraction", "hub_greens_function",
+    "hub_continued_fraction", "hub_greens_function", "hub_sector_create_k0", "hub_k0_layout",
 ]
 
 
@@ -103,6 +103,8 @@ def lib():
             "hub_lanczos_coefficients": (i32, [P, P, i32, P, P, P, P, P]),
             "hub_continued_fraction": (i32, [P, P, i32, ctypes.c_double, i32, P, P, P, P]),
             "hub_greens_function": (i32, [P, ctypes.c_double, P, i32, i32, i32, i32, P, P, P, P, P, P, P]),
+            "hub_sector_create_k0": (i32, [P, i32, i32, i32, P]),
+            "hub_k0_layout": (i32, [P, P, P, P]),
             "hub_status_str": (ctypes.c_char_p, [i32]),
             "hub_last_error": (ctypes.c_char_p, []),
             "hub_version": (ctypes.c_char_p, []),
@@ -158,7 +160,8 @@ class Sector:
     `model` is any object with attributes n_sites, bonds [(i, j)], t, U (per
     site) and eps (per site), plus n_up / n_dn unless given here."""
 
-    def __init__(self, model, n_up: Optional[int] = None, n_dn: Optional[int] = None):
+    def __init__(self, model, n_up: Optional[int] = None, n_dn: Optional[int] = None, translation: int = 0):
+        """translation = w > 0: the k = 0 block under the relabelling i -> i - w (mod M)."""
         L = lib()
         M = int(model.n_sites)
         self.n_up = int(model.n_up if n_up is None else n_up)
@@ -172,7 +175,12 @@ class Sector:
                    _ptr(self._bj) if len(self._bj) else None, _ptr(self._t) if len(self._t) else None,
                    _ptr(self._U), _ptr(self._eps))
         h = ctypes.c_void_p()
-        _check(L.hub_sector_create(ctypes.byref(m), self.n_up, self.n_dn, ctypes.byref(h)), "hub_sector_create")
+        if translation:
+            _check(L.hub_sector_create_k0(ctypes.byref(m), self.n_up, self.n_dn, int(translation), ctypes.byref(h)),
+                   "hub_sector_create_k0")
+        else:
+            _check(L.hub_sector_create(ctypes.byref(m), self.n_up, self.n_dn, ctypes.byref(h)), "hub_sector_create")
+        self.translation = int(translation)
         self._h = h
         self.M = M
         cu, cd, dim = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -282,6 +290,15 @@ class Sector:
                                       _dev_ptr(psi, F64, self.dim, "psi") if want else None,
                                       _stream(stream), ctypes.byref(info)), "hub_ground_state", allow)
         return GroundState(e0.value, psi if want else None, info.as_dict())
+
+    def k0_layout(self):
+        """(reps, periods) of a translation sector: rows of its vectors."""
+        n = ctypes.c_int64()
+        _check(lib().hub_k0_layout(self._h, ctypes.byref(n), None, None), "hub_k0_layout")
+        reps = np.zeros(n.value, dtype=np.uint64)
+        per = np.zeros(n.value, dtype=np.int32)
+        _check(lib().hub_k0_layout(self._h, ctypes.byref(n), _ptr(reps), _ptr(per)), "hub_k0_layout")
+        return reps, per
 
     # ------------------------------------------------ Green's function
     def apply_fermion(self, dst: "Sector", site: int, spin: int, create: bool, x, y=None, stream=None):

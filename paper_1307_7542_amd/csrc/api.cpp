@@ -36,6 +36,7 @@ void free_sector(hub_sector *s)
     if (!s) return;
     for (void *p : s->owned) (void)hipFree(p);
     s->owned.clear();
+    delete s->k0;
     delete s;
 }
 
@@ -301,6 +302,7 @@ hub_status hub_diagonal(const hub_sector *sec, int32_t dtype, void *dev_out, voi
     HUB_TRY(check_sector(sec));
     HUB_TRY(check_dtype(dtype));
     if (!dev_out) return fail(HUB_ERR_INVALID_ARG, "dev_out is NULL");
+    if (sec->k0) return fail(HUB_ERR_UNSUPPORTED, "not available for a translation (k = 0) sector");
     return launch_diagonal(sec, dtype, dev_out, (hipStream_t)stream);
 }
 
@@ -312,6 +314,7 @@ hub_status hub_start_vector(const hub_sector *sec, int32_t dtype, uint64_t seed,
     if (!dev_out) return fail(HUB_ERR_INVALID_ARG, "dev_out is NULL");
     hipStream_t st = (hipStream_t)stream;
     HUB_TRY(launch_start_vector(HUB_F64 == dtype ? HUB_F64 : HUB_F32, seed, dev_out, sec->dim, st));
+    HUB_TRY(k0_project(sec, dtype, dev_out, st));
     if (normalize) {
         double *tmp = nullptr;
         const size_t nb = sizeof(double) * (kRedGrid + 4);
@@ -333,7 +336,7 @@ hub_status hub_matvec(const hub_sector *sec, int32_t dtype, const void *dev_x, v
     const size_t bytes = (size_t)sec->dim * (dtype == HUB_F64 ? 8 : 4);
     const char *x = (const char *)dev_x, *y = (const char *)dev_y;
     if (x < y + bytes && y < x + bytes) return fail(HUB_ERR_INVALID_ARG, "x and y overlap");
-    return launch_matvec(sec, dtype, dev_x, dev_y, (hipStream_t)stream);
+    return apply_h(sec, dtype, dev_x, dev_y, (hipStream_t)stream);
 }
 
 hub_status hub_matvec_bytes(const hub_sector *sec, int32_t dtype, int64_t *bytes)
@@ -362,6 +365,7 @@ hub_status hub_param_bilinear(const hub_sector *sec, const void *dev_g, const vo
 {
     HUB_TRY(check_sector(sec));
     if (!dev_g || !dev_x) return fail(HUB_ERR_INVALID_ARG, "NULL vector");
+    if (sec->k0) return fail(HUB_ERR_UNSUPPORTED, "not available for a translation (k = 0) sector");
     return param_bilinear(sec, (const double *)dev_g, (const double *)dev_x, dbond, dU, deps, (hipStream_t)stream);
 }
 

@@ -809,6 +809,7 @@ hub_status hub_batch_create(const hub_sector *const *sectors, int32_t count, hub
         if (!s) return bfail(HUB_ERR_INVALID_ARG, "NULL sector in batch");
         if (p > 0 && s->device != sectors[0]->device) return bfail(HUB_ERR_INVALID_ARG, "sectors on different devices");
         if (!s->spin[0].ell_c32) return bfail(HUB_ERR_UNSUPPORTED, "sector without compact product tables");
+        if (s->k0) return bfail(HUB_ERR_UNSUPPORTED, "translation (k = 0) sectors cannot be batched");
         b->secs.push_back(s);
         b->off[p + 1] = b->off[p] + s->dim;
         b->max_cu = std::max(b->max_cu, (int)s->spin[0].count);

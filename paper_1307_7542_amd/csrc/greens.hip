@@ -120,6 +120,7 @@ std::complex<double> cfrac(const double *a, const double *b, int m, double norm2
 hub_status check_pair(const hub_sector *src, const hub_sector *dst, int spin, int create)
 {
     if (src->M != dst->M) return gfail(HUB_ERR_INVALID_ARG, "sectors of different lattices");
+    if (src->k0 || dst->k0) return gfail(HUB_ERR_UNSUPPORTED, "not available for translation (k = 0) sectors");
     const int d = create ? 1 : -1;
     const int other = 1 - spin;
     if (dst->spin[spin].N != src->spin[spin].N + d || dst->spin[other].N != src->spin[other].N)
@@ -228,6 +229,7 @@ hub_status hub_greens_function(const hub_sector *sec, double e0, const void *dev
 {
     const auto t0 = std::chrono::steady_clock::now();
     if (!sec || !dev_psi) return gfail(HUB_ERR_INVALID_ARG, "NULL argument");
+    if (sec->k0) return gfail(HUB_ERR_UNSUPPORTED, "not available for a translation (k = 0) sector");
     if (spin != 0 && spin != 1) return gfail(HUB_ERR_INVALID_ARG, "spin must be 0 (up) or 1 (down)");
     if (site < 0 || site >= sec->M) return gfail(HUB_ERR_INVALID_ARG, "site out of range");
     if (max_steps < 1) return gfail(HUB_ERR_INVALID_ARG, "max_steps must be positive");

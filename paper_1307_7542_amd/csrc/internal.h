@@ -58,6 +58,34 @@ struct SpinTables {
     uint32_t *ch_ell[2] = {nullptr, nullptr};
 };
 
+// Translation symmetry, k = 0 (Sec. VI), in the layout phi[i + b R] =
+// sqrt(P_i) psi(R_i, b): rows are the up representatives R_i (ascending), columns
+// every down state b (basis order).  G lowers every bit position by `w`.
+struct K0Tables {
+    int w = 1;                  // translation step in sites
+    int L = 0;                  // group order M / w
+    int64_t R = 0;              // up representatives
+    int max_q = 0;              // longest down cycle
+    int64_t n_orb = 0;          // down cycles
+    uint32_t *reps = nullptr;   // [R] up representatives
+    int32_t *period = nullptr;  // [R] period P_i (in steps of G)
+    double *rep_e64 = nullptr;  // [R] sum_i eps_i n_i of R_i
+    float *rep_e32 = nullptr;
+    int32_t *hop_rp = nullptr;  // [R + 1] up hops from each representative
+    int32_t *hop_row = nullptr; // [nnz] row of the hopped state's representative
+    int32_t *hop_s = nullptr;   // [nnz] translation of the hopped state w.r.t. it
+    double *hop_c64 = nullptr;  // [nnz] -t esign * phase * sqrt(P_i / P_i')
+    float *hop_c32 = nullptr;
+    int64_t hop_nnz = 0;
+    int32_t *orb_off = nullptr;   // [n_orb + 1] start of each down cycle in orb_cols
+    int32_t *orb_cols = nullptr;  // [count_dn] member a of cycle j -> down basis index
+    int32_t *orb_sign = nullptr;  // [count_dn] c_a with G^a |D_j> = c_a |member a>
+    int32_t *orb_sigma = nullptr; // [n_orb] G^q |D_j> = sigma |D_j>
+    int64_t n_short = 0;          // representatives with P_i < L
+    int32_t *short_rows = nullptr;   // [n_short]
+    int32_t *short_sigma = nullptr;  // [n_short] G^P_i |R_i> = sigma |R_i>
+};
+
 }  // namespace hub
 
 struct hub_sector {
@@ -84,12 +112,15 @@ struct hub_sector {
     bool force_chunked = false;       // use the row-chunked product even when a column fits
     int cu_count = 256;
     std::vector<void *> owned;        // every device allocation, freed by destroy
+    hub::K0Tables *k0 = nullptr;      // set for a translation-symmetric k = 0 sector
 };
 
 namespace hub {
 
 // ---- setup (setup.hip) -------------------------------------------------
 hub_status build_spin_tables(hub_sector *s, int spin, int N, hipStream_t st);
+// rp[0] = 0, rp[k + 1] = len[0] + ... + len[k] (temporaries owned by s)
+hub_status scan_lengths(hub_sector *s, const int32_t *len, int64_t n, int32_t *rp, hipStream_t st);
 hub_status build_chunked_tables(hub_sector *s, int spin, int dtype, int chunk_rows, hipStream_t st);
 hub_status rank_device(const hub_sector *s, int spin, const uint64_t *dx, int64_t n, int64_t *dout,
                        hipStream_t st);
@@ -131,6 +162,12 @@ hub_status launch_residual(const double *hpsi, const double *psi, const double *
 // ---- adjoint (adjoint.hip) ---------------------------------------------
 hub_status param_bilinear(const hub_sector *s, const double *g, const double *x, double *dbond, double *dU,
                           double *deps, hipStream_t st);
+
+// ---- translation symmetry (translation.hip) ------------------------------
+// H x for any sector: the k = 0 product for translation sectors, else launch_matvec.
+hub_status apply_h(const hub_sector *s, int dtype, const void *x, void *y, hipStream_t st);
+// Project a vector of a k = 0 sector onto its consistent subspace (identity otherwise).
+hub_status k0_project(const hub_sector *s, int dtype, void *x, hipStream_t st);
 
 // ---- Lanczos (lanczos.cpp) ---------------------------------------------
 double tri_lowest(const double *a, const double *b, int m, std::vector<double> &y);

@@ -184,6 +184,10 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     const int check_every = o->check_every > 0 ? o->check_every : 1;
     const bool reorth = o->reorth != 0;
     const bool want_vec = o->want_vector != 0 || o->refine != 0;
+    // k = 0 sectors with short-period rows: the vectors live in the consistent
+    // subspace; rounding noise outside it is removed from every new vector (the
+    // discarded directions carry eigenvalue 0, which may lie below the k = 0 block)
+    const bool reproject = s->k0 && s->k0->n_short > 0;
 
     hub_lanczos_info inf;
     std::memset(&inf, 0, sizeof(inf));
@@ -234,6 +238,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             HUB_TRY(launch_convert(HUB_F64, o->dev_start, dt, v, n, d_misc, 1, st));
         } else {
             HUB_TRY(launch_start_vector(dt, o->seed, W, n, st));
+            HUB_TRY(k0_project(s, dt, W, st));
             HUB_TRY(launch_dot(dt, W, W, n, partial, d_misc, 1, st));
             HUB_TRY(launch_convert(dt, W, dt, v, n, d_misc, 1, st));
         }
@@ -241,7 +246,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     };
     auto product = [&](const void *x, void *y) -> hub_status {
         HUB_TRY(tm.mark());
-        HUB_TRY(launch_matvec(s, dt, x, y, st));
+        HUB_TRY(apply_h(s, dt, x, y, st));
         HUB_TRY(tm.mark());
         inf.matvec_count++;
         return HUB_OK;
@@ -269,9 +274,14 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             HUB_TRY(launch_dot(dt, W, W, n, partial, d_misc + 9, 1, st));
             HUB_TRY(launch_dgks_flag(d_misc + 8, d_misc + 9, d_flag, st));
             HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, d_flag));
+            if (reproject) HUB_TRY(k0_project(s, dt, W, st));
             HUB_TRY(launch_dot(dt, W, W, n, partial, d_beta + k + 1, 1, st));
         } else {
             HUB_TRY(launch_lz_b(dt, W, v, d_alpha + k, n, partial, d_beta + k + 1, st));
+            if (reproject) {
+                HUB_TRY(k0_project(s, dt, W, st));
+                HUB_TRY(launch_dot(dt, W, W, n, partial, d_beta + k + 1, 1, st));
+            }
         }
         const bool last = (k + 1 == max_iter);
         if ((k + 1) % check_every == 0 || last) {
@@ -341,6 +351,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             for (int j = 0; j + 1 < m; ++j) {
                 HUB_TRY(product(vc, W));
                 HUB_TRY(launch_lz_replay(dt, W, vp, d_beta + j, vc, d_alpha + j, n, st));
+                if (reproject) HUB_TRY(k0_project(s, dt, W, st));
                 void *vn = vp ? vp : sp;
                 HUB_TRY(launch_lz_next(dt, W, vn, d_beta + j + 1, n, st));
                 vp = vc;
@@ -356,7 +367,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             } else {
                 HUB_TRY(mem.alloc((void **)&hpsi, sizeof(double) * (size_t)n));
             }
-            HUB_TRY(launch_matvec(s, HUB_F64, psi, hpsi, st));
+            HUB_TRY(apply_h(s, HUB_F64, psi, hpsi, st));
             HUB_TRY(launch_dot(HUB_F64, psi, hpsi, n, partial, d_misc + 4, 0, st));
             HUB_TRY(launch_residual(hpsi, psi, d_misc + 4, n, partial, d_misc + 5, st));
             double h2[2];
@@ -415,7 +426,7 @@ hub_status lanczos_coefficients(const hub_sector *s, const double *f, int max_st
     int m = kmax;
     double tmax = 0.0;
     for (int k = 0; k < kmax; ++k) {
-        HUB_TRY(launch_matvec(s, HUB_F64, v, W, st));
+        HUB_TRY(apply_h(s, HUB_F64, v, W, st));
         HUB_TRY(launch_lz_a(HUB_F64, W, v_prev, d_beta + k, v, n, partial, d_alpha + k, st));
         HUB_TRY(launch_lz_b(HUB_F64, W, v, d_alpha + k, n, partial, d_beta + k + 1, st));
         const bool last = (k + 1 == kmax);

@@ -318,6 +318,19 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 
 }  // namespace
 
+hub_status scan_lengths(hub_sector *s, const int32_t *len, int64_t n, int32_t *rp, hipStream_t st)
+{
+    const int64_t nblk = (n + kScanBlock - 1) / kScanBlock;
+    int64_t *tmp = nullptr, *bsum = nullptr;
+    HUB_TRY(dalloc(s, &tmp, n));
+    HUB_TRY(dalloc(s, &bsum, nblk));
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, len, n, tmp, bsum);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, bsum, nblk);
+    hipLaunchKernelGGL(k_scan_finish, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, len, tmp, bsum, n, rp);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
 hub_status build_spin_tables(hub_sector *s, int spin, int N, hipStream_t st)
 {
     SpinTables &T = s->spin[spin];
