@@ -86,6 +86,12 @@ struct K0Tables {
     int32_t *short_sigma = nullptr;  // [n_short] G^P_i |R_i> = sigma |R_i>
 };
 
+// Tuned shape of the four-rows-per-lane product (0 = not tuned yet).
+struct QuadShape {
+    int tb = 0, bs = 0, xc = 0;
+    float ms = 0.f;
+};
+
 }  // namespace hub
 
 struct hub_sector {
@@ -113,6 +119,7 @@ struct hub_sector {
     int cu_count = 256;
     std::vector<void *> owned;        // every device allocation, freed by destroy
     hub::K0Tables *k0 = nullptr;      // set for a translation-symmetric k = 0 sector
+    mutable hub::QuadShape quad[2];   // per dtype (0: FP64, 1: FP32), set by the first product
 };
 
 namespace hub {

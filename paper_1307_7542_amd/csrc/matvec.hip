@@ -26,6 +26,7 @@
 // H_up is read from its sliced-ELL copy: lane r of a wavefront owns row
 // 64*s + r of slice s and loads entry k, packed {column, value}, from a
 // coalesced address.
+#include <algorithm>
 #include <cstdlib>
 #include <type_traits>
 
@@ -178,6 +179,159 @@ __device__ __forceinline__ void stage_columns(const MvArgs<T> &A, T *xs, int b0,
         const int b = b0 + t;
         const T *__restrict__ xb = A.x + (int64_t)min(b, A.cd - 1) * A.cu;
         for (int a = threadIdx.x; a < A.cu; a += bs) xs[a * TB + t] = (b < A.cd) ? xb[a] : (T)0;
+    }
+}
+
+// ---- fused, four consecutive rows per lane ------------------------------
+// Same schedule and per-element arithmetic order as k_kron_fused, but lane q
+// owns rows 4q .. 4q+3 (count_up % 4 == 0): the column staging, the H_dn
+// neighbour reads and the stores become 16-byte (FP32) or 2 x 16-byte (FP64)
+// accesses, and the four rows' sliced-ELL entries k are four consecutive
+// lanes of the slice, read with one 16-byte load.  XC: XCD-contiguous tile
+// order (workgroup i on XCD i mod 8 takes the i-th tile of that XCD's range)
+// or plain launch order.
+template <typename T>
+struct Q4 {
+    T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ Q4<T> ld_q4(const T *p)
+{
+    Q4<T> r;
+    if constexpr (sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        r.v[0] = q.x;
+        r.v[1] = q.y;
+        r.v[2] = q.z;
+        r.v[3] = q.w;
+    } else {
+        const double2 q0 = reinterpret_cast<const double2 *>(p)[0], q1 = reinterpret_cast<const double2 *>(p)[1];
+        r.v[0] = q0.x;
+        r.v[1] = q0.y;
+        r.v[2] = q1.x;
+        r.v[3] = q1.y;
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void st_q4(T *p, const T (&v)[4])
+{
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+        reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+    }
+}
+
+template <typename T, int TB, int BS, bool XC>
+__global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__restrict__ sl_off,
+                                                  const uint32_t *__restrict__ ellc, const T *__restrict__ code_v,
+                                                  int ntiles)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *tab = reinterpret_cast<T *>(smem_raw);  // 256 code values
+    T *xs = tab + 256;                         // TB staged columns, interleaved
+    int tile;
+    if (XC) {
+        tile = xcd_tile(ntiles);
+    } else {
+        tile = (int)blockIdx.x < ntiles ? (int)blockIdx.x : -1;
+    }
+    if (tile < 0) return;
+    const int cu = A.cu, cd = A.cd, nq = cu >> 2;
+    const int b0 = tile * TB;
+    for (int i = threadIdx.x; i < 256; i += BS) tab[i] = code_v[i];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+        const T *__restrict__ xb = A.x + (int64_t)min(b0 + t, cd - 1) * cu;
+        for (int q = threadIdx.x; q < nq; q += BS) {
+            const Q4<T> v = ld_q4(xb + 4 * q);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xs[(4 * q + r) * TB + t] = v.v[r];
+        }
+    }
+    __syncthreads();
+    int ds[TB], de[TB];
+    uint32_t dnb[TB];
+    T edn[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+        const int b = min(b0 + t, cd - 1);
+        ds[t] = A.dn_rp[b];
+        de[t] = (b0 + t < cd) ? A.dn_rp[b + 1] : ds[t];
+        dnb[t] = A.dn_basis[b];
+        edn[t] = A.e_dn[b];
+    }
+    const int64_t cu64 = cu;
+    for (int q = threadIdx.x; q < nq; q += BS) {
+        const int a0 = 4 * q;
+        T acc[4][TB];
+        const uint4 ub = *reinterpret_cast<const uint4 *>(A.up_basis + a0);
+        const uint32_t uu[4] = {ub.x, ub.y, ub.z, ub.w};
+        const Q4<T> eu = ld_q4(A.e_up + a0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int t = 0; t < TB; ++t)
+                acc[r][t] = (diag_u(A, uu[r] & dnb[t]) + eu.v[r] + edn[t]) * xs[(a0 + r) * TB + t];
+        // H_up term: entries k of rows a0 .. a0+3 are lanes (a0 & 63) .. +3 of slice a0 >> 6
+        const int s = a0 >> 6;
+        const uint4 *__restrict__ e4 = reinterpret_cast<const uint4 *>(ellc + (int64_t)sl_off[s] * 64 + (a0 & 63));
+        const int len = sl_off[s + 1] - sl_off[s];
+        int k = 0;
+        for (; k + 2 <= len; k += 2) {
+            const uint4 ea = e4[16 * k], eb = e4[16 * (k + 1)];
+            const uint32_t e[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const T v = tab[e[i] >> 24];
+                const T *xr = xs + (e[i] & 0xFFFFFFu) * TB;
+#pragma unroll
+                for (int t = 0; t < TB; ++t) acc[i & 3][t] += v * xr[t];
+            }
+        }
+        if (k < len) {
+            const uint4 ea = e4[16 * k];
+            const uint32_t e[4] = {ea.x, ea.y, ea.z, ea.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const T v = tab[e[i] >> 24];
+                const T *xr = xs + (e[i] & 0xFFFFFFu) * TB;
+#pragma unroll
+                for (int t = 0; t < TB; ++t) acc[i][t] += v * xr[t];
+            }
+        }
+        // H_dn term: whole neighbour columns, four rows per load
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            int kk = ds[t];
+            for (; kk + 4 <= de[t]; kk += 4) {
+                Q4<T> v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const T w = A.dn_val[kk + u];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[r][t] += w * v[u].v[r];
+                }
+            }
+            for (; kk < de[t]; ++kk) {
+                const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
+                const T w = A.dn_val[kk];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r][t] += w * v.v[r];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            if (b0 + t >= cd) continue;
+            const T o[4] = {acc[0][t], acc[1][t], acc[2][t], acc[3][t]};
+            st_q4(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
+        }
     }
 }
 
@@ -608,24 +762,102 @@ hub_status launch_two_pass(const hub_sector *s, const MvArgs<T> &A, hipStream_t 
     return HUB_OK;
 }
 
+template <typename T, int TB, int BS, bool XC>
+hub_status launch_quad_t(const hub_sector *s, const MvArgs<T> &A, hipStream_t st)
+{
+    const SpinTables &U = s->spin[0];
+    const int ntiles = (A.cd + TB - 1) / TB;
+    const unsigned grid = XC ? 8u * (unsigned)((ntiles + 7) / 8) : (unsigned)ntiles;
+    const size_t lds = (size_t)(A.cu * TB + 256) * sizeof(T);
+    static bool attr = false;
+    if (!attr) {
+        HUB_TRY(allow_lds(k_kron_quad<T, TB, BS, XC>, s->lds_max));
+        attr = true;
+    }
+    const T *cv;
+    if constexpr (sizeof(T) == 8) cv = (const T *)U.code_v64;
+    else cv = (const T *)U.code_v32;
+    hipLaunchKernelGGL((k_kron_quad<T, TB, BS, XC>), dim3(grid), dim3(BS), lds, st, A, U.sl_off, U.ell_c32, cv, ntiles);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+// shape code: TB in 1..3, BS in {512, 1024}, XC in {0, 1}
+template <typename T>
+hub_status launch_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, int bs, int xc)
+{
+#define HUB_QUAD(TBV, BSV, XCV)                                                                       \
+    if (tb == TBV && bs == BSV && xc == XCV) return launch_quad_t<T, TBV, BSV, XCV>(s, A, st);
+    HUB_QUAD(1, 512, 0) HUB_QUAD(1, 512, 1) HUB_QUAD(1, 1024, 0) HUB_QUAD(1, 1024, 1)
+    HUB_QUAD(2, 512, 0) HUB_QUAD(2, 512, 1) HUB_QUAD(2, 1024, 0) HUB_QUAD(2, 1024, 1)
+    HUB_QUAD(3, 512, 0) HUB_QUAD(3, 512, 1) HUB_QUAD(3, 1024, 0) HUB_QUAD(3, 1024, 1)
+#undef HUB_QUAD
+    set_error("untuned product shape");
+    return HUB_ERR_UNSUPPORTED;
+}
+
+// First product of a dtype on a sector: time every shape whose columns fit in
+// the LDS (1 warm-up + 3 timed launches on the caller's x and y; every shape
+// computes the same values in the same order) and keep the fastest.
+template <typename T>
+hub_status tune_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, QuadShape &out)
+{
+    hipEvent_t e0, e1;
+    HUB_HIP(hipEventCreate(&e0));
+    HUB_HIP(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } ev{e0, e1};
+    float best = 1e30f;
+    QuadShape pick;
+    for (int tb = 1; tb <= 3; ++tb) {
+        if ((size_t)(A.cu * tb + 256) * sizeof(T) > s->lds_max) break;
+        for (int bs : {512, 1024})
+            for (int xc : {0, 1}) {
+                HUB_TRY(launch_quad<T>(s, A, st, tb, bs, xc));
+                HUB_HIP(hipEventRecord(e0, st));
+                for (int r = 0; r < 3; ++r) HUB_TRY(launch_quad<T>(s, A, st, tb, bs, xc));
+                HUB_HIP(hipEventRecord(e1, st));
+                HUB_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HUB_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    pick.tb = tb;
+                    pick.bs = bs;
+                    pick.xc = xc;
+                }
+            }
+    }
+    pick.ms = best / 3.0f;
+    out = pick;
+    return HUB_OK;
+}
+
 // Schedule selection.  Environment overrides for measurement: HUB_MATVEC_IMPL
 // (1 csr, 2 fused, 3 two-pass), HUB_MATVEC_TB, HUB_MATVEC_BS (512 / 1024),
+// HUB_MATVEC_XC (tile order), HUB_MATVEC_QUAD (0: one row per lane),
 // HUB_FUSED_R, HUB_ELL_FMT (0 packed, 1 compact), HUB_DN_OCC, HUB_DN_NT.
-// Default (measured on the ring M=14 and the 4x4 torus): fused, compact
-// entries, 1024-thread workgroups, two columns per workgroup when they fit in
-// half of the LDS, otherwise one.
+// Default: the four-rows-per-lane fused kernel when count_up % 4 == 0 (shape
+// tuned on the first product of each dtype), else the one-row fused kernel
+// with two columns per workgroup when they fit in half of the LDS; the
+// row-chunked kernel when a column does not fit in the LDS.
 template <typename T>
 hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
 {
     MvArgs<T> A = make_args<T>(s, x, y);
     const size_t col_bytes = (size_t)A.cu * sizeof(T);
     static const int impl = env_int("HUB_MATVEC_IMPL", 2);
-    static const int tb_env = env_int("HUB_MATVEC_TB", 0);
-    static const int bs_env = env_int("HUB_MATVEC_BS", 0);
+    // read on every call so a shape can be forced for measurement or tests
+    const int tb_env = env_int("HUB_MATVEC_TB", 0);
+    const int bs_env = env_int("HUB_MATVEC_BS", 0);
     static const int occ = env_int("HUB_DN_OCC", 4);
     static const int nt = env_int("HUB_DN_NT", 1);
     static const int rows = env_int("HUB_FUSED_R", 4);
     static const bool cf = env_int("HUB_ELL_FMT", 1) != 0;
+    const bool quad = env_int("HUB_MATVEC_QUAD", 1) != 0;
+    const int xc_env = env_int("HUB_MATVEC_XC", 1) != 0 ? 1 : 0;
     const size_t extra = 256 * sizeof(T);
     const size_t half = s->lds_max / 2;
     int tb = tb_env;
@@ -656,6 +888,15 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
                            U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di], (int)U.nslices);
         HUB_HIP(hipGetLastError());
         return HUB_OK;
+    }
+    if (impl == 2 && fits && cf && U.ell_c32 && (A.cu % 4) == 0 && quad) {
+        QuadShape &q = s->quad[di];
+        if (tb_env > 0 || bs_env > 0) {
+            const int t2 = std::min(std::max(tb_env > 0 ? tb_env : 1, 1), 3);
+            return launch_quad<T>(s, A, st, t2, bs_env == 512 ? 512 : 1024, xc_env);
+        }
+        if (q.tb == 0) HUB_TRY(tune_quad<T>(s, A, st, q));
+        return launch_quad<T>(s, A, st, q.tb, q.bs, q.xc);
     }
     if (impl == 2 && fits) {
         if (tb >= 4) return big ? launch_fused<T, 4, 1024, 1>(s, A, st, cf) : launch_fused<T, 4, 512, 1>(s, A, st, cf);

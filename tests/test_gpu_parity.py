@@ -460,3 +460,48 @@ def test_matvec_row_chunked_parity(hub, chunk, monkeypatch):
         if e_ref is not None:
             assert abs(gs.e0 - e_ref) <= 1e-10 * abs(e_ref)
         s.close()
+
+
+@pytest.mark.parametrize("which", ["ring10", "square3x4_n5", "ring12_u3"])
+def test_quad_product_shapes_bitwise(hub, which, monkeypatch):
+    """The four-rows-per-lane product (count_up % 4 == 0) gives bit-identical
+    results for every tile shape the tuner may pick (columns per workgroup,
+    workgroup size, tile order), matches the oracle, and agrees with the
+    one-row-per-lane kernel to rounding."""
+    import torch
+    if which == "ring10":
+        m = W.ring(10, U=3.0, n_up=5, n_dn=4).with_params(eps=[0.1 * i for i in range(10)])
+    elif which == "square3x4_n5":
+        m = W.square_periodic(3, 4, n_up=5, n_dn=5)
+    else:
+        m = W.ring(12, U=3.0, n_up=6, n_dn=6)
+    s = hub.Sector(m)
+    assert s.count_up % 4 == 0
+    osec = oracle.Sector(m)
+    xr = oracle.start_vector(31, osec.dim)
+    yr = oracle.spmv(osec.csr(), xr)
+    bound = _row_abs(osec, xr)
+    for dt, tol in ((hub.F64, 1e-13), (hub.F32, 1e-5)):
+        x = torch.from_numpy(xr).cuda()
+        if dt == hub.F32:
+            x = x.float()
+            ref = oracle.spmv(osec.csr(), x.cpu().numpy().astype(np.float64))
+        else:
+            ref = yr
+        y0 = s.matvec(x).cpu().numpy()
+        assert np.all(np.abs(y0.astype(np.float64) - ref) <= tol * bound + 1e-30)
+        for tb in (1, 2, 3):
+            for bs in (512, 1024):
+                for xc in (0, 1):
+                    monkeypatch.setenv("HUB_MATVEC_TB", str(tb))
+                    monkeypatch.setenv("HUB_MATVEC_BS", str(bs))
+                    monkeypatch.setenv("HUB_MATVEC_XC", str(xc))
+                    y = s.matvec(x).cpu().numpy()
+                    assert np.array_equal(y, y0), (which, dt, tb, bs, xc)
+        for k in ("HUB_MATVEC_TB", "HUB_MATVEC_BS", "HUB_MATVEC_XC"):
+            monkeypatch.delenv(k)
+        monkeypatch.setenv("HUB_MATVEC_QUAD", "0")
+        y1 = s.matvec(x).cpu().numpy()
+        monkeypatch.delenv("HUB_MATVEC_QUAD")
+        assert np.all(np.abs(y1.astype(np.float64) - y0.astype(np.float64)) <= 2 * tol * bound + 1e-30)
+    s.close()
