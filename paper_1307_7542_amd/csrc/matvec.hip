@@ -335,6 +335,98 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
     }
 }
 
+// Row-chunked product with four consecutive rows per lane (count_up and the
+// chunk length multiples of 4): the access pattern of k_kron_quad applied to
+// the phases of k_kron_chunked.
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_kron_chunked_quad(MvArgs<T> A, const int32_t *__restrict__ ch_off,
+                                                          const int64_t *__restrict__ ch_base,
+                                                          const uint32_t *__restrict__ ch_ell,
+                                                          const T *__restrict__ code_v, int nchunks, int chunk_rows,
+                                                          int nslices)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *tab = reinterpret_cast<T *>(smem_raw);
+    T *xs = tab + 256;
+    const int tile = xcd_tile(A.cd);
+    if (tile < 0) return;
+    const int cu = A.cu, nq = cu >> 2;
+    const int b = tile;
+    const int64_t cu64 = cu;
+    const T *__restrict__ xb = A.x + (int64_t)b * cu;
+    T *yb = A.y + (int64_t)b * cu;
+    for (int i = threadIdx.x; i < 256; i += BS) tab[i] = code_v[i];
+    const int ds = A.dn_rp[b], de = A.dn_rp[b + 1];
+    const uint32_t dnb = A.dn_basis[b];
+    const T edn = A.e_dn[b];
+    for (int p = 0; p < nchunks; ++p) {
+        const int q0 = (p * chunk_rows) >> 2;
+        const int q1 = min(nq, q0 + (chunk_rows >> 2));
+        __syncthreads();  // previous phase done with xs
+        for (int q = q0 + threadIdx.x; q < q1; q += BS) {
+            const Q4<T> v = ld_q4(xb + 4 * q);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) xs[4 * (q - q0) + r] = v.v[r];
+        }
+        __syncthreads();
+        const int32_t *off = ch_off + (int64_t)p * (nslices + 1);
+        const uint32_t *ell = ch_ell + ch_base[p];
+        for (int q = threadIdx.x; q < nq; q += BS) {
+            const int a0 = 4 * q;
+            T acc[4];
+            if (p == 0) {
+                const uint4 ub = *reinterpret_cast<const uint4 *>(A.up_basis + a0);
+                const uint32_t uu[4] = {ub.x, ub.y, ub.z, ub.w};
+                const Q4<T> eu = ld_q4(A.e_up + a0);
+                const Q4<T> xv = ld_q4(xb + a0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = (diag_u(A, uu[r] & dnb) + eu.v[r] + edn) * xv.v[r];
+            } else {
+                const Q4<T> yv = ld_q4(yb + a0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = yv.v[r];
+            }
+            const int s = a0 >> 6;
+            const uint4 *__restrict__ e4 = reinterpret_cast<const uint4 *>(ell + (int64_t)off[s] * 64 + (a0 & 63));
+            const int len = off[s + 1] - off[s];
+            int k = 0;
+            for (; k + 2 <= len; k += 2) {
+                const uint4 ea = e4[16 * k], eb = e4[16 * (k + 1)];
+                const uint32_t e[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+#pragma unroll
+                for (int i = 0; i < 8; ++i) acc[i & 3] += tab[e[i] >> 24] * xs[e[i] & 0xFFFFFFu];
+            }
+            if (k < len) {
+                const uint4 ea = e4[16 * k];
+                const uint32_t e[4] = {ea.x, ea.y, ea.z, ea.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i] += tab[e[i] >> 24] * xs[e[i] & 0xFFFFFFu];
+            }
+            if (p == 0) {
+                int kk = ds;
+                for (; kk + 4 <= de; kk += 4) {
+                    Q4<T> v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const T w = A.dn_val[kk + u];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[r] += w * v[u].v[r];
+                    }
+                }
+                for (; kk < de; ++kk) {
+                    const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
+                    const T w = A.dn_val[kk];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[r] += w * v.v[r];
+                }
+            }
+            st_q4(yb + a0, acc);
+        }
+    }
+}
+
 // ---- fused ------------------------------------------------------------
 // Each lane owns R rows (a, a + BS, ...) at once so the H_dn neighbour reads
 // of all R rows are in flight together.
@@ -884,8 +976,18 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
         if constexpr (sizeof(T) == 8) cv = (const T *)U.code_v64;
         else cv = (const T *)U.code_v32;
         const unsigned grid = 8u * (unsigned)((A.cd + 7) / 8);
-        hipLaunchKernelGGL((k_kron_chunked<T, BSC, 4>), dim3(grid), dim3(BSC), lds, st, A, U.ch_off[di],
-                           U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di], (int)U.nslices);
+        if (quad && (A.cu % 4) == 0 && (U.chunk_rows[di] % 4) == 0) {
+            static bool attrq = false;
+            if (!attrq) {
+                HUB_TRY(allow_lds(k_kron_chunked_quad<T, BSC>, s->lds_max));
+                attrq = true;
+            }
+            hipLaunchKernelGGL((k_kron_chunked_quad<T, BSC>), dim3(grid), dim3(BSC), lds, st, A, U.ch_off[di],
+                               U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di], (int)U.nslices);
+        } else {
+            hipLaunchKernelGGL((k_kron_chunked<T, BSC, 4>), dim3(grid), dim3(BSC), lds, st, A, U.ch_off[di],
+                               U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di], (int)U.nslices);
+        }
         HUB_HIP(hipGetLastError());
         return HUB_OK;
     }
