@@ -255,14 +255,63 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     HUB_TRY(make_start(Va));
     void *v_prev = nullptr, *v = Va, *spare = Vb;
 
-    std::vector<double> ha(kmax), hb(kmax + 1), y;
+    // Convergence checks run on the host while the GPU computes the next step:
+    // at a check step k, alpha_0..alpha_{k-1} and beta_1..beta_k are copied (one
+    // asynchronous copy into pinned memory) before step k is enqueued, and the
+    // host waits only for that copy.  A step finished after convergence is
+    // discarded (its coefficients are never used).
+    double *hpin = nullptr;  // pinned copy of dscal[0 .. 2 kmax + 1)
+    HUB_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * (size_t)(2 * kmax + 1)));
+    struct PinGuard {
+        double *p;
+        ~PinGuard() { (void)hipHostFree(p); }
+    } pin_guard{hpin};
+    const double *ha = hpin, *hb = hpin + kmax;
+    hipEvent_t copied;
+    HUB_HIP(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t e;
+        ~EvGuard() { (void)hipEventDestroy(e); }
+    } ev_guard{copied};
+    std::vector<double> y;
     int m_final = 0;
     double theta = 0.0, res = 0.0;
     bool converged = false, breakdown = false;
     double t_e0 = -1.0;
     double tmax = 0.0;
 
+    // m steps done: test the Ritz residual of T_m (host arrays ha, hb)
+    auto check = [&](int m) -> bool {
+        int mm = m;
+        for (int j = 0; j < m; ++j) {
+            tmax = std::max(tmax, std::fabs(ha[j]) + 2.0 * std::fabs(hb[j + 1]));
+            const double thr = 64.0 * ((dt == HUB_F64) ? DBL_EPSILON : FLT_EPSILON) * std::max(tmax, DBL_MIN);
+            if (!(hb[j + 1] > thr)) {
+                mm = j + 1;
+                breakdown = true;
+                break;
+            }
+        }
+        theta = tri_lowest(ha, hb + 1, mm, y);
+        res = std::fabs(hb[mm]) * std::fabs(y[mm - 1]);
+        const double scale = std::fabs(theta) > 0 ? std::fabs(theta) : 1.0;
+        m_final = mm;
+        if (breakdown || res <= tol * scale) {
+            converged = true;
+            if (breakdown) res = 0.0;
+            t_e0 = std::chrono::duration<double>(clk::now() - t0).count();
+            return true;
+        }
+        return false;
+    };
+    auto fetch = [&](int k) -> hub_status {  // alpha_0..alpha_{k-1}, beta_0..beta_k
+        HUB_HIP(hipMemcpyAsync(hpin, dscal, sizeof(double) * (size_t)(kmax + k + 1), hipMemcpyDeviceToHost, st));
+        HUB_HIP(hipEventRecord(copied, st));
+        return HUB_OK;
+    };
     for (int k = 0; k < max_iter; ++k) {
+        const bool check_now = k >= 1 && (k % check_every) == 0;
+        if (check_now) HUB_TRY(fetch(k));
         HUB_TRY(product(v, W));
         HUB_TRY(launch_lz_a(dt, W, v_prev, d_beta + k, v, n, partial, d_alpha + k, st));
         if (reorth) {
@@ -284,35 +333,16 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             }
         }
         const bool last = (k + 1 == max_iter);
-        if ((k + 1) % check_every == 0 || last) {
-            const int m = k + 1;
-            HUB_HIP(hipMemcpyAsync(ha.data(), d_alpha, sizeof(double) * m, hipMemcpyDeviceToHost, st));
-            HUB_HIP(hipMemcpyAsync(hb.data(), d_beta, sizeof(double) * (m + 1), hipMemcpyDeviceToHost, st));
-            HUB_HIP(hipStreamSynchronize(st));
-            // first breakdown (invariant subspace) within the new steps
-            int mm = m;
-            for (int j = 0; j < m; ++j) {
-                tmax = std::max(tmax, std::fabs(ha[j]) + 2.0 * std::fabs(hb[j + 1]));
-                const double thr = 64.0 * ((dt == HUB_F64) ? DBL_EPSILON : FLT_EPSILON) * std::max(tmax, DBL_MIN);
-                if (!(hb[j + 1] > thr)) {
-                    mm = j + 1;
-                    breakdown = true;
-                    break;
-                }
-            }
-            theta = tri_lowest(ha.data(), hb.data() + 1, mm, y);
-            res = std::fabs(hb[mm]) * std::fabs(y[mm - 1]);
-            const double scale = std::fabs(theta) > 0 ? std::fabs(theta) : 1.0;
-            if (breakdown || res <= tol * scale) {
-                converged = true;
-                m_final = mm;
-                if (breakdown) res = 0.0;
-                t_e0 = std::chrono::duration<double>(clk::now() - t0).count();
-                break;
-            }
-            m_final = m;
+        if (check_now) {
+            HUB_HIP(hipEventSynchronize(copied));  // step k keeps running meanwhile
+            if (check(k)) break;
         }
-        if (last) break;
+        if (last) {
+            HUB_TRY(fetch(k + 1));
+            HUB_HIP(hipEventSynchronize(copied));
+            check(k + 1);
+            break;
+        }
         // v_{k+1} = w / beta_{k+1}
         void *vn = nullptr;
         if (reorth) {

@@ -28,6 +28,9 @@
 // coalesced address.
 #include <algorithm>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "internal.h"
@@ -927,6 +930,21 @@ hub_status tune_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, Qu
     return HUB_OK;
 }
 
+// Tuned shapes are kept per device, dtype and sector structure (dimensions and
+// nonzeros; the values of t, U and eps do not change the timing), so sectors
+// of the same lattice share one tuning.
+struct ShapeKey {
+    int device, dtype;
+    int64_t cu, cd, nnz_up, nnz_dn;
+    bool operator<(const ShapeKey &o) const
+    {
+        return std::tie(device, dtype, cu, cd, nnz_up, nnz_dn) <
+               std::tie(o.device, o.dtype, o.cu, o.cd, o.nnz_up, o.nnz_dn);
+    }
+};
+std::mutex g_shape_mu;
+std::map<ShapeKey, QuadShape> g_shapes;
+
 // Schedule selection.  Environment overrides for measurement: HUB_MATVEC_IMPL
 // (1 csr, 2 fused, 3 two-pass), HUB_MATVEC_TB, HUB_MATVEC_BS (512 / 1024),
 // HUB_MATVEC_XC (tile order), HUB_MATVEC_QUAD (0: one row per lane),
@@ -997,7 +1015,19 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
             const int t2 = std::min(std::max(tb_env > 0 ? tb_env : 1, 1), 3);
             return launch_quad<T>(s, A, st, t2, bs_env == 512 ? 512 : 1024, xc_env);
         }
-        if (q.tb == 0) HUB_TRY(tune_quad<T>(s, A, st, q));
+        if (q.tb == 0) {
+            const ShapeKey key{s->device, di, (int64_t)A.cu, (int64_t)A.cd, s->spin[0].nnz, s->spin[1].nnz};
+            {
+                std::lock_guard<std::mutex> lk(g_shape_mu);
+                auto it = g_shapes.find(key);
+                if (it != g_shapes.end()) q = it->second;
+            }
+            if (q.tb == 0) {
+                HUB_TRY(tune_quad<T>(s, A, st, q));
+                std::lock_guard<std::mutex> lk(g_shape_mu);
+                g_shapes[key] = q;
+            }
+        }
         return launch_quad<T>(s, A, st, q.tb, q.bs, q.xc);
     }
     if (impl == 2 && fits) {

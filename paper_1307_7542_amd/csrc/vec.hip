@@ -165,6 +165,46 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Four consecutive elements per lane: 16-byte loads (FP32) or two 16-byte loads (FP64).
+template <typename T>
+struct E4 {
+    T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ E4<T> ld_e4(const T *p)
+{
+    E4<T> r;
+    if constexpr (sizeof(T) == 4) {
+        const float4 q = *reinterpret_cast<const float4 *>(p);
+        r.v[0] = q.x;
+        r.v[1] = q.y;
+        r.v[2] = q.z;
+        r.v[3] = q.w;
+    } else {
+        const double2 q0 = reinterpret_cast<const double2 *>(p)[0], q1 = reinterpret_cast<const double2 *>(p)[1];
+        r.v[0] = q0.x;
+        r.v[1] = q0.y;
+        r.v[2] = q1.x;
+        r.v[3] = q1.y;
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void st_e4(T *p, const T (&v)[4])
+{
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+        reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+    }
+}
+
+// partial[block * kstride + j] = sum over the block's elements of q_j * w, for
+// the k stored vectors in groups of GJ; lanes take four consecutive elements,
+// block 0 also the n % 4 tail.  Every vector is a separate allocation (aligned).
 template <typename T>
 __global__ __launch_bounds__(RB) void k_gram_dot(const T *const *__restrict__ Q, int k, const T *__restrict__ w,
                                                  int64_t n, double *__restrict__ partial, int kstride,
@@ -173,6 +213,8 @@ __global__ __launch_bounds__(RB) void k_gram_dot(const T *const *__restrict__ Q,
     if (skip && *skip) return;
     __shared__ double s[RB / 64][GJ];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t n4 = n >> 2;
+    const int64_t tail = n - 4 * n4;
     for (int j0 = 0; j0 < k; j0 += GJ) {
         double acc[GJ];
 #pragma unroll
@@ -181,11 +223,21 @@ __global__ __launch_bounds__(RB) void k_gram_dot(const T *const *__restrict__ Q,
         const T *q[GJ];
 #pragma unroll
         for (int u = 0; u < GJ; ++u) q[u] = Q[j0 + (u < jn ? u : 0)];
-        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
-            const double wi = (double)w[i];
+        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n4; i += (int64_t)gridDim.x * RB) {
+            const E4<T> wv = ld_e4(w + 4 * i);
 #pragma unroll
             for (int u = 0; u < GJ; ++u)
-                if (u < jn) acc[u] += (double)q[u][i] * wi;
+                if (u < jn) {
+                    const E4<T> qv = ld_e4(q[u] + 4 * i);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[u] += (double)qv.v[r] * (double)wv.v[r];
+                }
+        }
+        if (blockIdx.x == 0 && threadIdx.x < tail) {
+            const int64_t i = 4 * n4 + threadIdx.x;
+#pragma unroll
+            for (int u = 0; u < GJ; ++u)
+                if (u < jn) acc[u] += (double)q[u][i] * (double)w[i];
         }
 #pragma unroll
         for (int u = 0; u < GJ; ++u) {
@@ -216,13 +268,30 @@ __global__ __launch_bounds__(RB) void k_gram_final(const double *__restrict__ pa
     if (threadIdx.x == 0) coef[j] = r;
 }
 
-// w <- w - sum_j c_j q_j, evaluated in FP64 per element.
+// w <- w - sum_j c_j q_j, evaluated in FP64 per element; lanes take four
+// consecutive elements (the n % 4 tail element by element).
 template <typename T>
 __global__ void k_gram_update(const T *const *__restrict__ Q, int k, const double *__restrict__ coef,
                               T *__restrict__ w, int64_t n, const int *__restrict__ skip)
 {
     if (skip && *skip) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n4 = n >> 2;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < k; ++j) {
+            const double c = coef[j];
+            const E4<T> qv = ld_e4(Q[j] + 4 * i);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] += c * (double)qv.v[r];
+        }
+        const E4<T> wv = ld_e4(w + 4 * i);
+        T o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = (T)((double)wv.v[r] - acc[r]);
+        st_e4(w + 4 * i, o);
+    }
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double acc = 0.0;
         for (int j = 0; j < k; ++j) acc += coef[j] * (double)Q[j][i];
         w[i] = (T)((double)w[i] - acc);
