@@ -320,6 +320,7 @@ def main():
         pass
     if not args.no_extra:
         out["products_square4x4"] = product_timing(hub, torch, W.config("square4x4"))
+        out["products_ladder2x9"] = product_timing(hub, torch, W.config("ladder2x9"), reps=3)
         out["aim_batch64"] = batch_timing(hub, torch)
         out["greens_ring14_u4"] = greens_timing(hub, torch, models[4])
         out["k0_ring14_u4"] = k0_timing(hub, torch, models[4])

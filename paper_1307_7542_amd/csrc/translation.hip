@@ -225,15 +225,20 @@ __device__ __forceinline__ T k0_diag(const K0Args<T> &A, uint32_t both)
     return d;
 }
 
-// One workgroup per down cycle j (q <= QMAX members).  STAGE: the q columns
-// of the cycle in LDS (R x q values); otherwise read from global memory.
-template <typename T, int BS, int QMAX, bool STAGE>
+// One workgroup per down cycle j: the cycle's q columns are staged in LDS
+// (STAGE; R x q values) or read from global memory; wave w takes members
+// m = w, w + NW, ... and its lanes take rows i = lane + 64 r.  Each lane
+// computes whole output elements: diagonal, the H_up hops of row i (source
+// member (m - s) mod q with its phase, from per-cycle tables in LDS) and the
+// H_dn neighbour columns.
+template <typename T, int BS, bool STAGE>
 __global__ __launch_bounds__(BS) void k_k0_product(K0Args<T> A)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int32_t cols[QMAX], csg[QMAX];
-    __shared__ int8_t sg[QMAX * 32];
-    __shared__ int8_t srcm[QMAX * 32];
+    constexpr int NW = BS / 64;
+    __shared__ int32_t cols[32], csg[32];
+    __shared__ int8_t sg[32 * 32];
+    __shared__ int8_t srcm[32 * 32];
     T *xs = reinterpret_cast<T *>(smem_raw);
     const int j = blockIdx.x;
     const int o0 = A.orb_off[j];
@@ -258,59 +263,46 @@ __global__ __launch_bounds__(BS) void k_k0_product(K0Args<T> A)
         }
     }
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < R; i += BS) {
-        const uint32_t ri = A.reps[i];
-        const T ei = A.rep_e[i];
-        T acc[QMAX];
-#pragma unroll
-        for (int m = 0; m < QMAX; ++m) {
-            if (m < q) {
-                const int b = cols[m];
-                const T xv = STAGE ? xs[(int64_t)m * R + i] : A.x[(int64_t)b * R + i];
-                acc[m] = (k0_diag(A, ri & A.dn_basis[b]) + ei + A.e_dn[b]) * xv;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int m = wave; m < q; m += NW) {
+        const int b = cols[m];
+        const uint32_t db = A.dn_basis[b];
+        const T eb = A.e_dn[b];
+        const int ks = A.dn_rp[b], ke = A.dn_rp[b + 1];
+        for (int64_t i = lane; i < R; i += 64) {
+            const T xv = STAGE ? xs[(int64_t)m * R + i] : A.x[(int64_t)b * R + i];
+            T acc = (k0_diag(A, A.reps[i] & db) + A.rep_e[i] + eb) * xv;
+            for (int h = A.hop_rp[i]; h < A.hop_rp[i + 1]; ++h) {
+                const int s = A.hop_s[h];
+                const int a = srcm[m * 32 + s];
+                const int64_t r2 = A.hop_row[h];
+                const T c = A.hop_c[h];
+                const T xs2 = STAGE ? xs[(int64_t)a * R + r2] : A.x[(int64_t)cols[a] * R + r2];
+                acc += (sg[m * 32 + s] < 0 ? -c : c) * xs2;
             }
-        }
-        for (int h = A.hop_rp[i]; h < A.hop_rp[i + 1]; ++h) {
-            const int64_t r2 = A.hop_row[h];
-            const int s = A.hop_s[h];
-            const T c = A.hop_c[h];
-#pragma unroll
-            for (int m = 0; m < QMAX; ++m) {
-                if (m < q) {
-                    const int a = srcm[m * 32 + s];
-                    const T xv = STAGE ? xs[(int64_t)a * R + r2] : A.x[(int64_t)cols[a] * R + r2];
-                    acc[m] += (sg[m * 32 + s] < 0 ? -c : c) * xv;
-                }
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < QMAX; ++m) {
-            if (m < q) {
-                const int b = cols[m];
-                T s2 = (T)0;
-                for (int k = A.dn_rp[b]; k < A.dn_rp[b + 1]; ++k) s2 += A.dn_val[k] * A.x[(int64_t)A.dn_col[k] * R + i];
-                A.y[(int64_t)b * R + i] = acc[m] + s2;
-            }
+            T s2 = (T)0;
+            for (int k = ks; k < ke; ++k) s2 += A.dn_val[k] * A.x[(int64_t)A.dn_col[k] * R + i];
+            A.y[(int64_t)b * R + i] = acc + s2;
         }
     }
 }
 
 // Projector onto the consistent subspace of the rows with P_i < L: one
-// thread per (short row, down cycle) averages the q members over the
-// stabiliser G^P_i (order L / P_i), in place.
-template <typename T, int QMAX>
-__global__ __launch_bounds__(256) void k_k0_project(T *x, int64_t R, int L, int64_t n_orb,
-                                                    const int32_t *__restrict__ short_rows,
-                                                    const int32_t *__restrict__ period,
-                                                    const int32_t *__restrict__ short_sigma, int64_t n_short,
-                                                    const int32_t *__restrict__ orb_off,
-                                                    const int32_t *__restrict__ orb_cols,
-                                                    const int32_t *__restrict__ orb_sign,
-                                                    const int32_t *__restrict__ orb_sigma)
+// 64-lane block per (short row, down cycle); lane m holds member m and
+// averages the q members over the stabiliser G^P_i (order L / P_i), in place.
+template <typename T>
+__global__ __launch_bounds__(64) void k_k0_project(T *x, int64_t R, int L, int64_t n_orb,
+                                                   const int32_t *__restrict__ short_rows,
+                                                   const int32_t *__restrict__ period,
+                                                   const int32_t *__restrict__ short_sigma,
+                                                   const int32_t *__restrict__ orb_off,
+                                                   const int32_t *__restrict__ orb_cols,
+                                                   const int32_t *__restrict__ orb_sign,
+                                                   const int32_t *__restrict__ orb_sigma)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_short * n_orb) return;
-    const int64_t r = t / n_orb, j = t - (t / n_orb) * n_orb;
+    __shared__ T v[32];
+    __shared__ int32_t c[32];
+    const int64_t r = blockIdx.x / n_orb, j = blockIdx.x - (blockIdx.x / n_orb) * n_orb;
     const int64_t i = short_rows[r];
     const int P = period[i];
     const int su = short_sigma[r];
@@ -318,31 +310,25 @@ __global__ __launch_bounds__(256) void k_k0_project(T *x, int64_t R, int L, int6
     const int o0 = orb_off[j];
     const int q = orb_off[j + 1] - o0;
     const int sigma = orb_sigma[j];
-    const int32_t *c = orb_sign + o0;
-    T v[QMAX], out[QMAX];
-#pragma unroll
-    for (int m = 0; m < QMAX; ++m)
-        if (m < q) v[m] = x[(int64_t)orb_cols[o0 + m] * R + i];
-#pragma unroll
-    for (int m = 0; m < QMAX; ++m) {
-        if (m >= q) continue;
+    const int m = threadIdx.x;
+    int64_t addr = 0;
+    if (m < q) {
+        addr = (int64_t)orb_cols[o0 + m] * R + i;
+        v[m] = x[addr];
+        c[m] = orb_sign[o0 + m];
+    }
+    __syncthreads();
+    if (m < q) {
         double acc = 0.0;
         int gu = 1;
         for (int k = 0; k < n; ++k) {
             int a;
             const int g = cyc_sign(c, q, sigma, m, k * P, &a);
-            T va = (T)0;
-#pragma unroll
-            for (int mm = 0; mm < QMAX; ++mm)
-                if (mm == a) va = v[mm];
-            acc += (double)(gu * g) * (double)va;
+            acc += (double)(gu * g) * (double)v[a];
             gu *= su;
         }
-        out[m] = (T)(acc / (double)n);
+        x[addr] = (T)(acc / (double)n);
     }
-#pragma unroll
-    for (int m = 0; m < QMAX; ++m)
-        if (m < q) x[(int64_t)orb_cols[o0 + m] * R + i] = out[m];
 }
 
 template <typename T>
@@ -386,23 +372,22 @@ K0Args<T> k0_args(const hub_sector *s, const void *x, void *y)
     return A;
 }
 
-template <typename T, int QMAX>
+template <typename T>
 hub_status k0_project_t(const hub_sector *s, void *x, hipStream_t st)
 {
     const K0Tables &K = *s->k0;
     if (K.n_short == 0) return HUB_OK;
-    const int64_t n = K.n_short * K.n_orb;
-    hipLaunchKernelGGL((k_k0_project<T, QMAX>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (T *)x, K.R,
-                       K.L, K.n_orb, K.short_rows, K.period, K.short_sigma, K.n_short, K.orb_off, K.orb_cols,
-                       K.orb_sign, K.orb_sigma);
+    const int64_t nb = K.n_short * K.n_orb;
+    hipLaunchKernelGGL((k_k0_project<T>), dim3((unsigned)nb), dim3(64), 0, st, (T *)x, K.R, K.L, K.n_orb,
+                       K.short_rows, K.period, K.short_sigma, K.orb_off, K.orb_cols, K.orb_sign, K.orb_sigma);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
 
-template <typename T, int QMAX>
+template <typename T>
 hub_status k0_product_t(const hub_sector *s, const void *x, void *y, hipStream_t st)
 {
-    constexpr int BS = 256;
+    constexpr int BS = 1024;
     const K0Tables &K = *s->k0;
     const K0Args<T> A = k0_args<T>(s, x, y);
     const size_t lds = (size_t)K.max_q * (size_t)K.R * sizeof(T);
@@ -411,16 +396,16 @@ hub_status k0_product_t(const hub_sector *s, const void *x, void *y, hipStream_t
     if (lds <= dyn_max) {
         static bool attr = false;
         if (!attr) {
-            HUB_HIP(hipFuncSetAttribute((const void *)k_k0_product<T, BS, QMAX, true>,
+            HUB_HIP(hipFuncSetAttribute((const void *)k_k0_product<T, BS, true>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max));
             attr = true;
         }
-        hipLaunchKernelGGL((k_k0_product<T, BS, QMAX, true>), dim3((unsigned)K.n_orb), dim3(BS), lds, st, A);
+        hipLaunchKernelGGL((k_k0_product<T, BS, true>), dim3((unsigned)K.n_orb), dim3(BS), lds, st, A);
     } else {
-        hipLaunchKernelGGL((k_k0_product<T, BS, QMAX, false>), dim3((unsigned)K.n_orb), dim3(BS), 0, st, A);
+        hipLaunchKernelGGL((k_k0_product<T, BS, false>), dim3((unsigned)K.n_orb), dim3(BS), 0, st, A);
     }
     HUB_HIP(hipGetLastError());
-    return k0_project_t<T, QMAX>(s, y, st);
+    return k0_project_t<T>(s, y, st);
 }
 
 hub_status tfail(hub_status c, const std::string &m)
@@ -582,17 +567,15 @@ hub_status build_k0(hub_sector *s, int w, hipStream_t st)
 hub_status apply_h(const hub_sector *s, int dtype, const void *x, void *y, hipStream_t st)
 {
     if (!s->k0) return launch_matvec(s, dtype, x, y, st);
-    const int q = s->k0->max_q;
-    if (dtype == HUB_F64) return q <= 16 ? k0_product_t<double, 16>(s, x, y, st) : k0_product_t<double, 32>(s, x, y, st);
-    return q <= 16 ? k0_product_t<float, 16>(s, x, y, st) : k0_product_t<float, 32>(s, x, y, st);
+    if (dtype == HUB_F64) return k0_product_t<double>(s, x, y, st);
+    return k0_product_t<float>(s, x, y, st);
 }
 
 hub_status k0_project(const hub_sector *s, int dtype, void *x, hipStream_t st)
 {
     if (!s->k0) return HUB_OK;
-    const int q = s->k0->max_q;
-    if (dtype == HUB_F64) return q <= 16 ? k0_project_t<double, 16>(s, x, st) : k0_project_t<double, 32>(s, x, st);
-    return q <= 16 ? k0_project_t<float, 16>(s, x, st) : k0_project_t<float, 32>(s, x, st);
+    if (dtype == HUB_F64) return k0_project_t<double>(s, x, st);
+    return k0_project_t<float>(s, x, st);
 }
 
 }  // namespace hub
