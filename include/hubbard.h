@@ -188,6 +188,8 @@ typedef struct hub_lanczos_opts {
     int32_t refine;        /* FP64 Rayleigh quotient and residual (needs want_vector) */
     int32_t check_every;   /* host convergence test period; default 1 when <= 0 */
     int32_t time_kernels;  /* record HIP events around every product launch */
+    double e0_target;      /* reference energy for seconds_to_target (used when e0_target_rel > 0) */
+    double e0_target_rel;  /* record the first check with |theta - e0_target| <= rel |e0_target| */
 } hub_lanczos_opts;
 
 typedef struct hub_lanczos_info {
@@ -203,6 +205,8 @@ typedef struct hub_lanczos_info {
     double seconds_to_e0;   /* wall time until the Ritz test passed */
     double matvec_ms;       /* summed event time of those products (time_kernels) */
     int64_t matvec_bytes;   /* algorithmic bytes of one product: 2 dim s + tables */
+    int32_t iters_to_target; /* steps when the lowest Ritz value first met the e0 target (-1: never / unused) */
+    double seconds_to_target; /* wall time from entry until then (-1: never / unused) */
 } hub_lanczos_info;
 
 hub_status hub_ground_state(const hub_sector *sec, const hub_lanczos_opts *opts, double *e0, void *dev_psi,

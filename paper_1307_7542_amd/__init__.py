@@ -51,7 +51,7 @@ class LanczosOpts(ctypes.Structure):
         ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("seed", ctypes.c_uint64),
         ("dev_start", ctypes.c_void_p), ("vec_dtype", ctypes.c_int32), ("reorth", ctypes.c_int32),
         ("want_vector", ctypes.c_int32), ("refine", ctypes.c_int32), ("check_every", ctypes.c_int32),
-        ("time_kernels", ctypes.c_int32),
+        ("time_kernels", ctypes.c_int32), ("e0_target", ctypes.c_double), ("e0_target_rel", ctypes.c_double),
     ]
 
 
@@ -61,6 +61,7 @@ class LanczosInfo(ctypes.Structure):
         ("matvec_count", ctypes.c_int32), ("e0_ritz", ctypes.c_double), ("e0_refined", ctypes.c_double),
         ("residual", ctypes.c_double), ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double),
         ("seconds_to_e0", ctypes.c_double), ("matvec_ms", ctypes.c_double), ("matvec_bytes", ctypes.c_int64),
+        ("iters_to_target", ctypes.c_int32), ("seconds_to_target", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -276,13 +277,15 @@ class Sector:
     def ground_state(self, *, dtype: int = F64, reorth: bool = False, want_vector: bool = True,
                      refine: bool = False, max_iter: int = 400, tol: float = 0.0, seed: int = 7542,
                      start=None, check_every: int = 1, time_kernels: bool = False, psi=None,
-                     stream=None, allow_not_converged: bool = False) -> GroundState:
+                     stream=None, allow_not_converged: bool = False, e0_target: Optional[float] = None,
+                     e0_target_rel: float = 0.0) -> GroundState:
         want = want_vector or refine
         if want and psi is None:
             psi = self.empty(F64)
         o = LanczosOpts(max_iter, tol, seed,
                         _dev_ptr(start, F64, self.dim, "start") if start is not None else None,
-                        dtype, int(reorth), int(want_vector), int(refine), check_every, int(time_kernels))
+                        dtype, int(reorth), int(want_vector), int(refine), check_every, int(time_kernels),
+                        float(e0_target or 0.0), float(e0_target_rel if e0_target is not None else 0.0))
         info = LanczosInfo()
         e0 = ctypes.c_double()
         allow = (HUB_OK, HUB_ERR_NOT_CONVERGED) if allow_not_converged else (HUB_OK,)
@@ -424,7 +427,7 @@ class Batch:
                      stream=None, allow_not_converged: bool = False):
         want = want_vector or refine
         psi = self.empty(F64) if want else None
-        o = LanczosOpts(max_iter, tol, seed, None, dtype, 0, int(want_vector), int(refine), check_every, 0)
+        o = LanczosOpts(max_iter, tol, seed, None, dtype, 0, int(want_vector), int(refine), check_every, 0, 0.0, 0.0)
         e0 = np.zeros(len(self.sectors))
         it = np.zeros(len(self.sectors), dtype=np.int32)
         info = BatchInfo()

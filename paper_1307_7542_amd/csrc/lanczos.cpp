@@ -192,6 +192,9 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     hub_lanczos_info inf;
     std::memset(&inf, 0, sizeof(inf));
     inf.true_residual = -1.0;
+    inf.iters_to_target = -1;
+    inf.seconds_to_target = -1.0;
+    const bool want_target = o->e0_target_rel > 0.0;
     inf.matvec_bytes = matvec_bytes(s, dt);
 
     DevMem mem;
@@ -294,6 +297,11 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         }
         theta = tri_lowest(ha, hb + 1, mm, y);
         res = std::fabs(hb[mm]) * std::fabs(y[mm - 1]);
+        if (want_target && inf.iters_to_target < 0 &&
+            std::fabs(theta - o->e0_target) <= o->e0_target_rel * std::fabs(o->e0_target)) {
+            inf.iters_to_target = mm;
+            inf.seconds_to_target = std::chrono::duration<double>(clk::now() - t0).count();
+        }
         const double scale = std::fabs(theta) > 0 ? std::fabs(theta) : 1.0;
         m_final = mm;
         if (breakdown || res <= tol * scale) {

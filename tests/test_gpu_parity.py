@@ -505,3 +505,22 @@ def test_quad_product_shapes_bitwise(hub, which, monkeypatch):
         monkeypatch.delenv("HUB_MATVEC_QUAD")
         assert np.all(np.abs(y1.astype(np.float64) - y0.astype(np.float64)) <= 2 * tol * bound + 1e-30)
     s.close()
+
+
+def test_time_to_target_energy(hub):
+    """The solver records the first step whose lowest Ritz value is within the
+    requested relative distance of a reference energy (the time-to-E0 measure)."""
+    m = W.config("ring8")
+    s = hub.Sector(m)
+    _, e_ref, _ = oracle.ground_state(m)
+    g = s.ground_state(dtype=hub.F64, tol=1e-12, want_vector=False, e0_target=e_ref, e0_target_rel=1e-6)
+    it, sec = g.info["iters_to_target"], g.info["seconds_to_target"]
+    assert 1 <= it <= g.info["iters"] and 0.0 < sec <= g.info["seconds"]
+    g2 = s.ground_state(dtype=hub.F64, tol=1e-12, want_vector=False, e0_target=e_ref, e0_target_rel=1e-10)
+    assert it <= g2.info["iters_to_target"] <= g2.info["iters"]
+    g3 = s.ground_state(dtype=hub.F64, tol=1e-12, want_vector=False)
+    assert g3.info["iters_to_target"] == -1 and g3.info["seconds_to_target"] == -1.0
+    # a target never met (an energy below the ground state)
+    g4 = s.ground_state(dtype=hub.F64, tol=1e-12, want_vector=False, e0_target=e_ref - 1.0, e0_target_rel=1e-6)
+    assert g4.info["iters_to_target"] == -1
+    s.close()
