@@ -134,6 +134,15 @@ hub_status rank_device(const hub_sector *s, int spin, const uint64_t *dx, int64_
 
 // ---- product (matvec.hip) ----------------------------------------------
 hub_status launch_matvec(const hub_sector *s, int dtype, const void *x, void *y, hipStream_t st);
+// Product fused with the first Lanczos update: w = H x - beta v_prev (v_prev may
+// be NULL) and partial sums of <w, x> in apart (npart values, summed in order
+// they give alpha).  Available when matvec_lz_available(s, dtype).
+bool matvec_lz_available(const hub_sector *s, int dtype);
+int64_t matvec_lz_partials(const hub_sector *s);
+hub_status launch_matvec_lz(const hub_sector *s, int dtype, const void *x, void *w, const void *vprev,
+                            const double *beta, double *apart, int64_t *npart, hipStream_t st);
+// sum of np partials in a fixed order into *out (one block)
+hub_status launch_sum(const double *partial, int64_t np, double *out, hipStream_t st);
 hub_status launch_diagonal(const hub_sector *s, int dtype, void *out, hipStream_t st);
 int64_t matvec_bytes(const hub_sector *s, int dtype);
 

@@ -254,6 +254,24 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         inf.matvec_count++;
         return HUB_OK;
     };
+    // y = H x - beta v_prev and alpha = <y, x>: one fused launch (plus a fixed-order
+    // sum of its partials) where the product kernel supports it, else product + update
+    const bool fused = matvec_lz_available(s, dt);
+    double *apart = nullptr;
+    if (fused) HUB_TRY(mem.alloc((void **)&apart, sizeof(double) * (size_t)matvec_lz_partials(s)));
+    if (fused) inf.matvec_bytes += (int64_t)es * n;  // the update's read of v_prev
+    auto product_lz = [&](const void *x, void *y, const void *vp, const double *bk, double *aout) -> hub_status {
+        if (fused) {
+            int64_t np = 0;
+            HUB_TRY(tm.mark());
+            HUB_TRY(launch_matvec_lz(s, dt, x, y, vp, bk, apart, &np, st));
+            HUB_TRY(tm.mark());
+            inf.matvec_count++;
+            return launch_sum(apart, np, aout, st);
+        }
+        HUB_TRY(product(x, y));
+        return launch_lz_a(dt, y, vp, bk, x, n, partial, aout, st);
+    };
 
     HUB_TRY(make_start(Va));
     void *v_prev = nullptr, *v = Va, *spare = Vb;
@@ -320,8 +338,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     for (int k = 0; k < max_iter; ++k) {
         const bool check_now = k >= 1 && (k % check_every) == 0;
         if (check_now) HUB_TRY(fetch(k));
-        HUB_TRY(product(v, W));
-        HUB_TRY(launch_lz_a(dt, W, v_prev, d_beta + k, v, n, partial, d_alpha + k, st));
+        HUB_TRY(product_lz(v, W, v_prev, d_beta + k, d_alpha + k));
         if (reorth) {
             // classical Gram-Schmidt against every stored vector; the second pass
             // runs only when the first removed more than 1 - 1/sqrt(2) of the norm
@@ -387,8 +404,14 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             HUB_TRY(launch_psi_acc(dt, psi, a, d_y, n, 1, st));
             void *vp = nullptr, *vc = a, *sp = b;
             for (int j = 0; j + 1 < m; ++j) {
-                HUB_TRY(product(vc, W));
-                HUB_TRY(launch_lz_replay(dt, W, vp, d_beta + j, vc, d_alpha + j, n, st));
+                if (fused) {
+                    // same two roundings as the first pass: the fused update, then w -= alpha_j v
+                    HUB_TRY(product_lz(vc, W, vp, d_beta + j, d_misc + 10));
+                    HUB_TRY(launch_lz_b(dt, W, vc, d_alpha + j, n, partial, nullptr, st));
+                } else {
+                    HUB_TRY(product(vc, W));
+                    HUB_TRY(launch_lz_replay(dt, W, vp, d_beta + j, vc, d_alpha + j, n, st));
+                }
                 if (reproject) HUB_TRY(k0_project(s, dt, W, st));
                 void *vn = vp ? vp : sp;
                 HUB_TRY(launch_lz_next(dt, W, vn, d_beta + j + 1, n, st));

@@ -229,14 +229,35 @@ __device__ __forceinline__ void st_q4(T *p, const T (&v)[4])
     }
 }
 
-template <typename T, int TB, int BS, bool XC>
+// First Lanczos update fused into the product's epilogue: w = (H x) - beta v_prev
+// (rounded as the separate update kernel does) and the sum of w * x per column:
+// each group of 64 lane-quads (256 rows) is summed by one wavefront in a fixed
+// order, then the groups of a column in increasing order, so the per-column
+// partials do not depend on the tile shape.
+template <typename T>
+struct LzEpi {
+    const T *vprev;       // NULL at the first step
+    const double *beta;   // beta_k (device)
+    double *apart;        // [cd] per-column partials
+    int G;                // lane-quad groups per column: ceil(count_up / 256)
+};
+
+__device__ __forceinline__ double quad_wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T, int TB, int BS, bool XC, bool EPI>
 __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__restrict__ sl_off,
                                                   const uint32_t *__restrict__ ellc, const T *__restrict__ code_v,
-                                                  int ntiles)
+                                                  int ntiles, LzEpi<T> E)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tab = reinterpret_cast<T *>(smem_raw);  // 256 code values
     T *xs = tab + 256;                         // TB staged columns, interleaved
+    double *gpart = reinterpret_cast<double *>(xs + TB * A.cu);  // EPI: TB x G group partials
     int tile;
     if (XC) {
         tile = xcd_tile(ntiles);
@@ -269,8 +290,12 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
         edn[t] = A.e_dn[b];
     }
     const int64_t cu64 = cu;
-    for (int q = threadIdx.x; q < nq; q += BS) {
-        const int a0 = 4 * q;
+    const int lane = threadIdx.x & 63;
+    const double bt = (EPI && E.vprev) ? *E.beta : 0.0;
+    // every lane of a wavefront runs the same iterations (the epilogue reduces over the wavefront)
+    for (int q = threadIdx.x; q - lane < nq; q += BS) {
+        const bool live = q < nq;
+        const int a0 = 4 * (live ? q : 0);
         T acc[4][TB];
         const uint4 ub = *reinterpret_cast<const uint4 *>(A.up_basis + a0);
         const uint32_t uu[4] = {ub.x, ub.y, ub.z, ub.w};
@@ -332,8 +357,31 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
 #pragma unroll
         for (int t = 0; t < TB; ++t) {
             if (b0 + t >= cd) continue;
-            const T o[4] = {acc[0][t], acc[1][t], acc[2][t], acc[3][t]};
-            st_q4(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
+            T o[4] = {acc[0][t], acc[1][t], acc[2][t], acc[3][t]};
+            if (EPI) {
+                double part = 0.0;
+                if (live) {
+                    if (E.vprev) {
+                        const Q4<T> vp = ld_q4(E.vprev + (int64_t)(b0 + t) * cu64 + a0);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) o[r] = (T)((double)o[r] - bt * (double)vp.v[r]);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) part += (double)o[r] * (double)xs[(a0 + r) * TB + t];
+                }
+                part = quad_wave_sum(part);
+                if (lane == 0) gpart[t * E.G + (q >> 6)] = part;
+            }
+            if (live) st_q4(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
+        }
+    }
+    if (EPI) {
+        // one partial per column: its groups summed in increasing order
+        __syncthreads();
+        if (threadIdx.x < TB && b0 + (int)threadIdx.x < cd) {
+            double sum = 0.0;
+            for (int g = 0; g < E.G; ++g) sum += gpart[threadIdx.x * E.G + g];
+            E.apart[b0 + threadIdx.x] = sum;
         }
     }
 }
@@ -857,32 +905,46 @@ hub_status launch_two_pass(const hub_sector *s, const MvArgs<T> &A, hipStream_t 
     return HUB_OK;
 }
 
-template <typename T, int TB, int BS, bool XC>
-hub_status launch_quad_t(const hub_sector *s, const MvArgs<T> &A, hipStream_t st)
+template <typename T, int TB, int BS, bool XC, bool EPI>
+hub_status launch_quad_e(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const LzEpi<T> &E)
 {
     const SpinTables &U = s->spin[0];
     const int ntiles = (A.cd + TB - 1) / TB;
     const unsigned grid = XC ? 8u * (unsigned)((ntiles + 7) / 8) : (unsigned)ntiles;
-    const size_t lds = (size_t)(A.cu * TB + 256) * sizeof(T);
+    // columns (cu % 4 == 0 keeps the FP32 case 8-byte aligned), then the group partials
+    const size_t lds = (size_t)(A.cu * TB + 256) * sizeof(T) + (EPI ? (size_t)TB * E.G * sizeof(double) : 0);
+    if (lds > s->lds_max) {
+        set_error("fused product: tile does not fit in LDS");
+        return HUB_ERR_UNSUPPORTED;
+    }
     static bool attr = false;
     if (!attr) {
-        HUB_TRY(allow_lds(k_kron_quad<T, TB, BS, XC>, s->lds_max));
+        HUB_TRY(allow_lds(k_kron_quad<T, TB, BS, XC, EPI>, s->lds_max));
         attr = true;
     }
     const T *cv;
     if constexpr (sizeof(T) == 8) cv = (const T *)U.code_v64;
     else cv = (const T *)U.code_v32;
-    hipLaunchKernelGGL((k_kron_quad<T, TB, BS, XC>), dim3(grid), dim3(BS), lds, st, A, U.sl_off, U.ell_c32, cv, ntiles);
+    hipLaunchKernelGGL((k_kron_quad<T, TB, BS, XC, EPI>), dim3(grid), dim3(BS), lds, st, A, U.sl_off, U.ell_c32, cv,
+                       ntiles, E);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
 
-// shape code: TB in 1..3, BS in {512, 1024}, XC in {0, 1}
+template <typename T, int TB, int BS, bool XC>
+hub_status launch_quad_t(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const LzEpi<T> *E)
+{
+    if (E) return launch_quad_e<T, TB, BS, XC, true>(s, A, st, *E);
+    return launch_quad_e<T, TB, BS, XC, false>(s, A, st, LzEpi<T>{nullptr, nullptr, nullptr, 0});
+}
+
+// shape code: TB in 1..3, BS in {512, 1024}, XC in {0, 1}; E: fused Lanczos epilogue or NULL
 template <typename T>
-hub_status launch_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, int bs, int xc)
+hub_status launch_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, int bs, int xc,
+                       const LzEpi<T> *E = nullptr)
 {
 #define HUB_QUAD(TBV, BSV, XCV)                                                                       \
-    if (tb == TBV && bs == BSV && xc == XCV) return launch_quad_t<T, TBV, BSV, XCV>(s, A, st);
+    if (tb == TBV && bs == BSV && xc == XCV) return launch_quad_t<T, TBV, BSV, XCV>(s, A, st, E);
     HUB_QUAD(1, 512, 0) HUB_QUAD(1, 512, 1) HUB_QUAD(1, 1024, 0) HUB_QUAD(1, 1024, 1)
     HUB_QUAD(2, 512, 0) HUB_QUAD(2, 512, 1) HUB_QUAD(2, 1024, 0) HUB_QUAD(2, 1024, 1)
     HUB_QUAD(3, 512, 0) HUB_QUAD(3, 512, 1) HUB_QUAD(3, 1024, 0) HUB_QUAD(3, 1024, 1)
@@ -945,6 +1007,69 @@ struct ShapeKey {
 std::mutex g_shape_mu;
 std::map<ShapeKey, QuadShape> g_shapes;
 
+// Shape of the four-rows-per-lane product: forced by HUB_MATVEC_TB / _BS / _XC,
+// else the sector's tuned shape (tuning on first use, shared by sectors of
+// the same structure).
+template <typename T>
+hub_status quad_shape(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, QuadShape &out)
+{
+    const int di = (sizeof(T) == 8) ? 0 : 1;
+    const int tb_env = env_int("HUB_MATVEC_TB", 0);
+    const int bs_env = env_int("HUB_MATVEC_BS", 0);
+    if (tb_env > 0 || bs_env > 0) {
+        out.tb = std::min(std::max(tb_env > 0 ? tb_env : 1, 1), 3);
+        out.bs = bs_env == 512 ? 512 : 1024;
+        out.xc = env_int("HUB_MATVEC_XC", 1) != 0 ? 1 : 0;
+        return HUB_OK;
+    }
+    QuadShape &q = s->quad[di];
+    if (q.tb == 0) {
+        const ShapeKey key{s->device, di, (int64_t)A.cu, (int64_t)A.cd, s->spin[0].nnz, s->spin[1].nnz};
+        {
+            std::lock_guard<std::mutex> lk(g_shape_mu);
+            auto it = g_shapes.find(key);
+            if (it != g_shapes.end()) q = it->second;
+        }
+        if (q.tb == 0) {
+            HUB_TRY(tune_quad<T>(s, A, st, q));
+            std::lock_guard<std::mutex> lk(g_shape_mu);
+            g_shapes[key] = q;
+        }
+    }
+    out = q;
+    return HUB_OK;
+}
+
+// Whether the fused product + first Lanczos update is available for the sector.
+template <typename T>
+bool lz_fusable(const hub_sector *s)
+{
+    const SpinTables &U = s->spin[0];
+    const size_t col_bytes = (size_t)U.count * sizeof(T);
+    return !s->k0 && env_int("HUB_MATVEC_IMPL", 2) == 2 && env_int("HUB_MATVEC_QUAD", 1) != 0 &&
+           env_int("HUB_ELL_FMT", 1) != 0 && env_int("HUB_LZ_FUSE", 1) != 0 && U.ell_c32 && !s->force_chunked &&
+           (U.count % 4) == 0 && col_bytes + 256 * sizeof(T) <= s->lds_max;
+}
+
+template <typename T>
+hub_status run_kron_lz(const hub_sector *s, const void *x, void *w, const void *vprev, const double *beta,
+                       double *apart, int64_t *npart, hipStream_t st)
+{
+    if (!lz_fusable<T>(s)) return HUB_ERR_UNSUPPORTED;
+    MvArgs<T> A = make_args<T>(s, x, w);
+    QuadShape q;
+    HUB_TRY(quad_shape<T>(s, A, st, q));
+    const int G = (int)(((A.cu >> 2) + 63) / 64);
+    const LzEpi<T> E{(const T *)vprev, beta, apart, G};
+    *npart = (int64_t)A.cd;
+    // the group partials need TB * G doubles of LDS beside the columns: fall back to fewer columns
+    for (int tb = q.tb; tb >= 1; --tb) {
+        if ((size_t)(A.cu * tb + 256) * sizeof(T) + (size_t)tb * G * sizeof(double) <= s->lds_max)
+            return launch_quad<T>(s, A, st, tb, q.bs, q.xc, &E);
+    }
+    return HUB_ERR_UNSUPPORTED;
+}
+
 // Schedule selection.  Environment overrides for measurement: HUB_MATVEC_IMPL
 // (1 csr, 2 fused, 3 two-pass), HUB_MATVEC_TB, HUB_MATVEC_BS (512 / 1024),
 // HUB_MATVEC_XC (tile order), HUB_MATVEC_QUAD (0: one row per lane),
@@ -967,7 +1092,6 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
     static const int rows = env_int("HUB_FUSED_R", 4);
     static const bool cf = env_int("HUB_ELL_FMT", 1) != 0;
     const bool quad = env_int("HUB_MATVEC_QUAD", 1) != 0;
-    const int xc_env = env_int("HUB_MATVEC_XC", 1) != 0 ? 1 : 0;
     const size_t extra = 256 * sizeof(T);
     const size_t half = s->lds_max / 2;
     int tb = tb_env;
@@ -1010,24 +1134,8 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
         return HUB_OK;
     }
     if (impl == 2 && fits && cf && U.ell_c32 && (A.cu % 4) == 0 && quad) {
-        QuadShape &q = s->quad[di];
-        if (tb_env > 0 || bs_env > 0) {
-            const int t2 = std::min(std::max(tb_env > 0 ? tb_env : 1, 1), 3);
-            return launch_quad<T>(s, A, st, t2, bs_env == 512 ? 512 : 1024, xc_env);
-        }
-        if (q.tb == 0) {
-            const ShapeKey key{s->device, di, (int64_t)A.cu, (int64_t)A.cd, s->spin[0].nnz, s->spin[1].nnz};
-            {
-                std::lock_guard<std::mutex> lk(g_shape_mu);
-                auto it = g_shapes.find(key);
-                if (it != g_shapes.end()) q = it->second;
-            }
-            if (q.tb == 0) {
-                HUB_TRY(tune_quad<T>(s, A, st, q));
-                std::lock_guard<std::mutex> lk(g_shape_mu);
-                g_shapes[key] = q;
-            }
-        }
+        QuadShape q;
+        HUB_TRY(quad_shape<T>(s, A, st, q));
         return launch_quad<T>(s, A, st, q.tb, q.bs, q.xc);
     }
     if (impl == 2 && fits) {
@@ -1047,6 +1155,23 @@ hub_status launch_matvec(const hub_sector *s, int dtype, const void *x, void *y,
 {
     if (dtype == HUB_F64) return run_kron<double>(s, x, y, st);
     return run_kron<float>(s, x, y, st);
+}
+
+bool matvec_lz_available(const hub_sector *s, int dtype)
+{
+    return dtype == HUB_F64 ? lz_fusable<double>(s) : lz_fusable<float>(s);
+}
+
+int64_t matvec_lz_partials(const hub_sector *s)
+{
+    return s->spin[1].count;
+}
+
+hub_status launch_matvec_lz(const hub_sector *s, int dtype, const void *x, void *w, const void *vprev,
+                            const double *beta, double *apart, int64_t *npart, hipStream_t st)
+{
+    if (dtype == HUB_F64) return run_kron_lz<double>(s, x, w, vprev, beta, apart, npart, st);
+    return run_kron_lz<float>(s, x, w, vprev, beta, apart, npart, st);
 }
 
 hub_status launch_diagonal(const hub_sector *s, int dtype, void *out, hipStream_t st)

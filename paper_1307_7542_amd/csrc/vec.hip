@@ -443,6 +443,13 @@ hub_status launch_convert(int din, const void *x, int dout, void *y, int64_t n, 
     return HUB_OK;
 }
 
+hub_status launch_sum(const double *partial, int64_t np, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, (int)np, out, 0);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
 hub_status launch_lz_a(int dtype, void *w, const void *vprev, const double *beta, const void *v, int64_t n,
                        double *partial, double *alpha_out, hipStream_t st)
 {
