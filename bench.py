@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the 4x4-torus product timing")
     ap.add_argument("--copy-reference", type=int, default=0,
                     help="profiling aid: copy a buffer of this many MiB three times (counter calibration)")
+    ap.add_argument("--lanczos-only", type=str, default="",
+                    help="run one FP64 and one mixed solve of the named workload and exit (counter runs)")
     ap.add_argument("--matvec-only", type=str, default="",
                     help="profiling aid: 'workload:count' times count back-to-back products per dtype")
     return ap.parse_args()
@@ -180,6 +182,17 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(f"copied {args.copy_reference} MiB x3", flush=True)
+        return
+
+    if args.lanczos_only:
+        # the solver path alone (for counter runs of the fused product): one FP64 and one mixed solve
+        name = args.lanczos_only
+        sec = hub.Sector(W.config(name))
+        for dt in (F64, F32):
+            g = sec.ground_state(dtype=dt, want_vector=False, tol=1e-12 if dt == F64 else 1e-7)
+            torch.cuda.synchronize()
+            print(f"{name} lanczos dtype={'f64' if dt == F64 else 'f32'} iters={g.info['iters']}", flush=True)
+        sec.close()
         return
 
     if args.matvec_only:
