@@ -187,7 +187,7 @@ typedef struct hub_lanczos_opts {
     int32_t want_vector;   /* compute psi */
     int32_t refine;        /* FP64 Rayleigh quotient and residual (needs want_vector) */
     int32_t check_every;   /* host convergence test period; default 1 when <= 0 */
-    int32_t time_kernels;  /* record HIP events around every product launch */
+    int32_t time_kernels;  /* > 0: HIP events around every time_kernels-th product launch */
     double e0_target;      /* reference energy for seconds_to_target (used when e0_target_rel > 0) */
     double e0_target_rel;  /* record the first check with |theta - e0_target| <= rel |e0_target| */
 } hub_lanczos_opts;
@@ -203,10 +203,11 @@ typedef struct hub_lanczos_info {
     double true_residual;   /* ||H psi - E psi||_2 in FP64 (refine), else -1 */
     double seconds;         /* wall time of the call */
     double seconds_to_e0;   /* wall time until the Ritz test passed */
-    double matvec_ms;       /* summed event time of those products (time_kernels) */
+    double matvec_ms;       /* summed event time of the timed products (time_kernels) */
     int64_t matvec_bytes;   /* algorithmic bytes of one product: 2 dim s + tables */
     int32_t iters_to_target; /* steps when the lowest Ritz value first met the e0 target (-1: never / unused) */
     double seconds_to_target; /* wall time from entry until then (-1: never / unused) */
+    int32_t matvec_timed;   /* products whose time is in matvec_ms */
 } hub_lanczos_info;
 
 hub_status hub_ground_state(const hub_sector *sec, const hub_lanczos_opts *opts, double *e0, void *dev_psi,

@@ -62,6 +62,7 @@ class LanczosInfo(ctypes.Structure):
         ("residual", ctypes.c_double), ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double),
         ("seconds_to_e0", ctypes.c_double), ("matvec_ms", ctypes.c_double), ("matvec_bytes", ctypes.c_int64),
         ("iters_to_target", ctypes.c_int32), ("seconds_to_target", ctypes.c_double),
+        ("matvec_timed", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -276,7 +277,7 @@ class Sector:
 
     def ground_state(self, *, dtype: int = F64, reorth: bool = False, want_vector: bool = True,
                      refine: bool = False, max_iter: int = 400, tol: float = 0.0, seed: int = 7542,
-                     start=None, check_every: int = 1, time_kernels: bool = False, psi=None,
+                     start=None, check_every: int = 1, time_kernels: int = 0, psi=None,
                      stream=None, allow_not_converged: bool = False, e0_target: Optional[float] = None,
                      e0_target_rel: float = 0.0) -> GroundState:
         want = want_vector or refine

@@ -141,8 +141,8 @@ bool matvec_lz_available(const hub_sector *s, int dtype);
 int64_t matvec_lz_partials(const hub_sector *s);
 hub_status launch_matvec_lz(const hub_sector *s, int dtype, const void *x, void *w, const void *vprev,
                             const double *beta, double *apart, int64_t *npart, hipStream_t st);
-// sum of np partials in a fixed order into *out (one block)
-hub_status launch_sum(const double *partial, int64_t np, double *out, hipStream_t st);
+// sum of np partials in a fixed order into *out (one block); sqrt_result: its square root
+hub_status launch_sum(const double *partial, int64_t np, double *out, hipStream_t st, int sqrt_result = 0);
 hub_status launch_diagonal(const hub_sector *s, int dtype, void *out, hipStream_t st);
 int64_t matvec_bytes(const hub_sector *s, int dtype);
 
@@ -162,6 +162,17 @@ hub_status launch_lz_b(int dtype, void *w, const void *v, const double *alpha, i
                        double *beta_out, hipStream_t st);
 hub_status launch_lz_next(int dtype, const void *w, void *vnext, const double *beta, int64_t n,
                           hipStream_t st);
+// launch_lz_b with alpha formed inside the kernel from np partials (the value
+// launch_sum gives, also written to *alpha_out) and beta^2 partials left in
+// partial[0 .. red_grid(n)); launch_lz_next with beta formed from those
+// partials (written to *beta_out).  host_ab / host_step (device-visible pinned
+// host memory, or NULL): also store *alpha_k at host_ab[k] and beta at
+// host_ab[kmax + k + 1], then k + 1 at *host_step.
+hub_status launch_lz_b_sum(int dtype, void *w, const void *v, const double *apart, int64_t np, double *alpha_out,
+                          int64_t n, double *partial, hipStream_t st);
+hub_status launch_lz_next_sum(int dtype, const void *w, void *vnext, const double *partial, double *beta_out,
+                              int64_t n, hipStream_t st, double *host_ab = nullptr, int *host_step = nullptr,
+                              const double *alpha_k = nullptr, int k = 0, int kmax = 0);
 hub_status launch_lz_replay(int dtype, void *w, const void *vprev, const double *beta, const void *v,
                             const double *alpha, int64_t n, hipStream_t st);
 hub_status launch_psi_acc(int dtype, double *psi, const void *v, const double *ycoef, int64_t n, int first,

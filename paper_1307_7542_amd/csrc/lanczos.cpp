@@ -136,11 +136,24 @@ struct DevMem {
     }
 };
 
+// HIP events around sampled product launches: every `every`-th product when
+// on (an event record between two kernels delays the second by a few
+// microseconds, so timing every launch of a short product slows the solve).
 struct EventTimer {
     bool on = false;
+    int every = 1;
+    int seen = 0;
+    int timed = 0;
     hipStream_t st = nullptr;
     std::vector<hipEvent_t> ev;
     int used = 0;
+    bool sample()
+    {
+        if (!on) return false;
+        const bool t = (seen++ % every) == 0;
+        if (t) ++timed;
+        return t;
+    }
     ~EventTimer()
     {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -199,7 +212,8 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
 
     DevMem mem;
     EventTimer tm;
-    tm.on = o->time_kernels != 0;
+    tm.on = o->time_kernels > 0;
+    tm.every = std::max(1, o->time_kernels);
     tm.st = st;
 
     const int kmax = max_iter + 1;
@@ -248,9 +262,10 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         return HUB_OK;
     };
     auto product = [&](const void *x, void *y) -> hub_status {
-        HUB_TRY(tm.mark());
+        const bool timed = tm.sample();
+        if (timed) HUB_TRY(tm.mark());
         HUB_TRY(apply_h(s, dt, x, y, st));
-        HUB_TRY(tm.mark());
+        if (timed) HUB_TRY(tm.mark());
         inf.matvec_count++;
         return HUB_OK;
     };
@@ -260,17 +275,32 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     double *apart = nullptr;
     if (fused) HUB_TRY(mem.alloc((void **)&apart, sizeof(double) * (size_t)matvec_lz_partials(s)));
     if (fused) inf.matvec_bytes += (int64_t)es * n;  // the update's read of v_prev
+    // fused: alpha's per-column partials are left in apart[0 .. np_alpha) and
+    // summed by the w -= alpha v update (lz_b below); otherwise alpha goes to aout
+    int64_t np_alpha = 0;
     auto product_lz = [&](const void *x, void *y, const void *vp, const double *bk, double *aout) -> hub_status {
         if (fused) {
-            int64_t np = 0;
-            HUB_TRY(tm.mark());
-            HUB_TRY(launch_matvec_lz(s, dt, x, y, vp, bk, apart, &np, st));
-            HUB_TRY(tm.mark());
+            const bool timed = tm.sample();
+            if (timed) HUB_TRY(tm.mark());
+            HUB_TRY(launch_matvec_lz(s, dt, x, y, vp, bk, apart, &np_alpha, st));
+            if (timed) HUB_TRY(tm.mark());
             inf.matvec_count++;
-            return launch_sum(apart, np, aout, st);
+            return HUB_OK;
         }
         HUB_TRY(product(x, y));
         return launch_lz_a(dt, y, vp, bk, x, n, partial, aout, st);
+    };
+    // W -= alpha_k v with alpha_k written to *alpha_io (fused: formed from the
+    // product's partials, inside the update when they are few); beta^2 partials
+    // left in partial[0 .. red_grid(n)), their square-rooted sum in *beta_out if given
+    auto lz_b = [&](const void *vv, double *alpha_io, double *beta_out) -> hub_status {
+        if (fused && np_alpha <= 8192) {
+            HUB_TRY(launch_lz_b_sum(dt, W, vv, apart, np_alpha, alpha_io, n, partial, st));
+            if (beta_out) HUB_TRY(launch_sum(partial, red_grid(n), beta_out, st, 1));
+            return HUB_OK;
+        }
+        if (fused) HUB_TRY(launch_sum(apart, np_alpha, alpha_io, st));
+        return launch_lz_b(dt, W, vv, alpha_io, n, partial, beta_out, st);
     };
 
     HUB_TRY(make_start(Va));
@@ -281,12 +311,35 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     // asynchronous copy into pinned memory) before step k is enqueued, and the
     // host waits only for that copy.  A step finished after convergence is
     // discarded (its coefficients are never used).
+    //
+    // On the plain path (no reorthogonalisation, no reprojection) the
+    // normalisation kernel of step j itself stores alpha_j and beta_{j+1} into
+    // the pinned buffer and then publishes j + 1 in a pinned counter, so a check
+    // waits on host memory only: no copy and no event between the kernels.
     double *hpin = nullptr;  // pinned copy of dscal[0 .. 2 kmax + 1)
-    HUB_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * (size_t)(2 * kmax + 1)));
+    int *hflag = nullptr;    // pinned count of published steps
+    HUB_HIP(hipHostMalloc((void **)&hpin, sizeof(double) * (size_t)(2 * kmax + 1),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    // (kernels still queued on an early error return may write here: drain the stream first)
     struct PinGuard {
-        double *p;
-        ~PinGuard() { (void)hipHostFree(p); }
-    } pin_guard{hpin};
+        void *p;
+        hipStream_t st;
+        ~PinGuard()
+        {
+            if (!p) return;
+            (void)hipStreamSynchronize(st);
+            (void)hipHostFree(p);
+        }
+    } pin_guard{hpin, st}, flag_guard{nullptr, st};
+    HUB_HIP(hipHostMalloc((void **)&hflag, 64, hipHostMallocMapped | hipHostMallocCoherent));
+    flag_guard.p = hflag;
+    std::memset(hpin, 0, sizeof(double) * (size_t)(2 * kmax + 1));
+    __atomic_store_n(hflag, 0, __ATOMIC_RELEASE);
+    double *dpin = nullptr;
+    int *dflag = nullptr;
+    HUB_HIP(hipHostGetDevicePointer((void **)&dpin, hpin, 0));
+    HUB_HIP(hipHostGetDevicePointer((void **)&dflag, hflag, 0));
+    const bool publish = !reorth && !reproject;
     const double *ha = hpin, *hb = hpin + kmax;
     hipEvent_t copied;
     HUB_HIP(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
@@ -335,14 +388,32 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         HUB_HIP(hipEventRecord(copied, st));
         return HUB_OK;
     };
+    // publish mode: wait until steps 0 .. k-1 are published (a stream
+    // synchronisation after half a second of spinning surfaces device errors)
+    auto wait_published = [&](int k) -> hub_status {
+        const auto tw = clk::now();
+        unsigned spins = 0;
+        while (__atomic_load_n(hflag, __ATOMIC_ACQUIRE) < k) {
+            if ((++spins & 1023u) == 0 && clk::now() - tw > std::chrono::milliseconds(500)) {
+                HUB_HIP(hipStreamSynchronize(st));
+                if (__atomic_load_n(hflag, __ATOMIC_ACQUIRE) < k) {
+                    set_error("Lanczos: a step's coefficients were not published");
+                    return HUB_ERR_DEVICE;
+                }
+                break;
+            }
+            __builtin_ia32_pause();
+        }
+        return HUB_OK;
+    };
     for (int k = 0; k < max_iter; ++k) {
         const bool check_now = k >= 1 && (k % check_every) == 0;
-        if (check_now) HUB_TRY(fetch(k));
+        if (check_now && !publish) HUB_TRY(fetch(k));
         HUB_TRY(product_lz(v, W, v_prev, d_beta + k, d_alpha + k));
         if (reorth) {
             // classical Gram-Schmidt against every stored vector; the second pass
             // runs only when the first removed more than 1 - 1/sqrt(2) of the norm
-            HUB_TRY(launch_lz_b(dt, W, v, d_alpha + k, n, partial, d_misc + 8, st));
+            HUB_TRY(lz_b(v, d_alpha + k, d_misc + 8));
             HUB_HIP(hipMemcpyAsync(dQ, Q.data(), sizeof(void *) * Q.size(), hipMemcpyHostToDevice, st));
             HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, nullptr));
             HUB_TRY(launch_dot(dt, W, W, n, partial, d_misc + 9, 1, st));
@@ -351,18 +422,27 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             if (reproject) HUB_TRY(k0_project(s, dt, W, st));
             HUB_TRY(launch_dot(dt, W, W, n, partial, d_beta + k + 1, 1, st));
         } else {
-            HUB_TRY(launch_lz_b(dt, W, v, d_alpha + k, n, partial, d_beta + k + 1, st));
+            // beta_{k+1} is formed from the partials by the normalisation below
+            // (or here, on the last step); with reprojection, from the projected W
+            HUB_TRY(lz_b(v, d_alpha + k, nullptr));
             if (reproject) {
                 HUB_TRY(k0_project(s, dt, W, st));
                 HUB_TRY(launch_dot(dt, W, W, n, partial, d_beta + k + 1, 1, st));
             }
         }
+        const bool beta_pending = publish;
         const bool last = (k + 1 == max_iter);
         if (check_now) {
-            HUB_HIP(hipEventSynchronize(copied));  // step k keeps running meanwhile
+            // step k keeps running meanwhile
+            if (publish) {
+                HUB_TRY(wait_published(k));
+            } else {
+                HUB_HIP(hipEventSynchronize(copied));
+            }
             if (check(k)) break;
         }
         if (last) {
+            if (beta_pending) HUB_TRY(launch_sum(partial, red_grid(n), d_beta + k + 1, st, 1));
             HUB_TRY(fetch(k + 1));
             HUB_HIP(hipEventSynchronize(copied));
             check(k + 1);
@@ -375,7 +455,11 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         } else {
             vn = v_prev ? v_prev : spare;
         }
-        HUB_TRY(launch_lz_next(dt, W, vn, d_beta + k + 1, n, st));
+        if (beta_pending) {
+            HUB_TRY(launch_lz_next_sum(dt, W, vn, partial, d_beta + k + 1, n, st, dpin, dflag, d_alpha + k, k, kmax));
+        } else {
+            HUB_TRY(launch_lz_next(dt, W, vn, d_beta + k + 1, n, st));
+        }
         if (!reorth && !v_prev) spare = nullptr;
         v_prev = v;
         v = vn;
@@ -406,7 +490,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             for (int j = 0; j + 1 < m; ++j) {
                 if (fused) {
                     // same two roundings as the first pass: the fused update, then w -= alpha_j v
-                    HUB_TRY(product_lz(vc, W, vp, d_beta + j, d_misc + 10));
+                    HUB_TRY(product_lz(vc, W, vp, d_beta + j, nullptr));
                     HUB_TRY(launch_lz_b(dt, W, vc, d_alpha + j, n, partial, nullptr, st));
                 } else {
                     HUB_TRY(product(vc, W));
@@ -440,7 +524,10 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         }
     }
     HUB_HIP(hipStreamSynchronize(st));
-    if (tm.on) inf.matvec_ms = tm.total_ms();
+    if (tm.on) {
+        inf.matvec_ms = tm.total_ms();
+        inf.matvec_timed = tm.timed;
+    }
     inf.seconds = std::chrono::duration<double>(clk::now() - t0).count();
     if (e0_out) *e0_out = e0;
     if (info) *info = inf;

@@ -292,9 +292,10 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
     const int64_t cu64 = cu;
     const int lane = threadIdx.x & 63;
     const double bt = (EPI && E.vprev) ? *E.beta : 0.0;
-    // every lane of a wavefront runs the same iterations (the epilogue reduces over the wavefront)
-    for (int q = threadIdx.x; q - lane < nq; q += BS) {
-        const bool live = q < nq;
+    // with the epilogue every lane of a wavefront runs the same iterations (it
+    // reduces over the wavefront); without it a lane stops after its last quad
+    for (int q = threadIdx.x; EPI ? (q - lane < nq) : (q < nq); q += BS) {
+        const bool live = !EPI || q < nq;
         const int a0 = 4 * (live ? q : 0);
         T acc[4][TB];
         const uint4 ub = *reinterpret_cast<const uint4 *>(A.up_basis + a0);

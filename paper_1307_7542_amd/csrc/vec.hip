@@ -61,13 +61,22 @@ __global__ __launch_bounds__(RB) void k_dot(const T *__restrict__ x, const T *__
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
+// Sum of partial[0 .. np) in a fixed order by one block of RB threads.  Every
+// block that calls it obtains the same value, so a kernel that needs the total
+// of a previous kernel's partials can form it per block instead of waiting for
+// a separate single-block launch.
+__device__ __forceinline__ double block_total(const double *__restrict__ partial, int np, double *s)
+{
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += RB) acc += partial[i];
+    return block_sum(acc, s);
+}
+
 __global__ __launch_bounds__(RB) void k_final(const double *__restrict__ partial, int np, double *__restrict__ out,
                                               int sqrt_result)
 {
     __shared__ double s[RB];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < np; i += RB) acc += partial[i];
-    const double r = block_sum(acc, s);
+    const double r = block_total(partial, np, s);
     if (threadIdx.x == 0) *out = sqrt_result ? sqrt(r) : r;
 }
 
@@ -200,6 +209,80 @@ __device__ __forceinline__ void st_e4(T *p, const T (&v)[4])
         reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
         reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
     }
+}
+
+// k_lz_b with alpha = the sum of the product's per-column partials (the value
+// k_final would give), written to *alpha_out by block 0.  Lanes take four
+// consecutive elements (16-byte aligned vectors), block 0 also the n % 4 tail.
+template <typename T>
+__global__ __launch_bounds__(RB) void k_lz_b_sum(T *__restrict__ w, const T *__restrict__ v,
+                                                 const double *__restrict__ apart, int np,
+                                                 double *__restrict__ alpha_out, int64_t n,
+                                                 double *__restrict__ partial)
+{
+    __shared__ double s[RB];
+    const double al = block_total(apart, np, s);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = al;
+    double acc = 0.0;
+    const int64_t n4 = n >> 2;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n4; i += (int64_t)gridDim.x * RB) {
+        const E4<T> wv = ld_e4(w + 4 * i), vv = ld_e4(v + 4 * i);
+        T o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            o[r] = (T)((double)wv.v[r] - al * (double)vv.v[r]);
+            acc += (double)o[r] * (double)o[r];
+        }
+        st_e4(w + 4 * i, o);
+    }
+    if (blockIdx.x == 0)
+        for (int64_t i = 4 * n4 + threadIdx.x; i < n; i += RB) {
+            const T wi = (T)((double)w[i] - al * (double)v[i]);
+            w[i] = wi;
+            acc += (double)wi * (double)wi;
+        }
+    const double r = block_sum(acc, s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// k_lz_next with beta = sqrt(sum of k_lz_b's partials), written to *beta_out by
+// block 0; the same element layout as k_lz_b_sum.  When `pub` is set, block 0
+// also publishes alpha_k and beta_{k+1} to host memory and then the step count
+// k + 1, so the host can follow the recurrence without a copy or an event.
+struct HostPublish {
+    double *ab;           // host (device-visible) alpha[0 .. kmax) then beta[0 .. kmax]
+    int *step;            // host (device-visible) count of published steps
+    const double *alpha;  // device alpha_k
+    int k, kmax;
+};
+
+template <typename T>
+__global__ __launch_bounds__(RB) void k_lz_next_sum(const T *__restrict__ w, T *__restrict__ vnext,
+                                                    const double *__restrict__ partial, int np,
+                                                    double *__restrict__ beta_out, int64_t n, HostPublish pub)
+{
+    __shared__ double s[RB];
+    const double bt = sqrt(block_total(partial, np, s));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *beta_out = bt;
+        if (pub.ab) {
+            volatile double *ab = pub.ab;
+            ab[pub.k] = *pub.alpha;
+            ab[pub.kmax + pub.k + 1] = bt;
+            __threadfence_system();
+            *(volatile int *)pub.step = pub.k + 1;
+        }
+    }
+    const int64_t n4 = n >> 2;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n4; i += (int64_t)gridDim.x * RB) {
+        const E4<T> wv = ld_e4(w + 4 * i);
+        T o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = (bt > 0.0) ? (T)((double)wv.v[r] / bt) : (T)0;
+        st_e4(vnext + 4 * i, o);
+    }
+    if (blockIdx.x == 0)
+        for (int64_t i = 4 * n4 + threadIdx.x; i < n; i += RB) vnext[i] = (bt > 0.0) ? (T)((double)w[i] / bt) : (T)0;
 }
 
 // partial[block * kstride + j] = sum over the block's elements of q_j * w, for
@@ -443,9 +526,9 @@ hub_status launch_convert(int din, const void *x, int dout, void *y, int64_t n, 
     return HUB_OK;
 }
 
-hub_status launch_sum(const double *partial, int64_t np, double *out, hipStream_t st)
+hub_status launch_sum(const double *partial, int64_t np, double *out, hipStream_t st, int sqrt_result)
 {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, (int)np, out, 0);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, (int)np, out, sqrt_result);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
@@ -476,6 +559,44 @@ hub_status launch_lz_b(int dtype, void *w, const void *v, const double *alpha, i
         hipLaunchKernelGGL(k_lz_b<float>, dim3(G), dim3(RB), 0, st, (float *)w, (const float *)v, alpha, n,
                            partial);
     if (beta_out) hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, G, beta_out, 1);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_lz_b_sum(int dtype, void *w, const void *v, const double *apart, int64_t np, double *alpha_out,
+                          int64_t n, double *partial, hipStream_t st)
+{
+    if (((uintptr_t)w | (uintptr_t)v) % 16) {
+        set_error("lz_b_sum: vectors must be 16-byte aligned");
+        return HUB_ERR_INVALID_ARG;
+    }
+    const int G = red_grid(n);
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_lz_b_sum<double>, dim3(G), dim3(RB), 0, st, (double *)w, (const double *)v, apart,
+                           (int)np, alpha_out, n, partial);
+    else
+        hipLaunchKernelGGL(k_lz_b_sum<float>, dim3(G), dim3(RB), 0, st, (float *)w, (const float *)v, apart,
+                           (int)np, alpha_out, n, partial);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_lz_next_sum(int dtype, const void *w, void *vnext, const double *partial, double *beta_out,
+                              int64_t n, hipStream_t st, double *host_ab, int *host_step, const double *alpha_k,
+                              int k, int kmax)
+{
+    const HostPublish pub{host_ab, host_step, alpha_k, k, kmax};
+    if (((uintptr_t)w | (uintptr_t)vnext) % 16) {
+        set_error("lz_next_sum: vectors must be 16-byte aligned");
+        return HUB_ERR_INVALID_ARG;
+    }
+    const int G = red_grid(n);
+    if (dtype == HUB_F64)
+        hipLaunchKernelGGL(k_lz_next_sum<double>, dim3(G), dim3(RB), 0, st, (const double *)w, (double *)vnext,
+                           partial, G, beta_out, n, pub);
+    else
+        hipLaunchKernelGGL(k_lz_next_sum<float>, dim3(G), dim3(RB), 0, st, (const float *)w, (float *)vnext,
+                           partial, G, beta_out, n, pub);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }

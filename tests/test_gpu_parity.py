@@ -524,3 +524,28 @@ def test_time_to_target_energy(hub):
     g4 = s.ground_state(dtype=hub.F64, tol=1e-12, want_vector=False, e0_target=e_ref - 1.0, e0_target_rel=1e-6)
     assert g4.info["iters_to_target"] == -1
     s.close()
+
+
+@pytest.mark.parametrize("which", ["ring12_u3", "square3x4_n5"])
+def test_sampled_kernel_timing_leaves_results_unchanged(hub, which):
+    """Timing every N-th product with HIP events changes no arithmetic: the
+    energies and the eigenvector are bitwise those of an untimed solve, and the
+    number of timed launches is ceil(products / N)."""
+    import torch
+    if which == "ring12_u3":
+        m = W.ring(12, U=3.0, n_up=6, n_dn=6)
+    else:
+        m = W.square_periodic(3, 4, n_up=5, n_dn=5)
+    s = hub.Sector(m)
+    for dt in (hub.F64, hub.F32):
+        kw = dict(dtype=dt, tol=1e-12 if dt == hub.F64 else 1e-7, want_vector=True, refine=True)
+        g0 = s.ground_state(**kw)
+        for every in (1, 3):
+            g = s.ground_state(time_kernels=every, **kw)
+            assert g.e0 == g0.e0 and g.info["e0_ritz"] == g0.info["e0_ritz"]
+            assert torch.equal(g.psi, g0.psi)
+            cnt = g.info["matvec_count"]
+            assert g.info["matvec_timed"] == (cnt + every - 1) // every
+            assert g.info["matvec_ms"] > 0.0
+        assert g0.info["matvec_timed"] == 0 and g0.info["matvec_ms"] == 0.0
+    s.close()
