@@ -136,11 +136,15 @@ hub_status rank_device(const hub_sector *s, int spin, const uint64_t *dx, int64_
 hub_status launch_matvec(const hub_sector *s, int dtype, const void *x, void *y, hipStream_t st);
 // Product fused with the first Lanczos update: w = H x - beta v_prev (v_prev may
 // be NULL) and partial sums of <w, x> in apart (npart values, summed in order
-// they give alpha).  Available when matvec_lz_available(s, dtype).
+// they give alpha).  unnorm: x and v_prev are the unnormalised vectors
+// beta_k v_k and beta_{k-1} v_{k-1} (beta NULL at the first step, beta_prev
+// NULL for beta_0 = 1), w = (H x) / beta_k - (beta_k / beta_{k-1}) v_prev and
+// the partials sum to beta_k alpha_k.  Available when matvec_lz_available(s, dtype).
 bool matvec_lz_available(const hub_sector *s, int dtype);
 int64_t matvec_lz_partials(const hub_sector *s);
 hub_status launch_matvec_lz(const hub_sector *s, int dtype, const void *x, void *w, const void *vprev,
-                            const double *beta, double *apart, int64_t *npart, hipStream_t st);
+                            const double *beta, double *apart, int64_t *npart, hipStream_t st,
+                            const double *beta_prev = nullptr, int unnorm = 0);
 // sum of np partials in a fixed order into *out (one block); sqrt_result: its square root
 hub_status launch_sum(const double *partial, int64_t np, double *out, hipStream_t st, int sqrt_result = 0);
 hub_status launch_diagonal(const hub_sector *s, int dtype, void *out, hipStream_t st);
@@ -158,8 +162,9 @@ hub_status launch_convert(int din, const void *x, int dout, void *y, int64_t n, 
                           int invert, hipStream_t st);
 hub_status launch_lz_a(int dtype, void *w, const void *vprev, const double *beta, const void *v, int64_t n,
                        double *partial, double *alpha_out, hipStream_t st);
+// beta_div (may be NULL): v is the unnormalised beta_k v_k, subtract (alpha / beta_k) v
 hub_status launch_lz_b(int dtype, void *w, const void *v, const double *alpha, int64_t n, double *partial,
-                       double *beta_out, hipStream_t st);
+                       double *beta_out, hipStream_t st, const double *beta_div = nullptr);
 hub_status launch_lz_next(int dtype, const void *w, void *vnext, const double *beta, int64_t n,
                           hipStream_t st);
 // launch_lz_b with alpha formed inside the kernel from np partials (the value
@@ -169,14 +174,19 @@ hub_status launch_lz_next(int dtype, const void *w, void *vnext, const double *b
 // host memory, or NULL): also store *alpha_k at host_ab[k] and beta at
 // host_ab[kmax + k + 1], then k + 1 at *host_step.
 hub_status launch_lz_b_sum(int dtype, void *w, const void *v, const double *apart, int64_t np, double *alpha_out,
-                          int64_t n, double *partial, hipStream_t st);
+                          int64_t n, double *partial, hipStream_t st, const double *beta_k = nullptr,
+                          int unnorm = 0);
+// beta = sqrt(sum of the red_grid(n) partials) into *beta_out, published like launch_lz_next_sum (one block)
+hub_status launch_beta_pub(const double *partial, int64_t n, double *beta_out, hipStream_t st, double *host_ab,
+                           int *host_step, const double *alpha_k, int k, int kmax);
 hub_status launch_lz_next_sum(int dtype, const void *w, void *vnext, const double *partial, double *beta_out,
                               int64_t n, hipStream_t st, double *host_ab = nullptr, int *host_step = nullptr,
                               const double *alpha_k = nullptr, int k = 0, int kmax = 0);
 hub_status launch_lz_replay(int dtype, void *w, const void *vprev, const double *beta, const void *v,
                             const double *alpha, int64_t n, hipStream_t st);
+// psi (= 0 if first) += ycoef[0] * v, or ycoef[0] / div[0] * v when div is given
 hub_status launch_psi_acc(int dtype, double *psi, const void *v, const double *ycoef, int64_t n, int first,
-                          hipStream_t st);
+                          hipStream_t st, const double *div = nullptr);
 hub_status launch_gram(int dtype, const void *const *dQ, int k, void *w, int64_t n, double *partial,
                        double *coef, hipStream_t st, const int *skip);
 hub_status launch_dgks_flag(const double *before, const double *after, int *flag, hipStream_t st);

@@ -278,11 +278,12 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     // fused: alpha's per-column partials are left in apart[0 .. np_alpha) and
     // summed by the w -= alpha v update (lz_b below); otherwise alpha goes to aout
     int64_t np_alpha = 0;
-    auto product_lz = [&](const void *x, void *y, const void *vp, const double *bk, double *aout) -> hub_status {
+    auto product_lz = [&](const void *x, void *y, const void *vp, const double *bk, double *aout,
+                          const double *bprev = nullptr, int un = 0) -> hub_status {
         if (fused) {
             const bool timed = tm.sample();
             if (timed) HUB_TRY(tm.mark());
-            HUB_TRY(launch_matvec_lz(s, dt, x, y, vp, bk, apart, &np_alpha, st));
+            HUB_TRY(launch_matvec_lz(s, dt, x, y, vp, bk, apart, &np_alpha, st, bprev, un));
             if (timed) HUB_TRY(tm.mark());
             inf.matvec_count++;
             return HUB_OK;
@@ -305,6 +306,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
 
     HUB_TRY(make_start(Va));
     void *v_prev = nullptr, *v = Va, *spare = Vb;
+    void *const B0 = Va, *const B1 = Vb, *const B2 = W;  // the three vector buffers
 
     // Convergence checks run on the host while the GPU computes the next step:
     // at a check step k, alpha_0..alpha_{k-1} and beta_1..beta_k are copied (one
@@ -340,6 +342,11 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     HUB_HIP(hipHostGetDevicePointer((void **)&dpin, hpin, 0));
     HUB_HIP(hipHostGetDevicePointer((void **)&dflag, hflag, 0));
     const bool publish = !reorth && !reproject;
+    // Plain fused path: the vectors stay unnormalised, u_k = beta_k v_k (u_0 = v_0).
+    // The product's epilogue and the update scale by 1 / beta_k in FP64, so no
+    // normalisation pass is needed; a step is the fused product, the update and a
+    // one-block kernel that forms and publishes beta_{k+1}.
+    const bool unnorm = fused && publish && matvec_lz_partials(s) <= 8192;
     const double *ha = hpin, *hb = hpin + kmax;
     hipEvent_t copied;
     HUB_HIP(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
@@ -406,7 +413,31 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         }
         return HUB_OK;
     };
-    for (int k = 0; k < max_iter; ++k) {
+    for (int k = 0; unnorm && k < max_iter; ++k) {
+        const bool check_now = k >= 1 && (k % check_every) == 0;
+        const double *bk = k >= 1 ? d_beta + k : nullptr, *bprev = k >= 2 ? d_beta + k - 1 : nullptr;
+        HUB_TRY(product_lz(v, W, v_prev, bk, nullptr, bprev, 1));
+        HUB_TRY(launch_lz_b_sum(dt, W, v, apart, np_alpha, d_alpha + k, n, partial, st, bk, 1));
+        if (check_now) {
+            HUB_TRY(wait_published(k));  // step k keeps running meanwhile
+            if (check(k)) break;
+        }
+        if (k + 1 == max_iter) {
+            HUB_TRY(launch_sum(partial, red_grid(n), d_beta + k + 1, st, 1));
+            HUB_TRY(fetch(k + 1));
+            HUB_HIP(hipEventSynchronize(copied));
+            check(k + 1);
+            break;
+        }
+        HUB_TRY(launch_beta_pub(partial, n, d_beta + k + 1, st, dpin, dflag, d_alpha + k, k, kmax));
+        // W now holds u_{k+1}; the oldest buffer becomes the next output
+        void *freed = v_prev ? v_prev : spare;
+        if (!v_prev) spare = nullptr;
+        v_prev = v;
+        v = W;
+        W = freed;
+    }
+    for (int k = 0; !unnorm && k < max_iter; ++k) {
         const bool check_now = k >= 1 && (k % check_every) == 0;
         if (check_now && !publish) HUB_TRY(fetch(k));
         HUB_TRY(product_lz(v, W, v_prev, d_beta + k, d_alpha + k));
@@ -481,6 +512,23 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         if (reorth) {
             HUB_HIP(hipMemcpyAsync(dQ, Q.data(), sizeof(void *) * Q.size(), hipMemcpyHostToDevice, st));
             HUB_TRY(launch_psi_from_basis(dt, (const void *const *)dQ, m, d_y, psi, n, st));
+        } else if (unnorm) {
+            // second pass over the same unnormalised recurrence: psi = sum_j (y_j / beta_j) u_j
+            W = B2;
+            void *u = B0, *up = nullptr, *wb = B1, *sp = B2;
+            HUB_TRY(make_start(u));
+            HUB_TRY(launch_psi_acc(dt, psi, u, d_y, n, 1, st));
+            for (int j = 0; j + 1 < m; ++j) {
+                const double *bj = j >= 1 ? d_beta + j : nullptr, *bjp = j >= 2 ? d_beta + j - 1 : nullptr;
+                HUB_TRY(product_lz(u, wb, up, bj, nullptr, bjp, 1));
+                HUB_TRY(launch_lz_b(dt, wb, u, d_alpha + j, n, partial, nullptr, st, bj));
+                HUB_TRY(launch_psi_acc(dt, psi, wb, d_y + j + 1, n, 0, st, d_beta + j + 1));
+                void *freed = up ? up : sp;
+                if (!up) sp = nullptr;
+                up = u;
+                u = wb;
+                wb = freed;
+            }
         } else {
             // second pass over the same recurrence with the stored alpha / beta
             void *a = Va, *b = Vb;

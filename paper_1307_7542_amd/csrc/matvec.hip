@@ -234,13 +234,27 @@ __device__ __forceinline__ void st_q4(T *p, const T (&v)[4])
 // each group of 64 lane-quads (256 rows) is summed by one wavefront in a fixed
 // order, then the groups of a column in increasing order, so the per-column
 // partials do not depend on the tile shape.
+//
+// unnorm: the Lanczos vectors are kept unnormalised, x = beta_k v_k and
+// vprev = beta_{k-1} v_{k-1} (beta_0 taken as 1, beta NULL at the first step),
+// and the epilogue forms w = (H x) / beta_k - (beta_k / beta_{k-1}) vprev in
+// FP64 before the one rounding; the partials are then of <w, x> = beta_k alpha_k.
 template <typename T>
 struct LzEpi {
-    const T *vprev;       // NULL at the first step
-    const double *beta;   // beta_k (device)
-    double *apart;        // [cd] per-column partials
-    int G;                // lane-quad groups per column: ceil(count_up / 256)
+    const T *vprev;           // NULL at the first step
+    const double *beta;       // beta_k (device)
+    double *apart;            // [cd] per-column partials
+    int G;                    // lane-quad groups per column: ceil(count_up / 256)
+    const double *beta_prev;  // unnorm: beta_{k-1} (device), NULL for beta_0
+    int unnorm;
 };
+
+__device__ __forceinline__ double inv_beta(const double *b)
+{
+    if (!b) return 1.0;
+    const double v = *b;
+    return v > 0.0 ? 1.0 / v : 0.0;
+}
 
 __device__ __forceinline__ double quad_wave_sum(double v)
 {
@@ -291,7 +305,15 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
     }
     const int64_t cu64 = cu;
     const int lane = threadIdx.x & 63;
-    const double bt = (EPI && E.vprev) ? *E.beta : 0.0;
+    double bt = 0.0, sx = 1.0;
+    if (EPI) {
+        if (E.unnorm) {
+            sx = inv_beta(E.beta);
+            bt = E.vprev ? *E.beta * inv_beta(E.beta_prev) : 0.0;
+        } else if (E.vprev) {
+            bt = *E.beta;
+        }
+    }
     // with the epilogue every lane of a wavefront runs the same iterations (it
     // reduces over the wavefront); without it a lane stops after its last quad
     for (int q = threadIdx.x; EPI ? (q - lane < nq) : (q < nq); q += BS) {
@@ -362,7 +384,16 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
             if (EPI) {
                 double part = 0.0;
                 if (live) {
-                    if (E.vprev) {
+                    if (E.unnorm) {
+                        if (E.vprev) {
+                            const Q4<T> vp = ld_q4(E.vprev + (int64_t)(b0 + t) * cu64 + a0);
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) o[r] = (T)(sx * (double)o[r] - bt * (double)vp.v[r]);
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) o[r] = (T)(sx * (double)o[r]);
+                        }
+                    } else if (E.vprev) {
                         const Q4<T> vp = ld_q4(E.vprev + (int64_t)(b0 + t) * cu64 + a0);
 #pragma unroll
                         for (int r = 0; r < 4; ++r) o[r] = (T)((double)o[r] - bt * (double)vp.v[r]);
@@ -936,7 +967,7 @@ template <typename T, int TB, int BS, bool XC>
 hub_status launch_quad_t(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const LzEpi<T> *E)
 {
     if (E) return launch_quad_e<T, TB, BS, XC, true>(s, A, st, *E);
-    return launch_quad_e<T, TB, BS, XC, false>(s, A, st, LzEpi<T>{nullptr, nullptr, nullptr, 0});
+    return launch_quad_e<T, TB, BS, XC, false>(s, A, st, LzEpi<T>{nullptr, nullptr, nullptr, 0, nullptr, 0});
 }
 
 // shape code: TB in 1..3, BS in {512, 1024}, XC in {0, 1}; E: fused Lanczos epilogue or NULL
@@ -1055,14 +1086,14 @@ bool lz_fusable(const hub_sector *s)
 
 template <typename T>
 hub_status run_kron_lz(const hub_sector *s, const void *x, void *w, const void *vprev, const double *beta,
-                       double *apart, int64_t *npart, hipStream_t st)
+                       const double *beta_prev, int unnorm, double *apart, int64_t *npart, hipStream_t st)
 {
     if (!lz_fusable<T>(s)) return HUB_ERR_UNSUPPORTED;
     MvArgs<T> A = make_args<T>(s, x, w);
     QuadShape q;
     HUB_TRY(quad_shape<T>(s, A, st, q));
     const int G = (int)(((A.cu >> 2) + 63) / 64);
-    const LzEpi<T> E{(const T *)vprev, beta, apart, G};
+    const LzEpi<T> E{(const T *)vprev, beta, apart, G, beta_prev, unnorm};
     *npart = (int64_t)A.cd;
     // the group partials need TB * G doubles of LDS beside the columns: fall back to fewer columns
     for (int tb = q.tb; tb >= 1; --tb) {
@@ -1170,10 +1201,11 @@ int64_t matvec_lz_partials(const hub_sector *s)
 }
 
 hub_status launch_matvec_lz(const hub_sector *s, int dtype, const void *x, void *w, const void *vprev,
-                            const double *beta, double *apart, int64_t *npart, hipStream_t st)
+                            const double *beta, double *apart, int64_t *npart, hipStream_t st,
+                            const double *beta_prev, int unnorm)
 {
-    if (dtype == HUB_F64) return run_kron_lz<double>(s, x, w, vprev, beta, apart, npart, st);
-    return run_kron_lz<float>(s, x, w, vprev, beta, apart, npart, st);
+    if (dtype == HUB_F64) return run_kron_lz<double>(s, x, w, vprev, beta, beta_prev, unnorm, apart, npart, st);
+    return run_kron_lz<float>(s, x, w, vprev, beta, beta_prev, unnorm, apart, npart, st);
 }
 
 hub_status launch_diagonal(const hub_sector *s, int dtype, void *out, hipStream_t st)

@@ -31,6 +31,15 @@ __device__ __forceinline__ double block_sum(double v, double *s)
     return r;
 }
 
+// 1 / beta for a device beta (NULL: 1, beta <= 0: 0); the scale that turns an
+// unnormalised Lanczos vector beta_k v_k back into v_k
+__device__ __forceinline__ double inv_beta(const double *b)
+{
+    if (!b) return 1.0;
+    const double v = *b;
+    return v > 0.0 ? 1.0 / v : 0.0;
+}
+
 __device__ __forceinline__ double splitmix_entry(uint64_t seed, int64_t k)
 {
     // SplitMix64 (Steele, Lea & Flood 2014) output for state seed + (k+1) gamma,
@@ -111,14 +120,15 @@ __global__ __launch_bounds__(RB) void k_lz_a(T *__restrict__ w, const T *__restr
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
-// w <- w - alpha * v ; partial beta^2 = <w, w>
+// w <- w - alpha * v ; partial beta^2 = <w, w>.  beta_div (may be NULL): v is
+// the unnormalised beta_k v_k and the coefficient is alpha / beta_k.
 template <typename T>
 __global__ __launch_bounds__(RB) void k_lz_b(T *__restrict__ w, const T *__restrict__ v,
                                              const double *__restrict__ alpha, int64_t n,
-                                             double *__restrict__ partial)
+                                             double *__restrict__ partial, const double *__restrict__ beta_div)
 {
     __shared__ double s[RB];
-    const double al = *alpha;
+    const double al = beta_div ? *alpha * inv_beta(beta_div) : *alpha;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
         const T wi = (T)((double)w[i] - al * (double)v[i]);
@@ -153,9 +163,9 @@ __global__ void k_lz_replay(T *__restrict__ w, const T *__restrict__ vprev, cons
 
 template <typename T>
 __global__ void k_psi_acc(double *__restrict__ psi, const T *__restrict__ v, const double *__restrict__ y, int64_t n,
-                          int first)
+                          int first, const double *__restrict__ div)
 {
-    const double c = *y;
+    const double c = div ? *y * inv_beta(div) : *y;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         psi[i] = (first ? 0.0 : psi[i]) + c * (double)v[i];
 }
@@ -214,15 +224,22 @@ __device__ __forceinline__ void st_e4(T *p, const T (&v)[4])
 // k_lz_b with alpha = the sum of the product's per-column partials (the value
 // k_final would give), written to *alpha_out by block 0.  Lanes take four
 // consecutive elements (16-byte aligned vectors), block 0 also the n % 4 tail.
+//
+// unnorm: v is the unnormalised beta_k v_k (beta_k NULL at the first step) and
+// the partials sum to beta_k alpha_k: alpha_k = that sum / beta_k, and the
+// update subtracts (alpha_k / beta_k) v, leaving the unnormalised beta_{k+1} v_{k+1}.
 template <typename T>
 __global__ __launch_bounds__(RB) void k_lz_b_sum(T *__restrict__ w, const T *__restrict__ v,
                                                  const double *__restrict__ apart, int np,
                                                  double *__restrict__ alpha_out, int64_t n,
-                                                 double *__restrict__ partial)
+                                                 double *__restrict__ partial, const double *__restrict__ beta_k,
+                                                 int unnorm)
 {
     __shared__ double s[RB];
-    const double al = block_total(apart, np, s);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = al;
+    const double tot = block_total(apart, np, s);
+    const double alpha = unnorm ? tot * inv_beta(beta_k) : tot;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = alpha;
+    const double al = unnorm ? alpha * inv_beta(beta_k) : alpha;
     double acc = 0.0;
     const int64_t n4 = n >> 2;
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n4; i += (int64_t)gridDim.x * RB) {
@@ -283,6 +300,25 @@ __global__ __launch_bounds__(RB) void k_lz_next_sum(const T *__restrict__ w, T *
     }
     if (blockIdx.x == 0)
         for (int64_t i = 4 * n4 + threadIdx.x; i < n; i += RB) vnext[i] = (bt > 0.0) ? (T)((double)w[i] / bt) : (T)0;
+}
+
+// beta_{k+1} = sqrt(sum of the update's partials) into *beta_out, and the same
+// publication to host memory as k_lz_next_sum (one block)
+__global__ __launch_bounds__(RB) void k_beta_pub(const double *__restrict__ partial, int np,
+                                                 double *__restrict__ beta_out, HostPublish pub)
+{
+    __shared__ double s[RB];
+    const double bt = sqrt(block_total(partial, np, s));
+    if (threadIdx.x == 0) {
+        *beta_out = bt;
+        if (pub.ab) {
+            volatile double *ab = pub.ab;
+            ab[pub.k] = *pub.alpha;
+            ab[pub.kmax + pub.k + 1] = bt;
+            __threadfence_system();
+            *(volatile int *)pub.step = pub.k + 1;
+        }
+    }
 }
 
 // partial[block * kstride + j] = sum over the block's elements of q_j * w, for
@@ -549,22 +585,22 @@ hub_status launch_lz_a(int dtype, void *w, const void *vprev, const double *beta
 }
 
 hub_status launch_lz_b(int dtype, void *w, const void *v, const double *alpha, int64_t n, double *partial,
-                       double *beta_out, hipStream_t st)
+                       double *beta_out, hipStream_t st, const double *beta_div)
 {
     const int G = red_grid(n);
     if (dtype == HUB_F64)
         hipLaunchKernelGGL(k_lz_b<double>, dim3(G), dim3(RB), 0, st, (double *)w, (const double *)v, alpha, n,
-                           partial);
+                           partial, beta_div);
     else
         hipLaunchKernelGGL(k_lz_b<float>, dim3(G), dim3(RB), 0, st, (float *)w, (const float *)v, alpha, n,
-                           partial);
+                           partial, beta_div);
     if (beta_out) hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, G, beta_out, 1);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
 
 hub_status launch_lz_b_sum(int dtype, void *w, const void *v, const double *apart, int64_t np, double *alpha_out,
-                          int64_t n, double *partial, hipStream_t st)
+                          int64_t n, double *partial, hipStream_t st, const double *beta_k, int unnorm)
 {
     if (((uintptr_t)w | (uintptr_t)v) % 16) {
         set_error("lz_b_sum: vectors must be 16-byte aligned");
@@ -573,10 +609,10 @@ hub_status launch_lz_b_sum(int dtype, void *w, const void *v, const double *apar
     const int G = red_grid(n);
     if (dtype == HUB_F64)
         hipLaunchKernelGGL(k_lz_b_sum<double>, dim3(G), dim3(RB), 0, st, (double *)w, (const double *)v, apart,
-                           (int)np, alpha_out, n, partial);
+                           (int)np, alpha_out, n, partial, beta_k, unnorm);
     else
         hipLaunchKernelGGL(k_lz_b_sum<float>, dim3(G), dim3(RB), 0, st, (float *)w, (const float *)v, apart,
-                           (int)np, alpha_out, n, partial);
+                           (int)np, alpha_out, n, partial, beta_k, unnorm);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
@@ -597,6 +633,15 @@ hub_status launch_lz_next_sum(int dtype, const void *w, void *vnext, const doubl
     else
         hipLaunchKernelGGL(k_lz_next_sum<float>, dim3(G), dim3(RB), 0, st, (const float *)w, (float *)vnext,
                            partial, G, beta_out, n, pub);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_beta_pub(const double *partial, int64_t n, double *beta_out, hipStream_t st, double *host_ab,
+                           int *host_step, const double *alpha_k, int k, int kmax)
+{
+    const HostPublish pub{host_ab, host_step, alpha_k, k, kmax};
+    hipLaunchKernelGGL(k_beta_pub, dim3(1), dim3(RB), 0, st, partial, red_grid(n), beta_out, pub);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
@@ -627,14 +672,14 @@ hub_status launch_lz_replay(int dtype, void *w, const void *vprev, const double 
 }
 
 hub_status launch_psi_acc(int dtype, double *psi, const void *v, const double *ycoef, int64_t n, int first,
-                          hipStream_t st)
+                          hipStream_t st, const double *div)
 {
     if (dtype == HUB_F64)
         hipLaunchKernelGGL(k_psi_acc<double>, dim3(ew_grid(n)), dim3(256), 0, st, psi, (const double *)v, ycoef, n,
-                           first);
+                           first, div);
     else
         hipLaunchKernelGGL(k_psi_acc<float>, dim3(ew_grid(n)), dim3(256), 0, st, psi, (const float *)v, ycoef, n,
-                           first);
+                           first, div);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
