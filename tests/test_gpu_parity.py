@@ -549,3 +549,38 @@ def test_sampled_kernel_timing_leaves_results_unchanged(hub, which):
             assert g.info["matvec_ms"] > 0.0
         assert g0.info["matvec_timed"] == 0 and g0.info["matvec_ms"] == 0.0
     s.close()
+
+
+def test_unnormalised_recurrence_matches_normalised(hub, monkeypatch):
+    """The plain fused path keeps beta_k v_k instead of v_k; the energies and the
+    eigenvector agree with the normalised, unfused recurrence (HUB_LZ_FUSE=0)."""
+    import torch
+    m = W.ring(12, U=3.0, n_up=6, n_dn=6).with_params(eps=[0.05 * ((7 * i) % 12) for i in range(12)])
+    s = hub.Sector(m)
+    assert s.count_up % 4 == 0
+    for dt, tol_e, tol_v in ((hub.F64, 1e-12, 1e-9), (hub.F32, 1e-9, 1e-5)):
+        kw = dict(dtype=dt, tol=1e-12 if dt == hub.F64 else 1e-7, want_vector=True, refine=True)
+        g_un = s.ground_state(**kw)
+        monkeypatch.setenv("HUB_LZ_FUSE", "0")
+        g_no = s.ground_state(**kw)
+        monkeypatch.delenv("HUB_LZ_FUSE")
+        assert abs(g_un.e0 - g_no.e0) <= tol_e * abs(g_no.e0), (dt, g_un.e0, g_no.e0)
+        ov = float(torch.dot(g_un.psi, g_no.psi))
+        assert abs(ov) >= 1.0 - tol_v, (dt, ov)
+        assert g_un.info["true_residual"] <= (1e-9 if dt == hub.F64 else 1e-5) * abs(g_un.e0)
+    s.close()
+
+
+def test_unnormalised_recurrence_breakdown(hub):
+    """t = 0 on a sector the fused product handles: H = D has seven distinct
+    values, so the recurrence breaks down early; E0 = 0 (a state without double
+    occupancy exists at half filling) on both precisions."""
+    m = W.ring(12, t=0.0, U=2.0, n_up=6, n_dn=6)
+    s = hub.Sector(m)
+    assert s.count_up % 4 == 0
+    for dt in (hub.F64, hub.F32):
+        g = s.ground_state(dtype=dt, want_vector=True, refine=True)
+        assert g.info["breakdown"] == 1 and g.info["iters"] <= 10, g.info
+        assert abs(g.e0) <= 1e-12
+        assert g.info["true_residual"] <= 1e-6
+    s.close()
