@@ -1116,14 +1116,14 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
 {
     MvArgs<T> A = make_args<T>(s, x, y);
     const size_t col_bytes = (size_t)A.cu * sizeof(T);
-    static const int impl = env_int("HUB_MATVEC_IMPL", 2);
-    // read on every call so a shape can be forced for measurement or tests
+    // read on every call so a variant or shape can be forced for measurement or tests
+    const int impl = env_int("HUB_MATVEC_IMPL", 2);
     const int tb_env = env_int("HUB_MATVEC_TB", 0);
     const int bs_env = env_int("HUB_MATVEC_BS", 0);
-    static const int occ = env_int("HUB_DN_OCC", 4);
-    static const int nt = env_int("HUB_DN_NT", 1);
-    static const int rows = env_int("HUB_FUSED_R", 4);
-    static const bool cf = env_int("HUB_ELL_FMT", 1) != 0;
+    const int occ = env_int("HUB_DN_OCC", 4);
+    const int nt = env_int("HUB_DN_NT", 1);
+    const int rows = env_int("HUB_FUSED_R", 4);
+    const bool cf = env_int("HUB_ELL_FMT", 1) != 0;
     const bool quad = env_int("HUB_MATVEC_QUAD", 1) != 0;
     const size_t extra = 256 * sizeof(T);
     const size_t half = s->lds_max / 2;

@@ -584,3 +584,64 @@ def test_unnormalised_recurrence_breakdown(hub):
         assert abs(g.e0) <= 1e-12
         assert g.info["true_residual"] <= 1e-6
     s.close()
+
+
+def _variant_model(which):
+    if which == "ring10_eps":
+        return W.ring(10, U=3.0, n_up=5, n_dn=4).with_params(eps=[0.1 * i for i in range(10)])
+    if which == "ring9":
+        return W.ring(9, U=2.0, n_up=4, n_dn=3)           # count_up = 126 (not a multiple of 4)
+    return W.square_periodic(3, 4, n_up=5, n_dn=5)
+
+
+@pytest.mark.parametrize("variant", ["csr", "two_pass", "packed_rows", "compact_rows", "compact_rows_r1"])
+@pytest.mark.parametrize("which", ["ring10_eps", "ring9", "square3x4_n5"])
+def test_product_variants_match_oracle(hub, variant, which, monkeypatch):
+    """Every selectable product schedule (kept for measurement) against the oracle:
+    one workgroup per column over CSR; two passes (H_dn term on row tiles, then
+    H_up term and D); one row per lane with packed or compact entries."""
+    import torch
+    env = {"csr": {"HUB_MATVEC_IMPL": "1"},
+           "two_pass": {"HUB_MATVEC_IMPL": "3"},
+           "packed_rows": {"HUB_ELL_FMT": "0"},
+           "compact_rows": {"HUB_MATVEC_QUAD": "0"},
+           "compact_rows_r1": {"HUB_MATVEC_QUAD": "0", "HUB_MATVEC_TB": "1", "HUB_FUSED_R": "1"}}[variant]
+    m = _variant_model(which)
+    s = hub.Sector(m)
+    osec = oracle.Sector(m)
+    xr = oracle.start_vector(19, osec.dim)
+    bound = _row_abs(osec, xr)
+    yr = oracle.spmv(osec.csr(), xr)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    try:
+        for dt, tol in ((hub.F64, 1e-13), (hub.F32, 1e-5)):
+            x = torch.from_numpy(xr).cuda()
+            if dt == hub.F32:
+                x = x.float()
+            y = s.matvec(x).double().cpu().numpy()
+            ref = yr if dt == hub.F64 else oracle.spmv(osec.csr(), x.double().cpu().numpy())
+            assert np.all(np.abs(y - ref) <= tol * bound + 1e-30), (variant, which, dt)
+    finally:
+        for k in env:
+            monkeypatch.delenv(k)
+    s.close()
+
+
+def test_many_bonds_use_packed_entries(hub):
+    """More than 127 bonds do not fit the 8-bit entry code: the product falls back
+    to packed entries (all 136 pairs of 17 sites, random t, eps; N = 2/1)."""
+    import torch
+    m = W.random_graph(17, 136, seed=917).with_params(n_up=2, n_dn=1)
+    assert len(m.bonds) == 136
+    s = hub.Sector(m)
+    osec = oracle.Sector(m)
+    xr = oracle.start_vector(23, osec.dim)
+    bound = _row_abs(osec, xr)
+    yr = oracle.spmv(osec.csr(), xr)
+    y = s.matvec(torch.from_numpy(xr).cuda()).cpu().numpy()
+    assert np.all(np.abs(y - yr) <= 1e-13 * bound + 1e-300)
+    g = s.ground_state(dtype=hub.F64, want_vector=False)
+    e_ref = float(np.linalg.eigvalsh(osec.dense())[0])
+    assert abs(g.e0 - e_ref) <= 1e-10 * abs(e_ref)
+    s.close()
