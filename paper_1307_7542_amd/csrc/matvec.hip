@@ -510,6 +510,111 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_quad(MvArgs<T> A, const int
     }
 }
 
+// Row-chunked product with the output held in registers: work item (column b,
+// row part j) owns quads [j BS QPL, (j+1) BS QPL) of column b, QPL per lane.
+// It stages every row chunk of column b in turn (the P parts of a column are
+// consecutive work items of one XCD, so the chunks come from that XCD's L2)
+// and accumulates the chunk's H_up entries of its rows; then the H_dn term and
+// one store.  Per element: diagonal, H_up entries in column order, H_dn
+// entries -- the order of k_kron_quad -- and no partial results in memory.
+// Columns are interleaved over the XCDs (b = 8 k + xcd).
+template <typename T, int BS, int QPL>
+__global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const int32_t *__restrict__ ch_off,
+                                                           const int64_t *__restrict__ ch_base,
+                                                           const uint32_t *__restrict__ ch_ell,
+                                                           const T *__restrict__ code_v, int nchunks,
+                                                           int chunk_rows, int nslices, int P)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *tab = reinterpret_cast<T *>(smem_raw);
+    T *xs = tab + 256;
+    const int xcd = (int)(blockIdx.x & 7), r = (int)(blockIdx.x >> 3);
+    const int b = 8 * (r / P) + xcd, part = r % P;
+    if (b >= A.cd) return;
+    const int cu = A.cu, nq = cu >> 2;
+    const int64_t cu64 = cu;
+    const int qa = part * BS * QPL;
+    const T *__restrict__ xb = A.x + (int64_t)b * cu;
+    for (int i = threadIdx.x; i < 256; i += BS) tab[i] = code_v[i];
+    const uint32_t dnb = A.dn_basis[b];
+    const T edn = A.e_dn[b];
+    T acc[QPL][4];
+#pragma unroll
+    for (int i = 0; i < QPL; ++i) {
+        const int q = qa + (int)threadIdx.x + i * BS;
+        if (q < nq) {
+            const int a0 = 4 * q;
+            const uint4 ub = *reinterpret_cast<const uint4 *>(A.up_basis + a0);
+            const uint32_t uu[4] = {ub.x, ub.y, ub.z, ub.w};
+            const Q4<T> eu = ld_q4(A.e_up + a0);
+            const Q4<T> xv = ld_q4(xb + a0);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) acc[i][rr] = (diag_u(A, uu[rr] & dnb) + eu.v[rr] + edn) * xv.v[rr];
+        }
+    }
+    for (int p = 0; p < nchunks; ++p) {
+        const int q0 = (p * chunk_rows) >> 2;
+        const int q1 = min(nq, q0 + (chunk_rows >> 2));
+        __syncthreads();  // previous chunk done with xs
+        for (int q = q0 + threadIdx.x; q < q1; q += BS) {
+            const Q4<T> v = ld_q4(xb + 4 * q);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) xs[4 * (q - q0) + rr] = v.v[rr];
+        }
+        __syncthreads();
+        const int32_t *off = ch_off + (int64_t)p * (nslices + 1);
+        const uint32_t *ell = ch_ell + ch_base[p];
+#pragma unroll
+        for (int i = 0; i < QPL; ++i) {
+            const int q = qa + (int)threadIdx.x + i * BS;
+            if (q >= nq) continue;
+            const int a0 = 4 * q;
+            const int sl = a0 >> 6;
+            const uint4 *__restrict__ e4 = reinterpret_cast<const uint4 *>(ell + (int64_t)off[sl] * 64 + (a0 & 63));
+            const int len = off[sl + 1] - off[sl];
+            int k = 0;
+            for (; k + 2 <= len; k += 2) {
+                const uint4 ea = e4[16 * k], eb = e4[16 * (k + 1)];
+                const uint32_t e[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc[i][u & 3] += tab[e[u] >> 24] * xs[e[u] & 0xFFFFFFu];
+            }
+            if (k < len) {
+                const uint4 ea = e4[16 * k];
+                const uint32_t e[4] = {ea.x, ea.y, ea.z, ea.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[i][u] += tab[e[u] >> 24] * xs[e[u] & 0xFFFFFFu];
+            }
+        }
+    }
+    const int ds = A.dn_rp[b], de = A.dn_rp[b + 1];
+#pragma unroll
+    for (int i = 0; i < QPL; ++i) {
+        const int q = qa + (int)threadIdx.x + i * BS;
+        if (q >= nq) continue;
+        const int a0 = 4 * q;
+        int kk = ds;
+        for (; kk + 4 <= de; kk += 4) {
+            Q4<T> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const T w = A.dn_val[kk + u];
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) acc[i][rr] += w * v[u].v[rr];
+            }
+        }
+        for (; kk < de; ++kk) {
+            const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
+            const T w = A.dn_val[kk];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) acc[i][rr] += w * v.v[rr];
+        }
+        st_q4(A.y + (int64_t)b * cu64 + a0, acc[i]);
+    }
+}
+
 // ---- fused ------------------------------------------------------------
 // Each lane owns R rows (a, a + BS, ...) at once so the H_dn neighbour reads
 // of all R rows are in flight together.
@@ -1151,7 +1256,20 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
         if constexpr (sizeof(T) == 8) cv = (const T *)U.code_v64;
         else cv = (const T *)U.code_v32;
         const unsigned grid = 8u * (unsigned)((A.cd + 7) / 8);
-        if (quad && (A.cu % 4) == 0 && (U.chunk_rows[di] % 4) == 0) {
+        if (quad && (A.cu % 4) == 0 && (U.chunk_rows[di] % 4) == 0 && env_int("HUB_CHUNK_PARTS", 1) != 0) {
+            constexpr int QPL = 4;
+            const int nq = (int)(A.cu >> 2);
+            const int P = (nq + BSC * QPL - 1) / (BSC * QPL);
+            static bool attrp = false;
+            if (!attrp) {
+                HUB_TRY(allow_lds(k_kron_chunked_parts<T, BSC, QPL>, s->lds_max));
+                attrp = true;
+            }
+            const unsigned gridp = 8u * (unsigned)P * (unsigned)((A.cd + 7) / 8);
+            hipLaunchKernelGGL((k_kron_chunked_parts<T, BSC, QPL>), dim3(gridp), dim3(BSC), lds, st, A,
+                               U.ch_off[di], U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di],
+                               (int)U.nslices, P);
+        } else if (quad && (A.cu % 4) == 0 && (U.chunk_rows[di] % 4) == 0) {
             // tile order: launch order (all XCDs on nearby columns, so recently read
             // neighbour columns are more often still in the MALL: 2x9 ladder FP32 39.3 -> 37.6 ms)
             // or XCD-contiguous ranges (HUB_CHUNK_XC=1)

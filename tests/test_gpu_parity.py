@@ -437,11 +437,15 @@ def test_param_bilinear_vs_oracle(hub, which):
 
 
 @pytest.mark.parametrize("chunk", [64, 200, 1000])
-def test_matvec_row_chunked_parity(hub, chunk, monkeypatch):
+@pytest.mark.parametrize("parts", [1, 0])
+def test_matvec_row_chunked_parity(hub, chunk, parts, monkeypatch):
     """The row-chunked product (used when a column exceeds the LDS) forced on
-    small sectors with several chunks and a ragged last chunk."""
+    small sectors with several chunks and a ragged last chunk; parts = 1: output
+    rows in registers (work items of one column and a row part), 0: one work item
+    per column with the partial output in memory between chunks."""
     import torch
     monkeypatch.setenv("HUB_CHUNK_ROWS", str(chunk))
+    monkeypatch.setenv("HUB_CHUNK_PARTS", str(parts))
     for m in (W.square_periodic(3, 4, n_up=5, n_dn=4), W.random_graph(10, 17, seed=303, site_U=True)):
         s = hub.Sector(m)
         osec = oracle.Sector(m)
@@ -644,4 +648,29 @@ def test_many_bonds_use_packed_entries(hub):
     g = s.ground_state(dtype=hub.F64, want_vector=False)
     e_ref = float(np.linalg.eigvalsh(osec.dense())[0])
     assert abs(g.e0 - e_ref) <= 1e-10 * abs(e_ref)
+    s.close()
+
+
+@pytest.mark.parametrize("parts", [1, 0])
+def test_matvec_row_chunked_several_row_parts(hub, parts, monkeypatch):
+    """count_up = 18564 (ring M=18, N_up=6) is more than one row part of the
+    register-held output (4 x 1024 quads): parts, chunks (5000 rows) and the
+    ragged ends all at once, against the oracle."""
+    import torch
+    monkeypatch.setenv("HUB_CHUNK_ROWS", "5000")
+    monkeypatch.setenv("HUB_CHUNK_PARTS", str(parts))
+    m = W.ring(18, U=3.0, n_up=6, n_dn=1).with_params(eps=[0.03 * i for i in range(18)])
+    s = hub.Sector(m)
+    assert s.count_up == 18564
+    osec = oracle.Sector(m)
+    xr = oracle.start_vector(41, osec.dim)
+    bound = _row_abs(osec, xr)
+    yr = oracle.spmv(osec.csr(), xr)
+    x64 = torch.from_numpy(xr).cuda()
+    y64 = s.matvec(x64).cpu().numpy()
+    assert np.all(np.abs(y64 - yr) <= 1e-13 * bound + 1e-300)
+    x32 = x64.float()
+    y32 = s.matvec(x32).double().cpu().numpy()
+    yr32 = oracle.spmv(osec.csr(), x32.double().cpu().numpy())
+    assert np.all(np.abs(y32 - yr32) <= 1e-5 * bound + 1e-30)
     s.close()
