@@ -53,6 +53,7 @@ struct SpinTables {
     // (a contiguous sub-range of the sorted CSR row), columns relative to the chunk.
     int nchunks[2] = {0, 0};        // per dtype (0: FP64, 1: FP32)
     int chunk_rows[2] = {0, 0};
+    int chunk_tb[2] = {1, 1};       // columns per work item the chunks were sized for
     int32_t *ch_off[2] = {nullptr, nullptr};   // [nchunks * (nslices + 1)] entry offsets / 64
     int64_t *ch_base[2] = {nullptr, nullptr};  // host-side copy not needed; device [nchunks]
     uint32_t *ch_ell[2] = {nullptr, nullptr};

@@ -510,15 +510,16 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_quad(MvArgs<T> A, const int
     }
 }
 
-// Row-chunked product with the output held in registers: work item (column b,
-// row part j) owns quads [j BS QPL, (j+1) BS QPL) of column b, QPL per lane.
-// It stages every row chunk of column b in turn (the P parts of a column are
-// consecutive work items of one XCD, so the chunks come from that XCD's L2)
-// and accumulates the chunk's H_up entries of its rows; then the H_dn term and
-// one store.  Per element: diagonal, H_up entries in column order, H_dn
-// entries -- the order of k_kron_quad -- and no partial results in memory.
-// Columns are interleaved over the XCDs (b = 8 k + xcd).
-template <typename T, int BS, int QPL>
+// Row-chunked product with the output held in registers: work item (tile of TB
+// columns, row part j) owns quads [j BS QPL, (j+1) BS QPL) of its columns, QPL
+// per lane.  It stages every row chunk of its columns in turn (interleaved,
+// element (a, t) at a TB + t; the P parts of a tile are consecutive work items
+// of one XCD, so the chunks come from that XCD's L2) and accumulates the
+// chunk's H_up entries of its rows, each entry serving the TB columns; then the
+// H_dn term and one store.  Per element: diagonal, H_up entries in column
+// order, H_dn entries -- the order of k_kron_quad -- and no partial results in
+// memory.  Tiles are interleaved over the XCDs (tile = 8 k + xcd).
+template <typename T, int BS, int QPL, int TB>
 __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const int32_t *__restrict__ ch_off,
                                                            const int64_t *__restrict__ ch_base,
                                                            const uint32_t *__restrict__ ch_ell,
@@ -529,16 +530,29 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const in
     T *tab = reinterpret_cast<T *>(smem_raw);
     T *xs = tab + 256;
     const int xcd = (int)(blockIdx.x & 7), r = (int)(blockIdx.x >> 3);
-    const int b = 8 * (r / P) + xcd, part = r % P;
-    if (b >= A.cd) return;
+    const int tile = 8 * (r / P) + xcd, part = r % P;
+    const int cd = A.cd;
+    const int ntiles = (cd + TB - 1) / TB;
+    if (tile >= ntiles) return;
+    const int b0 = tile * TB;
     const int cu = A.cu, nq = cu >> 2;
     const int64_t cu64 = cu;
     const int qa = part * BS * QPL;
-    const T *__restrict__ xb = A.x + (int64_t)b * cu;
     for (int i = threadIdx.x; i < 256; i += BS) tab[i] = code_v[i];
-    const uint32_t dnb = A.dn_basis[b];
-    const T edn = A.e_dn[b];
-    T acc[QPL][4];
+    const T *xb[TB];
+    uint32_t dnb[TB];
+    T edn[TB];
+    int ds[TB], de[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+        const int b = min(b0 + t, cd - 1);
+        xb[t] = A.x + (int64_t)b * cu;
+        dnb[t] = A.dn_basis[b];
+        edn[t] = A.e_dn[b];
+        ds[t] = A.dn_rp[b];
+        de[t] = (b0 + t < cd) ? A.dn_rp[b + 1] : ds[t];
+    }
+    T acc[QPL][4][TB];
 #pragma unroll
     for (int i = 0; i < QPL; ++i) {
         const int q = qa + (int)threadIdx.x + i * BS;
@@ -547,20 +561,26 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const in
             const uint4 ub = *reinterpret_cast<const uint4 *>(A.up_basis + a0);
             const uint32_t uu[4] = {ub.x, ub.y, ub.z, ub.w};
             const Q4<T> eu = ld_q4(A.e_up + a0);
-            const Q4<T> xv = ld_q4(xb + a0);
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) acc[i][rr] = (diag_u(A, uu[rr] & dnb) + eu.v[rr] + edn) * xv.v[rr];
+            for (int t = 0; t < TB; ++t) {
+                const Q4<T> xv = ld_q4(xb[t] + a0);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+                    acc[i][rr][t] = (diag_u(A, uu[rr] & dnb[t]) + eu.v[rr] + edn[t]) * xv.v[rr];
+            }
         }
     }
     for (int p = 0; p < nchunks; ++p) {
         const int q0 = (p * chunk_rows) >> 2;
         const int q1 = min(nq, q0 + (chunk_rows >> 2));
         __syncthreads();  // previous chunk done with xs
-        for (int q = q0 + threadIdx.x; q < q1; q += BS) {
-            const Q4<T> v = ld_q4(xb + 4 * q);
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) xs[4 * (q - q0) + rr] = v.v[rr];
-        }
+        for (int t = 0; t < TB; ++t)
+            for (int q = q0 + threadIdx.x; q < q1; q += BS) {
+                const Q4<T> v = ld_q4(xb[t] + 4 * q);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) xs[(4 * (q - q0) + rr) * TB + t] = v.v[rr];
+            }
         __syncthreads();
         const int32_t *off = ch_off + (int64_t)p * (nslices + 1);
         const uint32_t *ell = ch_ell + ch_base[p];
@@ -577,41 +597,56 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const in
                 const uint4 ea = e4[16 * k], eb = e4[16 * (k + 1)];
                 const uint32_t e[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc[i][u & 3] += tab[e[u] >> 24] * xs[e[u] & 0xFFFFFFu];
+                for (int u = 0; u < 8; ++u) {
+                    const T v = tab[e[u] >> 24];
+                    const T *xr = xs + (e[u] & 0xFFFFFFu) * TB;
+#pragma unroll
+                    for (int t = 0; t < TB; ++t) acc[i][u & 3][t] += v * xr[t];
+                }
             }
             if (k < len) {
                 const uint4 ea = e4[16 * k];
                 const uint32_t e[4] = {ea.x, ea.y, ea.z, ea.w};
 #pragma unroll
-                for (int u = 0; u < 4; ++u) acc[i][u] += tab[e[u] >> 24] * xs[e[u] & 0xFFFFFFu];
+                for (int u = 0; u < 4; ++u) {
+                    const T v = tab[e[u] >> 24];
+                    const T *xr = xs + (e[u] & 0xFFFFFFu) * TB;
+#pragma unroll
+                    for (int t = 0; t < TB; ++t) acc[i][u][t] += v * xr[t];
+                }
             }
         }
     }
-    const int ds = A.dn_rp[b], de = A.dn_rp[b + 1];
 #pragma unroll
     for (int i = 0; i < QPL; ++i) {
         const int q = qa + (int)threadIdx.x + i * BS;
         if (q >= nq) continue;
         const int a0 = 4 * q;
-        int kk = ds;
-        for (; kk + 4 <= de; kk += 4) {
-            Q4<T> v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
+        for (int t = 0; t < TB; ++t) {
+            int kk = ds[t];
+            for (; kk + 4 <= de[t]; kk += 4) {
+                Q4<T> v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const T w = A.dn_val[kk + u];
+                for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr) acc[i][rr] += w * v[u].v[rr];
+                for (int u = 0; u < 4; ++u) {
+                    const T w = A.dn_val[kk + u];
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v[u].v[rr];
+                }
+            }
+            for (; kk < de[t]; ++kk) {
+                const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
+                const T w = A.dn_val[kk];
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v.v[rr];
+            }
+            if (b0 + t < cd) {
+                const T o[4] = {acc[i][0][t], acc[i][1][t], acc[i][2][t], acc[i][3][t]};
+                st_q4(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
             }
         }
-        for (; kk < de; ++kk) {
-            const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
-            const T w = A.dn_val[kk];
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) acc[i][rr] += w * v.v[rr];
-        }
-        st_q4(A.y + (int64_t)b * cu64 + a0, acc[i]);
     }
 }
 
@@ -1208,6 +1243,44 @@ hub_status run_kron_lz(const hub_sector *s, const void *x, void *w, const void *
     return HUB_ERR_UNSUPPORTED;
 }
 
+// Row-chunked product with register-held output rows: TB columns per work
+// item (the chunk tables were sized for TB), 4 x 1024 lane-quads per row part.
+template <typename T, int TB>
+hub_status launch_chunked_parts_t(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const T *cv)
+{
+    constexpr int BSC = 1024, QPL = 4;
+    const int di = (sizeof(T) == 8) ? 0 : 1;
+    const SpinTables &U = s->spin[0];
+    const size_t lds = ((size_t)U.chunk_rows[di] * TB + 256) * sizeof(T);
+    if (lds > s->lds_max) {
+        set_error("row-chunked product: chunk does not fit in LDS");
+        return HUB_ERR_UNSUPPORTED;
+    }
+    const int nq = (int)(A.cu >> 2);
+    const int P = (nq + BSC * QPL - 1) / (BSC * QPL);
+    const int ntiles = (A.cd + TB - 1) / TB;
+    static bool attr = false;
+    if (!attr) {
+        HUB_TRY(allow_lds(k_kron_chunked_parts<T, BSC, QPL, TB>, s->lds_max));
+        attr = true;
+    }
+    const unsigned grid = 8u * (unsigned)P * (unsigned)((ntiles + 7) / 8);
+    hipLaunchKernelGGL((k_kron_chunked_parts<T, BSC, QPL, TB>), dim3(grid), dim3(BSC), lds, st, A, U.ch_off[di],
+                       U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di], (int)U.nslices, P);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+template <typename T>
+hub_status launch_chunked_parts(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, const T *cv)
+{
+    // FP64 with four columns would need more registers than a 1024-lane workgroup has
+    if constexpr (sizeof(T) == 4)
+        if (tb >= 4) return launch_chunked_parts_t<T, 4>(s, A, st, cv);
+    if (tb >= 2) return launch_chunked_parts_t<T, 2>(s, A, st, cv);
+    return launch_chunked_parts_t<T, 1>(s, A, st, cv);
+}
+
 // Schedule selection.  Environment overrides for measurement: HUB_MATVEC_IMPL
 // (1 csr, 2 fused, 3 two-pass), HUB_MATVEC_TB, HUB_MATVEC_BS (512 / 1024),
 // HUB_MATVEC_XC (tile order), HUB_MATVEC_QUAD (0: one row per lane),
@@ -1256,19 +1329,9 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
         if constexpr (sizeof(T) == 8) cv = (const T *)U.code_v64;
         else cv = (const T *)U.code_v32;
         const unsigned grid = 8u * (unsigned)((A.cd + 7) / 8);
+        const int ctb = U.chunk_tb[di];
         if (quad && (A.cu % 4) == 0 && (U.chunk_rows[di] % 4) == 0 && env_int("HUB_CHUNK_PARTS", 1) != 0) {
-            constexpr int QPL = 4;
-            const int nq = (int)(A.cu >> 2);
-            const int P = (nq + BSC * QPL - 1) / (BSC * QPL);
-            static bool attrp = false;
-            if (!attrp) {
-                HUB_TRY(allow_lds(k_kron_chunked_parts<T, BSC, QPL>, s->lds_max));
-                attrp = true;
-            }
-            const unsigned gridp = 8u * (unsigned)P * (unsigned)((A.cd + 7) / 8);
-            hipLaunchKernelGGL((k_kron_chunked_parts<T, BSC, QPL>), dim3(gridp), dim3(BSC), lds, st, A,
-                               U.ch_off[di], U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di],
-                               (int)U.nslices, P);
+            HUB_TRY(launch_chunked_parts<T>(s, A, st, ctb, cv));
         } else if (quad && (A.cu % 4) == 0 && (U.chunk_rows[di] % 4) == 0) {
             // tile order: launch order (all XCDs on nearby columns, so recently read
             // neighbour columns are more often still in the MALL: 2x9 ladder FP32 39.3 -> 37.6 ms)

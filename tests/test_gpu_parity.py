@@ -651,14 +651,16 @@ def test_many_bonds_use_packed_entries(hub):
     s.close()
 
 
-@pytest.mark.parametrize("parts", [1, 0])
-def test_matvec_row_chunked_several_row_parts(hub, parts, monkeypatch):
+@pytest.mark.parametrize("parts,tb", [(1, "1"), (1, "2"), (1, "4"), (0, "1")])
+def test_matvec_row_chunked_several_row_parts(hub, parts, tb, monkeypatch):
     """count_up = 18564 (ring M=18, N_up=6) is more than one row part of the
-    register-held output (4 x 1024 quads): parts, chunks (5000 rows) and the
-    ragged ends all at once, against the oracle."""
+    register-held output (4 x 1024 quads): parts, chunks (5000 rows), 1, 2 or 4
+    columns per work item (18 columns: a ragged last tile) and the ragged ends
+    all at once, against the oracle."""
     import torch
     monkeypatch.setenv("HUB_CHUNK_ROWS", "5000")
     monkeypatch.setenv("HUB_CHUNK_PARTS", str(parts))
+    monkeypatch.setenv("HUB_CHUNK_TB", tb)
     m = W.ring(18, U=3.0, n_up=6, n_dn=1).with_params(eps=[0.03 * i for i in range(18)])
     s = hub.Sector(m)
     assert s.count_up == 18564
