@@ -75,6 +75,26 @@ def product_timing(hub, torch, model, reps=10):
     return out
 
 
+def ladder_mixed(hub, torch, model):
+    """The 2x9 ladder (N = 9/9, dim 2.36e9): FP32 vectors and products with FP64
+    scalars, plain recurrence, then the FP64 refinement of the eigenpair; the
+    FP32 Ritz value against the FP64 Rayleigh quotient."""
+    sec = hub.Sector(model)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = sec.ground_state(dtype=hub.F32, reorth=False, refine=True, tol=1e-7, max_iter=400)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    i = g.info
+    out = {"dim": sec.dim, "iters": i["iters"], "solve_s": dt, "e0_ritz_fp32": i["e0_ritz"],
+           "e0_refined_fp64": i["e0_refined"],
+           "rel_err_ritz_vs_refined": abs(i["e0_ritz"] - i["e0_refined"]) / abs(i["e0_refined"]),
+           "true_residual_fp64": i["true_residual"]}
+    del g
+    sec.close()
+    return out
+
+
 def batch_timing(hub, torch, count=64):
     """The synthetic impurity-model batch (one DMFT step's exact-diagonalisation
     solves): one batched FP64 solve and one FP32 solve with FP64 refinement,
@@ -363,6 +383,7 @@ def main():
     if not args.no_extra:
         out["products_square4x4"] = product_timing(hub, torch, W.config("square4x4"))
         out["products_ladder2x9"] = product_timing(hub, torch, W.config("ladder2x9"), reps=3)
+        out["lanczos_ladder2x9_mixed"] = ladder_mixed(hub, torch, W.config("ladder2x9"))
         out["aim_batch64"] = batch_timing(hub, torch)
         out["greens_ring14_u4"] = greens_timing(hub, torch, models[4])
         out["k0_ring14_u4"] = k0_timing(hub, torch, models[4])
