@@ -95,6 +95,35 @@ def ladder_mixed(hub, torch, model):
     return out
 
 
+def square_mixed_gradients(hub, torch, model):
+    """Config of the 4x4 torus (N = 7/7, dim 1.31e8, random t): FP32-mixed plain
+    Lanczos with FP64 refinement, then the adjoint bilinear forms on psi, i.e.
+    dE0/dt for the 32 bonds, dE0/dU_i and dE0/deps_i (Hellmann-Feynman). The
+    Euler identity sum t dE/dt + sum U dE/dU + sum eps dE/deps = E (H is linear
+    and homogeneous in its parameters) checks them."""
+    import numpy as np
+    sec = hub.Sector(model)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = sec.ground_state(dtype=hub.F32, reorth=False, refine=True, tol=1e-7, max_iter=600)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    db, dU, de = sec.param_bilinear(g.psi, g.psi)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tvec = sec.bonds()[2]  # canonical bonds, in the order of db
+    euler = float(np.dot(tvec, db) + np.dot(model.U, dU) + np.dot(model.eps, de))
+    i = g.info
+    out = {"dim": sec.dim, "iters": i["iters"], "solve_s": t1 - t0, "gradient_s": t2 - t1,
+           "e0_ritz_fp32": i["e0_ritz"], "e0_refined_fp64": i["e0_refined"],
+           "rel_err_ritz_vs_refined": abs(i["e0_ritz"] - i["e0_refined"]) / abs(i["e0_refined"]),
+           "true_residual_fp64": i["true_residual"], "dE_dU_sum": float(np.sum(dU)),
+           "euler_identity_rel": abs(euler - i["e0_refined"]) / abs(i["e0_refined"])}
+    del g
+    sec.close()
+    return out
+
+
 def batch_timing(hub, torch, count=64):
     """The synthetic impurity-model batch (one DMFT step's exact-diagonalisation
     solves): one batched FP64 solve and one FP32 solve with FP64 refinement,
@@ -382,6 +411,7 @@ def main():
         pass
     if not args.no_extra:
         out["products_square4x4"] = product_timing(hub, torch, W.config("square4x4"))
+        out["lanczos_square4x4_mixed_gradients"] = square_mixed_gradients(hub, torch, W.config("square4x4"))
         out["products_ladder2x9"] = product_timing(hub, torch, W.config("ladder2x9"), reps=3)
         out["lanczos_ladder2x9_mixed"] = ladder_mixed(hub, torch, W.config("ladder2x9"))
         out["aim_batch64"] = batch_timing(hub, torch)
