@@ -214,8 +214,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the "
-                                   "design notes but not implemented", "n_gpus": max(args.gpus, world)}))
+        print(json.dumps({"error": "the product and the solver run on one GPU only; sharding V by column "
+                                   "blocks over several GPUs is designed but not implemented",
+                          "n_gpus": max(args.gpus, world)}))
         sys.exit(2)
 
     import torch
