@@ -61,7 +61,7 @@ __global__ void k_rank(const uint64_t *__restrict__ xs, int64_t n, int M, int N,
     if (i >= n) return;
     const uint64_t x = xs[i];
     const uint64_t lim = (M >= 32) ? (uint64_t)0xFFFFFFFFull : ((1ull << M) - 1ull);
-    if ((x & ~lim) != 0 || __popcll(x) != N) {
+    if ((x & ~lim) != 0 || (int)__popcll(x) != N) {
         out[i] = -1;
         return;
     }

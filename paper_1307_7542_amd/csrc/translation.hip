@@ -245,7 +245,7 @@ __global__ __launch_bounds__(BS) void k_k0_product(K0Args<T> A)
     const int q = A.orb_off[j + 1] - o0;
     const int sigma = A.orb_sigma[j];
     const int64_t R = A.R;
-    if (threadIdx.x < q) {
+    if ((int)threadIdx.x < q) {
         cols[threadIdx.x] = A.orb_cols[o0 + threadIdx.x];
         csg[threadIdx.x] = A.orb_sign[o0 + threadIdx.x];
     }
