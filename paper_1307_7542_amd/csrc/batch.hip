@@ -319,6 +319,82 @@ __global__ __launch_bounds__(BRB) void k_b_psi(Seg S, double *psi, const T *v, c
 }
 
 // psi *= scale[p]
+// Per block: the largest |psi| of the block's elements and its sector-local
+// index (ties: the lower index).
+__device__ __forceinline__ bool amax_better(double a1, int64_t i1, double a2, int64_t i2)
+{
+    return a1 > a2 || (a1 == a2 && i1 < i2);
+}
+
+__global__ __launch_bounds__(BRB) void k_b_amax(Seg S, const double *psi, double *pa, int64_t *pi)
+{
+    __shared__ double sa[BRB];
+    __shared__ int64_t si[BRB];
+    double best = -1.0;
+    int64_t bi = INT64_MAX;
+    SEG_LOOP(S, p, i)
+    {
+        const double a = fabs(psi[o_p + i]);
+        if (amax_better(a, i, best, bi)) {
+            best = a;
+            bi = i;
+        }
+    }
+    sa[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = BRB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o && amax_better(sa[threadIdx.x + o], si[threadIdx.x + o], sa[threadIdx.x], si[threadIdx.x])) {
+            sa[threadIdx.x] = sa[threadIdx.x + o];
+            si[threadIdx.x] = si[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pa[blockIdx.x] = sa[0];
+        pi[blockIdx.x] = si[0];
+    }
+}
+
+// One block per sector: scale[p] = sign / ||psi_p|| with the norm from the
+// squared-norm partials (k_b_final's order) and the sign of the largest-magnitude
+// entry (lowest index on ties), so that k_b_scale_psi leaves a unit vector whose
+// largest entry is positive.
+__global__ __launch_bounds__(BRB) void k_b_norm_sign(Seg S, const double *partial, const double *pa,
+                                                     const int64_t *pi, const double *psi, double *scale)
+{
+    __shared__ double sh[BRB];
+    __shared__ double sa[BRB];
+    __shared__ int64_t si[BRB];
+    const int p = blockIdx.x;
+    double acc = 0.0, best = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int j = threadIdx.x; j < S.nseg[p]; j += BRB) {
+        acc += partial[S.start[p] + j];
+        if (amax_better(pa[S.start[p] + j], pi[S.start[p] + j], best, bi)) {
+            best = pa[S.start[p] + j];
+            bi = pi[S.start[p] + j];
+        }
+    }
+    const double s2 = bblock_sum(acc, sh);
+    sa[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = BRB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o && amax_better(sa[threadIdx.x + o], si[threadIdx.x + o], sa[threadIdx.x], si[threadIdx.x])) {
+            sa[threadIdx.x] = sa[threadIdx.x + o];
+            si[threadIdx.x] = si[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double nr = sqrt(s2);
+        const int64_t n_p = S.off[p + 1] - S.off[p];
+        const double v = (si[0] >= 0 && si[0] < n_p) ? psi[S.off[p] + si[0]] : 0.0;
+        scale[p] = (nr > 0.0 ? 1.0 / nr : 0.0) * (v < 0.0 ? -1.0 : 1.0);
+    }
+}
+
 __global__ __launch_bounds__(BRB) void k_b_scale_psi(Seg S, double *psi, const double *scale)
 {
     const int pp = S.prob[blockIdx.x];
@@ -646,22 +722,74 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
         }
     } gg{graph, gexec};
 
-    std::vector<double> ha((size_t)P * kmax), hb((size_t)P * kmax);
     std::vector<int> m_final(P, 0), conv(P, 0);
     std::vector<double> theta(P, 0.0);
     std::vector<std::vector<double>> ys(P);
     std::vector<double> tmax(P, 0.0);
     int replays = 0, nactive = P;
-    while (true) {
-        HUB_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * (size_t)P * kmax, hipMemcpyDeviceToHost, st));
-        HUB_HIP(hipMemcpyAsync(hb.data(), beta, sizeof(double) * (size_t)P * kmax, hipMemcpyDeviceToHost, st));
-        HUB_HIP(hipStreamSynchronize(st));
+
+    // Convergence checks overlap the GPU: after every group of check_every steps
+    // the coefficients are copied into one of two pinned buffers, the next group
+    // is enqueued before the host examines the previous copy, and the new active
+    // mask (through pinned memory as well) reaches the device one group later.
+    // A sector found converged may so run one more group; those steps are never
+    // used (its T and psi stop at the step of the test).
+    const size_t nab = (size_t)P * kmax;
+    double *hab = nullptr;  // [2 slots][alpha | beta]
+    int *hmask = nullptr;   // [2][P]
+    HUB_HIP(hipHostMalloc((void **)&hab, sizeof(double) * 4 * nab));
+    struct PinGuard {
+        void *p;
+        hipStream_t st;
+        ~PinGuard()
+        {
+            if (!p) return;
+            (void)hipStreamSynchronize(st);
+            (void)hipHostFree(p);
+        }
+    } pin_ab{hab, st}, pin_mask{nullptr, st};
+    HUB_HIP(hipHostMalloc((void **)&hmask, sizeof(int) * 2 * (size_t)P));
+    pin_mask.p = hmask;
+    hipEvent_t cev[2] = {nullptr, nullptr};
+    HUB_HIP(hipEventCreateWithFlags(&cev[0], hipEventDisableTiming));
+    HUB_HIP(hipEventCreateWithFlags(&cev[1], hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard()
+        {
+            for (int i = 0; i < 2; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } evg{cev};
+    int kslot[2] = {0, 0};
+    auto enqueue_copy = [&](int sl) -> hub_status {
+        HUB_HIP(hipMemcpyAsync(hab + (size_t)sl * 2 * nab, alpha, sizeof(double) * nab, hipMemcpyDeviceToHost, st));
+        HUB_HIP(hipMemcpyAsync(hab + (size_t)sl * 2 * nab + nab, beta, sizeof(double) * nab, hipMemcpyDeviceToHost,
+                               st));
+        HUB_HIP(hipEventRecord(cev[sl], st));
+        kslot[sl] = k;
+        return HUB_OK;
+    };
+    auto enqueue_steps = [&](int nsteps) -> hub_status {
+        for (int s2 = 0; s2 < nsteps; ++s2) {
+            if (use_graph) {
+                HUB_HIP(hipGraphLaunch(gexec, st));
+                ++replays;
+            } else {
+                HUB_TRY(one_step());
+            }
+        }
+        k += nsteps;
+        return HUB_OK;
+    };
+    // Ritz test of every active sector on a copy holding kk steps
+    auto check_copy = [&](const double *ha, const double *hb, int kk) {
         for (int p = 0; p < P; ++p) {
             if (!hact[p]) continue;
-            const double *a = ha.data() + (size_t)p * kmax;
-            const double *bb = hb.data() + (size_t)p * kmax;
+            const double *a = ha + (size_t)p * kmax;
+            const double *bb = hb + (size_t)p * kmax;
             const int64_t dimp = b->off[p + 1] - b->off[p];
-            int m = (int)std::min<int64_t>(k, dimp);
+            int m = (int)std::min<int64_t>(kk, dimp);
             bool brk = false;
             for (int j = 0; j < m; ++j) {
                 tmax[p] = std::max(tmax[p], std::fabs(a[j]) + 2.0 * std::fabs(bb[j + 1]));
@@ -685,19 +813,24 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
                 --nactive;
             }
         }
-        HUB_HIP(hipMemcpyAsync(active, hact.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
-        HUB_HIP(hipStreamSynchronize(st));
-        if (nactive == 0 || k >= max_iter) break;
-        const int nsteps = std::min(check_every, max_iter - k);
-        for (int s2 = 0; s2 < nsteps; ++s2) {
-            if (use_graph) {
-                HUB_HIP(hipGraphLaunch(gexec, st));
-                ++replays;
-            } else {
-                HUB_TRY(one_step());
-            }
+    };
+    HUB_TRY(enqueue_copy(0));
+    int sl = 0, msl = 0;
+    while (true) {
+        const int nsteps = nactive > 0 ? std::min(check_every, max_iter - k) : 0;
+        if (nsteps > 0) {
+            HUB_TRY(enqueue_steps(nsteps));
+            HUB_TRY(enqueue_copy(sl ^ 1));
         }
-        k += nsteps;
+        HUB_HIP(hipEventSynchronize(cev[sl]));  // the group just enqueued keeps running
+        const double *ha = hab + (size_t)sl * 2 * nab;
+        check_copy(ha, ha + nab, kslot[sl]);
+        if (nactive == 0 || nsteps == 0) break;
+        int *hm = hmask + (size_t)msl * P;
+        std::memcpy(hm, hact.data(), sizeof(int) * (size_t)P);
+        HUB_HIP(hipMemcpyAsync(active, hm, sizeof(int) * P, hipMemcpyHostToDevice, st));
+        msl ^= 1;
+        sl ^= 1;
     }
     std::vector<double> e0(theta);
 
@@ -726,24 +859,18 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
             vc = vn;
             vn = tmp;
         }
-        // normalise and fix the sign (largest-magnitude entry positive, lowest index on ties)
-        HUB_HIP(hipGetLastError());
-        HUB_HIP(hipStreamSynchronize(st));
-        std::vector<double> hpsi((size_t)n);
-        HUB_HIP(hipMemcpy(hpsi.data(), psi, sizeof(double) * n, hipMemcpyDeviceToHost));
-        std::vector<double> sc(P, 1.0);
-        for (int p = 0; p < P; ++p) {
-            double s2 = 0.0, best = -1.0;
-            int64_t bi = 0;
-            for (int64_t i = b->off[p]; i < b->off[p + 1]; ++i) {
-                s2 += hpsi[i] * hpsi[i];
-                if (std::fabs(hpsi[i]) > best) { best = std::fabs(hpsi[i]); bi = i; }
-            }
-            const double nr = std::sqrt(s2);
-            sc[p] = (nr > 0 ? 1.0 / nr : 0.0) * (hpsi[bi] < 0 ? -1.0 : 1.0);
-        }
-        HUB_HIP(hipMemcpyAsync(nrm, sc.data(), sizeof(double) * P, hipMemcpyHostToDevice, st));
+        // normalise and fix the sign (largest-magnitude entry positive, lowest index on ties), on the device
+        double *pa = nullptr;
+        int64_t *pi = nullptr;
+        HUB_TRY(alloc((void **)&pa, sizeof(double) * (size_t)b->nblocks));
+        HUB_TRY(alloc((void **)&pi, sizeof(int64_t) * (size_t)b->nblocks));
+        hipLaunchKernelGGL(k_b_dot<double>, dim3(b->nblocks), dim3(BRB), 0, st, S, (const double *)psi,
+                           (const double *)psi, partial, (const int *)nullptr);
+        hipLaunchKernelGGL(k_b_amax, dim3(b->nblocks), dim3(BRB), 0, st, S, (const double *)psi, pa, pi);
+        hipLaunchKernelGGL(k_b_norm_sign, dim3(P), dim3(BRB), 0, st, S, (const double *)partial,
+                           (const double *)pa, (const int64_t *)pi, (const double *)psi, nrm);
         hipLaunchKernelGGL(k_b_scale_psi, dim3(b->nblocks), dim3(BRB), 0, st, S, psi, (const double *)nrm);
+        HUB_HIP(hipGetLastError());
         if (o->refine) {
             double *hp = nullptr;
             HUB_TRY(alloc((void **)&hp, sizeof(double) * n));
