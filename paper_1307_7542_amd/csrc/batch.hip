@@ -713,6 +713,18 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
         use_graph = false;
     }
     (void)hipGetLastError();
+    // a whole group of check_every steps in one graph as well (one launch per group)
+    hipGraph_t graph_g = nullptr;
+    hipGraphExec_t gexec_g = nullptr;
+    if (use_graph && check_every > 1 && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        hub_status cs = HUB_OK;
+        for (int s2 = 0; s2 < check_every && cs == HUB_OK; ++s2) cs = one_step();
+        hipError_t ec = hipStreamEndCapture(st, &graph_g);
+        if (cs != HUB_OK || ec != hipSuccess ||
+            hipGraphInstantiate(&gexec_g, graph_g, nullptr, nullptr, 0) != hipSuccess)
+            gexec_g = nullptr;
+    }
+    (void)hipGetLastError();
     struct GraphGuard {
         hipGraph_t g;
         hipGraphExec_t x;
@@ -720,7 +732,7 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
             if (x) (void)hipGraphExecDestroy(x);
             if (g) (void)hipGraphDestroy(g);
         }
-    } gg{graph, gexec};
+    } gg{graph, gexec}, gg_group{graph_g, gexec_g};
 
     std::vector<int> m_final(P, 0), conv(P, 0);
     std::vector<double> theta(P, 0.0);
@@ -771,6 +783,12 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
         return HUB_OK;
     };
     auto enqueue_steps = [&](int nsteps) -> hub_status {
+        if (gexec_g && nsteps == check_every) {
+            HUB_HIP(hipGraphLaunch(gexec_g, st));
+            replays += nsteps;
+            k += nsteps;
+            return HUB_OK;
+        }
         for (int s2 = 0; s2 < nsteps; ++s2) {
             if (use_graph) {
                 HUB_HIP(hipGraphLaunch(gexec, st));
