@@ -78,14 +78,19 @@ __device__ __forceinline__ Roles<T> roles(T *const *ptrs, int k)
     return r;
 }
 
-// Batched product.  SEL: take x = v and y = w from the pointer table at the
-// device step counter (graph replay); otherwise x, y as given.
+// Batched product.  SEL (the Lanczos step): x = v and y = w from the pointer
+// table at the device step counter, and the first update fused in: w = H v -
+// beta_k v_prev (rounded as a separate update would be) and this work item's
+// partial of <w, v> in ipart[item] (a fixed-order block sum); otherwise x, y
+// as given.
 template <typename T, int TB, int BS, bool SEL>
 __global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ desc, const int2 *__restrict__ items,
                                                    const T *xg, T *yg, T *const *ptrs, const int *step,
-                                                   const int *__restrict__ active)
+                                                   const int *__restrict__ active, const double *__restrict__ beta,
+                                                   int kmax, double *__restrict__ ipart)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[SEL ? BS : 1];
     T *tab = reinterpret_cast<T *>(smem_raw);
     T *xs = tab + 256;
     const int2 it = items[blockIdx.x];
@@ -93,11 +98,18 @@ __global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ 
     const BDesc<T> D = desc[it.x];
     const T *x = xg;
     T *y = yg;
+    const T *vp = nullptr;
+    int k = 0;
+    double bt = 0.0;
     if (SEL) {
-        const Roles<T> r = roles(ptrs, *step);
+        k = *step;
+        const Roles<T> r = roles(ptrs, k);
         x = r.v;
         y = r.w;
+        vp = r.vp + D.off;
+        if (k > 0) bt = beta[(int64_t)it.x * kmax + k];
     }
+    double dacc = 0.0;
     x += D.off;
     y += D.off;
     const int cu = D.cu, cd = D.cd;
@@ -135,10 +147,43 @@ __global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ 
             const int b = b0 + t;
             if (b >= cd) continue;
             T s2 = (T)0;
-            for (int k = D.dn_rp[b]; k < D.dn_rp[b + 1]; ++k) s2 += D.dn_val[k] * x[(int64_t)D.dn_col[k] * cu + a];
-            y[(int64_t)b * cu + a] = acc[t] + s2;
+            for (int kk = D.dn_rp[b]; kk < D.dn_rp[b + 1]; ++kk) s2 += D.dn_val[kk] * x[(int64_t)D.dn_col[kk] * cu + a];
+            T o = acc[t] + s2;
+            if (SEL) {
+                if (k > 0) o = (T)((double)o - bt * (double)vp[(int64_t)b * cu + a]);
+                dacc += (double)o * (double)xs[a * TB + t];
+            }
+            y[(int64_t)b * cu + a] = o;
         }
     }
+    if (SEL) {
+        red[threadIdx.x] = dacc;
+        __syncthreads();
+        for (int o2 = BS / 2; o2 > 0; o2 >>= 1) {
+            if (threadIdx.x < (unsigned)o2) red[threadIdx.x] += red[threadIdx.x + o2];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) ipart[blockIdx.x] = red[0];
+    }
+}
+
+// alpha[p * kmax + step] = the sum of sector p's work-item partials, in item order
+__global__ __launch_bounds__(BRB) void k_b_ifinal(const int *__restrict__ istart, const int *__restrict__ icount,
+                                                  const double *__restrict__ ipart, double *alpha, int kmax,
+                                                  const int *step, const int *__restrict__ active)
+{
+    __shared__ double sh[BRB];
+    const int p = blockIdx.x;
+    if (active && !active[p]) return;
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < icount[p]; j += BRB) acc += ipart[istart[p] + j];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = BRB / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) alpha[(int64_t)p * kmax + *step] = sh[0];
 }
 
 struct Seg {
@@ -198,31 +243,6 @@ __global__ __launch_bounds__(BRB) void k_b_final(Seg S, const double *partial, d
         const int sl = step ? (*step + step_add) : slot;
         out[(int64_t)p * ostride + sl] = sqrt_result ? sqrt(r) : r;
     }
-}
-
-// w -= beta_k v_prev (k > 0); partial alpha = <w, v>.
-template <typename T>
-__global__ __launch_bounds__(BRB) void k_b_lz_a(Seg S, T *const *ptrs, const int *step, const double *beta,
-                                                int kmax, double *partial, const int *__restrict__ active)
-{
-    __shared__ double sh[BRB];
-    const int pp = S.prob[blockIdx.x];
-    if (active && !active[pp]) return;
-    const int k = *step;
-    const Roles<T> r = roles(ptrs, k);
-    const double bt = (k > 0) ? beta[(int64_t)pp * kmax + k] : 0.0;
-    double acc = 0.0;
-    SEG_LOOP(S, p, i)
-    {
-        T wi = r.w[o_p + i];
-        if (k > 0) {
-            wi = (T)((double)wi - bt * (double)r.vp[o_p + i]);
-            r.w[o_p + i] = wi;
-        }
-        acc += (double)wi * (double)r.v[o_p + i];
-    }
-    const double s = bblock_sum(acc, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
 // w -= alpha_k v; partial beta^2 = <w, w>.
@@ -425,6 +445,7 @@ struct hub_batch {
     int tb[2] = {1, 1}, bs[2] = {256, 256};
     int2 *items[2] = {nullptr, nullptr};
     int nitems[2] = {0, 0};
+    int *istart[2] = {nullptr, nullptr}, *icount[2] = {nullptr, nullptr};  // items of each sector
     double tune_seconds = 0.0;
 };
 
@@ -497,7 +518,7 @@ BDesc<T> make_desc(const hub_sector *s, int64_t off)
 
 template <typename T, int TB, int BS, bool SEL>
 hub_status launch_bk(hub_batch *b, int di, const T *x, T *y, T *const *ptrs, const int *step, const int *active,
-                     hipStream_t st)
+                     hipStream_t st, const double *beta, int kmax, double *ipart)
 {
     const size_t lds = (size_t)(256 + (size_t)b->max_cu * TB) * sizeof(T);
     static bool attr = false;
@@ -507,19 +528,22 @@ hub_status launch_bk(hub_batch *b, int di, const T *x, T *y, T *const *ptrs, con
         attr = true;
     }
     hipLaunchKernelGGL((k_batch_kron<T, TB, BS, SEL>), dim3(b->nitems[di]), dim3(BS), lds, st,
-                       (const BDesc<T> *)b->desc[di], b->items[di], x, y, ptrs, step, active);
+                       (const BDesc<T> *)b->desc[di], b->items[di], x, y, ptrs, step, active, beta, kmax, ipart);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
 
+// SEL: the Lanczos step (vectors from the pointer table, first update fused,
+// item partials of alpha in ipart; beta and kmax as in the solver's arrays)
 template <typename T, bool SEL>
 hub_status launch_batch_product(hub_batch *b, const T *x, T *y, T *const *ptrs, const int *step, const int *active,
-                                hipStream_t st)
+                                hipStream_t st, const double *beta = nullptr, int kmax = 0, double *ipart = nullptr)
 {
     const int di = (sizeof(T) == 8) ? 0 : 1;
     const int tb = b->tb[di], bs = b->bs[di];
 #define HUB_BK(TBV, BSV)                                                                 \
-    if (tb == TBV && bs == BSV) return launch_bk<T, TBV, BSV, SEL>(b, di, x, y, ptrs, step, active, st);
+    if (tb == TBV && bs == BSV)                                                          \
+        return launch_bk<T, TBV, BSV, SEL>(b, di, x, y, ptrs, step, active, st, beta, kmax, ipart);
     HUB_BK(1, 256) HUB_BK(2, 256) HUB_BK(4, 256) HUB_BK(8, 256)
     HUB_BK(1, 512) HUB_BK(2, 512) HUB_BK(4, 512) HUB_BK(8, 512)
 #undef HUB_BK
@@ -542,6 +566,16 @@ hub_status build_items(hub_batch *b, int di, int tb)
     HUB_TRY(balloc(b, &b->items[di], it.size()));
     HUB_HIP(hipMemcpy(b->items[di], it.data(), sizeof(int2) * it.size(), hipMemcpyHostToDevice));
     b->nitems[di] = (int)it.size();
+    // the items of sector p are [istart[p], istart[p] + icount[p]) (sector-major order)
+    std::vector<int> hs(b->P, 0), hc(b->P, 0);
+    for (int i = 0; i < (int)it.size(); ++i) {
+        if (hc[it[i].x] == 0) hs[it[i].x] = i;
+        ++hc[it[i].x];
+    }
+    if (!b->istart[di]) HUB_TRY(balloc(b, &b->istart[di], (size_t)b->P));
+    if (!b->icount[di]) HUB_TRY(balloc(b, &b->icount[di], (size_t)b->P));
+    HUB_HIP(hipMemcpy(b->istart[di], hs.data(), sizeof(int) * b->P, hipMemcpyHostToDevice));
+    HUB_HIP(hipMemcpy(b->icount[di], hc.data(), sizeof(int) * b->P, hipMemcpyHostToDevice));
     b->tb[di] = tb;
     return HUB_OK;
 }
@@ -656,6 +690,8 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
     HUB_TRY(alloc((void **)&alpha, sizeof(double) * (size_t)P * kmax));
     HUB_TRY(alloc((void **)&beta, sizeof(double) * (size_t)P * kmax));
     HUB_TRY(alloc((void **)&partial, sizeof(double) * (size_t)b->nblocks));
+    double *ipart = nullptr;  // alpha partials of the fused product, one per work item
+    HUB_TRY(alloc((void **)&ipart, sizeof(double) * (size_t)std::max(1, b->nitems[di])));
     HUB_TRY(alloc((void **)&nrm, sizeof(double) * (size_t)P * 4));
     HUB_TRY(alloc((void **)&ycoef, sizeof(double) * (size_t)P * kmax));
     HUB_HIP(hipMemcpyAsync(ptrs, V, sizeof(T *) * 4, hipMemcpyHostToDevice, st));
@@ -680,11 +716,10 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
 
     // one Lanczos step, captured as a graph
     auto one_step = [&]() -> hub_status {
-        HUB_TRY((launch_batch_product<T, true>(b, nullptr, nullptr, ptrs, step, active, st)));
-        hipLaunchKernelGGL(k_b_lz_a<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, ptrs, (const int *)step,
-                           (const double *)beta, kmax, partial, (const int *)active);
-        hipLaunchKernelGGL(k_b_final, dim3(P), dim3(BRB), 0, st, S, (const double *)partial, alpha, kmax, 0,
-                           (const int *)step, 0, 0, (const int *)active);
+        HUB_TRY((launch_batch_product<T, true>(b, nullptr, nullptr, ptrs, step, active, st, beta, kmax, ipart)));
+        hipLaunchKernelGGL(k_b_ifinal, dim3(P), dim3(BRB), 0, st, (const int *)b->istart[di],
+                           (const int *)b->icount[di], (const double *)ipart, alpha, kmax, (const int *)step,
+                           (const int *)active);
         hipLaunchKernelGGL(k_b_lz_b<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, ptrs, (const int *)step,
                            (const double *)alpha, kmax, partial, (const int *)active);
         hipLaunchKernelGGL(k_b_final, dim3(P), dim3(BRB), 0, st, S, (const double *)partial, beta, kmax, 0,
@@ -960,7 +995,9 @@ hub_status hub_batch_create(const hub_sector *const *sectors, int32_t count, hub
         b->max_cu = std::max(b->max_cu, (int)s->spin[0].count);
     }
     b->device = sectors[0]->device;
-    b->lds_max = sectors[0]->lds_max;
+    // dynamic LDS for the product's panel; 4 KB stay for the static reduction array
+    // of the fused Lanczos update (up to 512 doubles)
+    b->lds_max = sectors[0]->lds_max - 4096;
     HUB_HIP(hipSetDevice(b->device));
     if ((size_t)(256 + (size_t)b->max_cu) * 8 > b->lds_max)
         return bfail(HUB_ERR_UNSUPPORTED, "a sector's column does not fit in LDS for the batched product");
