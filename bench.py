@@ -103,9 +103,14 @@ def square_mixed_gradients(hub, torch, model):
     and homogeneous in its parameters) checks them."""
     import numpy as np
     sec = hub.Sector(model)
+    # time-to-E0 against the FP64 GPU value (no oracle value exists at this size)
+    e_ref = sec.ground_state(dtype=hub.F64, want_vector=False, tol=1e-10, max_iter=2000).e0
+    g64 = sec.ground_state(dtype=hub.F64, want_vector=False, tol=1e-8, max_iter=2000, e0_target=e_ref,
+                           e0_target_rel=1e-6)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g = sec.ground_state(dtype=hub.F32, reorth=False, refine=True, tol=1e-7, max_iter=600)
+    g = sec.ground_state(dtype=hub.F32, reorth=False, refine=True, tol=1e-7, max_iter=600, e0_target=e_ref,
+                         e0_target_rel=1e-6)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     db, dU, de = sec.param_bilinear(g.psi, g.psi)
@@ -118,6 +123,9 @@ def square_mixed_gradients(hub, torch, model):
            "e0_ritz_fp32": i["e0_ritz"], "e0_refined_fp64": i["e0_refined"],
            "rel_err_ritz_vs_refined": abs(i["e0_ritz"] - i["e0_refined"]) / abs(i["e0_refined"]),
            "true_residual_fp64": i["true_residual"], "dE_dU_sum": float(np.sum(dU)),
+           "e0_ref_fp64": e_ref,
+           "time_to_e0_s": {"fp64_plain": g64.info["seconds_to_target"], "mixed_plain": i["seconds_to_target"]},
+           "iters_to_e0": {"fp64_plain": g64.info["iters_to_target"], "mixed_plain": i["iters_to_target"]},
            "euler_identity_rel": abs(euler - i["e0_refined"]) / abs(i["e0_refined"])}
     del g
     sec.close()
