@@ -250,8 +250,9 @@ hub_status hub_batch_offsets(const hub_batch *batch, int64_t *offsets);
 hub_status hub_batch_matvec(hub_batch *batch, int32_t dtype, const void *dev_x, void *dev_y, void *stream);
 
 typedef struct hub_batch_info {
-    int32_t steps;            /* lockstep Lanczos steps taken (max over sectors) */
-    int32_t graph_replays;    /* steps executed by replaying the captured step graph */
+    int32_t steps;            /* lockstep Lanczos steps executed (max over sectors; includes the
+                                 group run while the last convergence test was on the host) */
+    int32_t graph_replays;    /* steps executed by replaying a captured step or group graph */
     int32_t tile_columns;     /* tuned columns per workgroup of the product */
     int32_t block_size;       /* tuned workgroup size of the product */
     double seconds;           /* wall time of the call */
@@ -261,8 +262,11 @@ typedef struct hub_batch_info {
 /*
  * Lowest eigenvalue of every sector of the batch by the plain Lanczos
  * recurrence (Sec. IV) run in lockstep: per-sector alpha / beta in FP64 on the
- * device, converged sectors masked out, one step captured once as a HIP graph
- * and replayed.  opts as for hub_ground_state except reorth (must be 0:
+ * device, converged sectors masked out, one step (and one group of check_every
+ * steps, default 5) captured once as a HIP graph and replayed.  The test after a
+ * group runs on the host while the GPU runs the next group, so a sector may
+ * step one group past its convergence (those steps are not used).  opts as for
+ * hub_ground_state except reorth (must be 0:
  * UNSUPPORTED) and dev_start (must be NULL: UNSUPPORTED); refine without
  * dev_psi is INVALID_ARG.
  * e0[count] receives the Ritz values (or FP64 Rayleigh quotients with refine),
