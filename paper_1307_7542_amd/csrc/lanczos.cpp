@@ -275,6 +275,10 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     double *apart = nullptr;
     if (fused) HUB_TRY(mem.alloc((void **)&apart, sizeof(double) * (size_t)matvec_lz_partials(s)));
     if (fused) inf.matvec_bytes += (int64_t)es * n;  // the update's read of v_prev
+    // Up to this many per-column partials, every block of the update kernel sums
+    // them itself (the 4x4 torus: 11440, a few microseconds per launch) instead
+    // of a separate single-block launch.
+    constexpr int64_t kSumInUpdate = 65536;
     // fused: alpha's per-column partials are left in apart[0 .. np_alpha) and
     // summed by the w -= alpha v update (lz_b below); otherwise alpha goes to aout
     int64_t np_alpha = 0;
@@ -295,7 +299,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     // product's partials, inside the update when they are few); beta^2 partials
     // left in partial[0 .. red_grid(n)), their square-rooted sum in *beta_out if given
     auto lz_b = [&](const void *vv, double *alpha_io, double *beta_out) -> hub_status {
-        if (fused && np_alpha <= 8192) {
+        if (fused && np_alpha <= kSumInUpdate) {
             HUB_TRY(launch_lz_b_sum(dt, W, vv, apart, np_alpha, alpha_io, n, partial, st));
             if (beta_out) HUB_TRY(launch_sum(partial, red_grid(n), beta_out, st, 1));
             return HUB_OK;
@@ -346,7 +350,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     // The product's epilogue and the update scale by 1 / beta_k in FP64, so no
     // normalisation pass is needed; a step is the fused product, the update and a
     // one-block kernel that forms and publishes beta_{k+1}.
-    const bool unnorm = fused && publish && matvec_lz_partials(s) <= 8192;
+    const bool unnorm = fused && publish && matvec_lz_partials(s) <= kSumInUpdate;
     const double *ha = hpin, *hb = hpin + kmax;
     hipEvent_t copied;
     HUB_HIP(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
