@@ -572,6 +572,9 @@ def test_unnormalised_recurrence_matches_normalised(hub, monkeypatch):
         ov = float(torch.dot(g_un.psi, g_no.psi))
         assert abs(ov) >= 1.0 - tol_v, (dt, ov)
         assert g_un.info["true_residual"] <= (1e-9 if dt == hub.F64 else 1e-5) * abs(g_un.e0)
+        # convergence tested every 4th step (waits on a later published step)
+        g4 = s.ground_state(check_every=4, **kw)
+        assert abs(g4.e0 - g_no.e0) <= tol_e * abs(g_no.e0) and g4.info["iters"] % 4 == 0
     s.close()
 
 
