@@ -161,6 +161,7 @@ hub_status launch_dot(int dtype, const void *x, const void *y, int64_t n, double
                       int sqrt_result, hipStream_t st);
 hub_status launch_convert(int din, const void *x, int dout, void *y, int64_t n, const double *scale_dev,
                           int invert, hipStream_t st);
+// alpha_out NULL: leave the red_grid(n) partials of alpha in partial, no final sum
 hub_status launch_lz_a(int dtype, void *w, const void *vprev, const double *beta, const void *v, int64_t n,
                        double *partial, double *alpha_out, hipStream_t st);
 // beta_div (may be NULL): v is the unnormalised beta_k v_k, subtract (alpha / beta_k) v

@@ -293,7 +293,10 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             return HUB_OK;
         }
         HUB_TRY(product(x, y));
-        return launch_lz_a(dt, y, vp, bk, x, n, partial, aout, st);
+        if (!aout) return launch_lz_a(dt, y, vp, bk, x, n, partial, nullptr, st);
+        // partials of alpha beside the ones the update writes; summed inside it
+        np_alpha = red_grid(n);
+        return launch_lz_a(dt, y, vp, bk, x, n, partial + kRedGrid, nullptr, st);
     };
     // W -= alpha_k v with alpha_k written to *alpha_io (fused: formed from the
     // product's partials, inside the update when they are few); beta^2 partials
@@ -304,7 +307,12 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             if (beta_out) HUB_TRY(launch_sum(partial, red_grid(n), beta_out, st, 1));
             return HUB_OK;
         }
-        if (fused) HUB_TRY(launch_sum(apart, np_alpha, alpha_io, st));
+        if (!fused) {
+            HUB_TRY(launch_lz_b_sum(dt, W, vv, partial + kRedGrid, np_alpha, alpha_io, n, partial, st));
+            if (beta_out) HUB_TRY(launch_sum(partial, red_grid(n), beta_out, st, 1));
+            return HUB_OK;
+        }
+        HUB_TRY(launch_sum(apart, np_alpha, alpha_io, st));
         return launch_lz_b(dt, W, vv, alpha_io, n, partial, beta_out, st);
     };
 
@@ -627,10 +635,13 @@ hub_status lanczos_coefficients(const hub_sector *s, const double *f, int max_st
     double tmax = 0.0;
     for (int k = 0; k < kmax; ++k) {
         HUB_TRY(apply_h(s, HUB_F64, v, W, st));
-        HUB_TRY(launch_lz_a(HUB_F64, W, v_prev, d_beta + k, v, n, partial, d_alpha + k, st));
-        HUB_TRY(launch_lz_b(HUB_F64, W, v, d_alpha + k, n, partial, d_beta + k + 1, st));
+        // alpha's partials beside beta's; both summed inside the kernels that use them
+        HUB_TRY(launch_lz_a(HUB_F64, W, v_prev, d_beta + k, v, n, partial + kRedGrid, nullptr, st));
+        HUB_TRY(launch_lz_b_sum(HUB_F64, W, v, partial + kRedGrid, red_grid(n), d_alpha + k, n, partial, st));
         const bool last = (k + 1 == kmax);
-        if ((k + 1) % 16 == 0 || last) {
+        const bool check_now = (k + 1) % 16 == 0 || last;
+        if (check_now) HUB_TRY(launch_sum(partial, red_grid(n), d_beta + k + 1, st, 1));
+        if (check_now) {
             const int mm = k + 1;
             HUB_HIP(hipMemcpyAsync(ha.data(), d_alpha, sizeof(double) * mm, hipMemcpyDeviceToHost, st));
             HUB_HIP(hipMemcpyAsync(hb.data(), d_beta, sizeof(double) * (mm + 1), hipMemcpyDeviceToHost, st));
@@ -649,7 +660,11 @@ hub_status lanczos_coefficients(const hub_sector *s, const double *f, int max_st
         }
         if (last) break;
         void *vn = v_prev ? v_prev : spare;
-        HUB_TRY(launch_lz_next(HUB_F64, W, vn, d_beta + k + 1, n, st));
+        if (check_now) {
+            HUB_TRY(launch_lz_next(HUB_F64, W, vn, d_beta + k + 1, n, st));
+        } else {
+            HUB_TRY(launch_lz_next_sum(HUB_F64, W, vn, partial, d_beta + k + 1, n, st));
+        }
         v_prev = v;
         v = vn;
     }

@@ -579,7 +579,7 @@ hub_status launch_lz_a(int dtype, void *w, const void *vprev, const double *beta
     else
         hipLaunchKernelGGL(k_lz_a<float>, dim3(G), dim3(RB), 0, st, (float *)w, (const float *)vprev, beta,
                            (const float *)v, n, partial);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, G, alpha_out, 0);
+    if (alpha_out) hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, G, alpha_out, 0);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
