@@ -10,22 +10,25 @@
 // The two terms want orthogonal access patterns.  In column-major storage the
 // H_dn term combines whole neighbouring columns (coalesced, with a row of H_dn
 // that is uniform over a workgroup), while the H_up term gathers inside one
-// column along a different row of H_up for every lane.  Three schedules:
+// column along a different row of H_up for every lane.  Schedules:
 //
-//   fused   : one workgroup per TB output columns; the TB input columns are
-//             staged in LDS for the H_up gathers, the H_dn neighbour columns
-//             are read through L2 / MALL.  One HBM pass when the neighbour
-//             columns hit in cache.
-//   two-pass: (1) Z = V H_dn^T on row tiles that every workgroup of one XCD
-//             sweeps together, so the tile stays in that XCD's L2 while its
-//             ~deg_dn re-reads happen; (2) Y = Z + H_up V + D o V on LDS column
-//             panels.  Two HBM passes over V, bounded cache footprint.
-//   csr     : plain per-column kernel over CSR rows (fallback when a column
-//             does not fit in LDS).
+//   k_kron_quad (default when count_up % 4 == 0 and a column fits in LDS): one
+//             workgroup per TB output columns, the TB input columns staged in
+//             LDS for the H_up gathers, the H_dn neighbour columns read through
+//             L2 / MALL; each lane owns four consecutive rows (16-byte accesses).
+//             The tile shape is timed on the first product and cached; the
+//             first Lanczos update can be fused into its epilogue.
+//   k_kron_fused: the same schedule with one row per lane (count_up % 4 != 0).
+//   k_kron_chunked_parts (a column larger than the LDS): work items of TB
+//             columns x a part of the rows; the row chunks of the columns are
+//             staged in turn and the output rows stay in registers.
+//   two-pass, csr, one-row chunked: kept for measurement and for sectors whose
+//             entries do not fit the compact format (csr fallback).
 //
 // H_up is read from its sliced-ELL copy: lane r of a wavefront owns row
-// 64*s + r of slice s and loads entry k, packed {column, value}, from a
-// coalesced address.
+// 64*s + r of slice s and loads entry k from a coalesced address; the default
+// entry is {column : 24, code : 8} with the value looked up in a 256-entry
+// table in LDS.
 #include <algorithm>
 #include <cstdlib>
 #include <map>
