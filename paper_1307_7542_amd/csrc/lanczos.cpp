@@ -1,9 +1,12 @@
 // Host driver of the Lanczos ground-state solve (Sec. IV).  The product and all
 // vector work run in the HIP kernels of matvec.hip / vec.hip on the caller's
-// stream; alpha and beta stay in device memory and are copied to the host only
-// when the convergence test runs.  The small tridiagonal eigenproblem is solved
-// on the host: the lowest eigenvalue by bisection on the Sturm sequence count,
-// its eigenvector by inverse iteration with a partially pivoted tridiagonal LU.
+// stream; alpha and beta are formed on the device and reach the host either
+// through pinned memory that the step's last kernel writes (plain recurrence)
+// or by a copy at the convergence test (full reorthogonalisation, k = 0
+// reprojection); the test runs while the GPU computes the next step.  The small
+// tridiagonal eigenproblem is solved on the host: the lowest eigenvalue by
+// bisection on the Sturm sequence count, its eigenvector by inverse iteration
+// with a partially pivoted tridiagonal LU.
 #include <algorithm>
 #include <chrono>
 #include <cfloat>

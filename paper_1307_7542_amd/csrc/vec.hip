@@ -4,9 +4,10 @@
 //
 // Reductions are deterministic: a fixed number of blocks (a function of n
 // only) each reduce a contiguous stride pattern into one FP64 partial with an
-// LDS tree, and a single block sums the partials in a fixed order.  Repeating
-// a computation therefore reproduces it bit for bit, which the two-pass
-// eigenvector assembly relies on.
+// LDS tree, and the partials are summed in a fixed order, by a single block or
+// by every block of the kernel that needs the total (the same order, so the
+// same value).  Repeating a computation therefore reproduces it bit for bit,
+// which the two-pass eigenvector assembly relies on.
 //
 // Vectors of FP32 ("mixed") or FP64 storage; every scalar (alpha, beta, Gram
 // coefficients, norms) is FP64 and every update is evaluated in FP64 and
