@@ -30,6 +30,7 @@
 // entry is {column : 24, code : 8} with the value looked up in a 256-entry
 // table in LDS.
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -1305,7 +1306,10 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
     const int nt = env_int("HUB_DN_NT", 1);
     const int rows = env_int("HUB_FUSED_R", 4);
     const bool cf = env_int("HUB_ELL_FMT", 1) != 0;
-    const bool quad = env_int("HUB_MATVEC_QUAD", 1) != 0;
+    // four-rows-per-lane kernels use 16-byte accesses: caller vectors that are
+    // not 16-byte aligned take the one-row-per-lane kernels
+    const bool aligned16 = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0;
+    const bool quad = env_int("HUB_MATVEC_QUAD", 1) != 0 && aligned16;
     const size_t extra = 256 * sizeof(T);
     const size_t half = s->lds_max / 2;
     int tb = tb_env;

@@ -679,3 +679,33 @@ def test_matvec_row_chunked_several_row_parts(hub, parts, tb, monkeypatch):
     yr32 = oracle.spmv(osec.csr(), x32.double().cpu().numpy())
     assert np.all(np.abs(y32 - yr32) <= 1e-5 * bound + 1e-30)
     s.close()
+
+
+@pytest.mark.parametrize("which", ["square3x4_n5", "ring10_eps"])
+def test_matvec_unaligned_views(hub, which, monkeypatch):
+    """Vectors that start at an element but not a 16-byte boundary (views into a
+    larger buffer) take the one-row-per-lane kernels and give the oracle's product;
+    also with the row-chunked schedule forced."""
+    import torch
+    m = _variant_model(which)
+    for chunk in (None, 200):
+        if chunk:
+            monkeypatch.setenv("HUB_CHUNK_ROWS", str(chunk))
+        s = hub.Sector(m)
+        osec = oracle.Sector(m)
+        xr = oracle.start_vector(13, osec.dim)
+        bound = _row_abs(osec, xr)
+        for dt, tol in ((hub.F64, 1e-13), (hub.F32, 1e-5)):
+            tdt = torch.float64 if dt == hub.F64 else torch.float32
+            xb = torch.zeros(osec.dim + 1, dtype=tdt, device="cuda")
+            yb = torch.zeros(osec.dim + 3, dtype=tdt, device="cuda")
+            x = xb[1:]
+            x.copy_(torch.from_numpy(xr).to(tdt))
+            y = yb[3:]
+            assert x.data_ptr() % 16 != 0 and y.data_ptr() % 16 != 0
+            s.matvec(x, y)
+            ref = oracle.spmv(osec.csr(), x.double().cpu().numpy())
+            assert np.all(np.abs(y.double().cpu().numpy() - ref) <= tol * bound + 1e-30), (which, chunk, dt)
+        s.close()
+        if chunk:
+            monkeypatch.delenv("HUB_CHUNK_ROWS")
