@@ -27,8 +27,10 @@
  *     (Sec. III A).  Up operators are ordered before down operators (Sec. II),
  *     so no sign couples the two spins and H is exactly the Kronecker sum.
  *   - Vectors passed as device pointers hold count_up * count_dn elements of the
- *     stated dtype, column-major as above, 256-byte aligned is recommended
- *     (required: element alignment).  The caller owns them.
+ *     stated dtype, column-major as above.  Element alignment is required;
+ *     16-byte alignment (any fresh allocation) lets the product use its
+ *     16-byte-access kernels, otherwise it takes slower one-row kernels.  The
+ *     caller owns them.
  *
  * Errors: every entry point returns a hub_status; none aborts or throws.
  * hub_last_error() gives a thread-local message for the last failure.
