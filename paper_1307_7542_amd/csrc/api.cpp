@@ -2,6 +2,7 @@
 // and dispatch to the HIP kernels.  No entry point aborts or throws.
 #include <cmath>
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -346,6 +347,8 @@ hub_status hub_matvec(const hub_sector *sec, int32_t dtype, const void *dev_x, v
     const size_t bytes = (size_t)sec->dim * (dtype == HUB_F64 ? 8 : 4);
     const char *x = (const char *)dev_x, *y = (const char *)dev_y;
     if (x < y + bytes && y < x + bytes) return fail(HUB_ERR_INVALID_ARG, "x and y overlap");
+    const uintptr_t es = (dtype == HUB_F64) ? 8 : 4;
+    if (((uintptr_t)x | (uintptr_t)y) % es) return fail(HUB_ERR_INVALID_ARG, "x or y not aligned to its element");
     return apply_h(sec, dtype, dev_x, dev_y, (hipStream_t)stream);
 }
 

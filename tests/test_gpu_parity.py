@@ -239,10 +239,19 @@ def test_matvec_repeatable_bitwise(hub):
 
 
 def test_matvec_rejects_overlap(hub):
+    import ctypes
+    import torch
     s = hub.Sector(W.config("ring8"))
     x = s.start_vector(seed=1)
     with pytest.raises(hub.HubError):
         s.matvec(x, x)
+    buf = torch.zeros(2 * s.dim + 4, dtype=torch.float64, device="cuda")
+    with pytest.raises(hub.HubError):          # partial overlap
+        s.matvec(buf[:s.dim], buf[5:5 + s.dim])
+    # a pointer that is not aligned to its element is refused before any launch
+    st = hub.lib().hub_matvec(s._h, hub.F64, ctypes.c_void_p(buf.data_ptr() + 4),
+                              ctypes.c_void_p(buf.data_ptr() + 8 * (s.dim + 2)), None)
+    assert st == 1  # HUB_ERR_INVALID_ARG
     s.close()
 
 
