@@ -324,6 +324,14 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
         const bool live = !EPI || q < nq;
         const int a0 = 4 * (live ? q : 0);
         T acc[4][TB];
+        // the epilogue's v_prev rows are loaded first: a lane runs only one or
+        // two iterations, so a load issued after the gathers leaves its latency exposed
+        Q4<T> vpq[EPI ? TB : 1];
+        if (EPI && live && E.vprev) {
+#pragma unroll
+            for (int t = 0; t < TB; ++t)
+                vpq[t] = ld_q4(E.vprev + (int64_t)min(b0 + t, cd - 1) * cu64 + a0);
+        }
         const uint4 ub = *reinterpret_cast<const uint4 *>(A.up_basis + a0);
         const uint32_t uu[4] = {ub.x, ub.y, ub.z, ub.w};
         const Q4<T> eu = ld_q4(A.e_up + a0);
@@ -390,7 +398,7 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
                 if (live) {
                     if (E.unnorm) {
                         if (E.vprev) {
-                            const Q4<T> vp = ld_q4(E.vprev + (int64_t)(b0 + t) * cu64 + a0);
+                            const Q4<T> &vp = vpq[t];
 #pragma unroll
                             for (int r = 0; r < 4; ++r) o[r] = (T)(sx * (double)o[r] - bt * (double)vp.v[r]);
                         } else {
@@ -398,7 +406,7 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
                             for (int r = 0; r < 4; ++r) o[r] = (T)(sx * (double)o[r]);
                         }
                     } else if (E.vprev) {
-                        const Q4<T> vp = ld_q4(E.vprev + (int64_t)(b0 + t) * cu64 + a0);
+                        const Q4<T> &vp = vpq[t];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) o[r] = (T)((double)o[r] - bt * (double)vp.v[r]);
                     }
@@ -1225,7 +1233,8 @@ bool lz_fusable(const hub_sector *s)
     const size_t col_bytes = (size_t)U.count * sizeof(T);
     return !s->k0 && env_int("HUB_MATVEC_IMPL", 2) == 2 && env_int("HUB_MATVEC_QUAD", 1) != 0 &&
            env_int("HUB_ELL_FMT", 1) != 0 && env_int("HUB_LZ_FUSE", 1) != 0 && U.ell_c32 && !s->force_chunked &&
-           (U.count % 4) == 0 && col_bytes + 256 * sizeof(T) <= s->lds_max;
+           (U.count % 4) == 0 &&
+           col_bytes + 256 * sizeof(T) + (size_t)((U.count / 4 + 63) / 64) * sizeof(double) <= s->lds_max;
 }
 
 template <typename T>
