@@ -121,6 +121,7 @@ struct hub_sector {
     std::vector<void *> owned;        // every device allocation, freed by destroy
     hub::K0Tables *k0 = nullptr;      // set for a translation-symmetric k = 0 sector
     mutable hub::QuadShape quad[2];   // per dtype (0: FP64, 1: FP32), set by the first product
+    mutable hub::QuadShape quad_lz[2];  // the same for the product fused with the Lanczos update
 };
 
 namespace hub {

@@ -1141,8 +1141,16 @@ hub_status launch_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, 
 // the LDS (1 warm-up + 5 timed launches on the caller's x and y; every shape
 // computes the same values in the same order) and keep the fastest; a later
 // candidate must win by 3 % so that timing noise rarely changes the pick.
+// Times every shape that fits, in two interleaved rounds of five launches,
+// and keeps the one with the smallest time (each shape's better round).  epi: the shapes are timed as the
+// product fused with the first Lanczos update, whose ranking differs from the
+// plain product's (on the ring M=14, FP32 with two columns per workgroup:
+// 57 vs 55 us plain but 90 vs 75 us fused for 1024 vs 512 lanes); the epilogue
+// then reads x as v_prev with beta = 0 and writes its partials to apart
+// (count_dn doubles), all overwritten by the caller's own launch.
 template <typename T>
-hub_status tune_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, QuadShape &out)
+hub_status tune_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, QuadShape &out, bool epi,
+                     double *apart)
 {
     hipEvent_t e0, e1;
     HUB_HIP(hipEventCreate(&e0));
@@ -1151,29 +1159,50 @@ hub_status tune_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, Qu
         hipEvent_t a, b;
         ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     } ev{e0, e1};
-    float best = 1e30f;
-    QuadShape pick;
+    const int G = (int)(((A.cu >> 2) + 63) / 64);
+    double *zero = nullptr;
+    struct Buf {
+        double *p = nullptr;
+        ~Buf() { (void)hipFree(p); }
+    } zb;
+    LzEpi<T> E{};
+    if (epi) {
+        HUB_HIP(hipMalloc((void **)&zero, sizeof(double)));
+        zb.p = zero;
+        HUB_HIP(hipMemsetAsync(zero, 0, sizeof(double), st));
+        E = LzEpi<T>{A.x, zero, apart, G, nullptr, 0};
+    }
+    std::vector<QuadShape> cand;
     for (int tb = 1; tb <= 3; ++tb) {
-        if ((size_t)(A.cu * tb + 256) * sizeof(T) > s->lds_max) break;
+        const size_t lds = (size_t)(A.cu * tb + 256) * sizeof(T) + (epi ? (size_t)tb * G * sizeof(double) : 0);
+        if (lds > s->lds_max) break;
         for (int bs : {512, 1024})
             for (int xc : {0, 1}) {
-                HUB_TRY(launch_quad<T>(s, A, st, tb, bs, xc));
-                HUB_HIP(hipEventRecord(e0, st));
-                for (int r = 0; r < 5; ++r) HUB_TRY(launch_quad<T>(s, A, st, tb, bs, xc));
-                HUB_HIP(hipEventRecord(e1, st));
-                HUB_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HUB_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < 0.97f * best) {
-                    best = ms;
-                    pick.tb = tb;
-                    pick.bs = bs;
-                    pick.xc = xc;
-                }
+                QuadShape c;
+                c.tb = tb;
+                c.bs = bs;
+                c.xc = xc;
+                c.ms = 1e30f;
+                cand.push_back(c);
             }
     }
-    pick.ms = best / 5.0f;
-    out = pick;
+    if (cand.empty()) {
+        set_error("no product shape fits in LDS");
+        return HUB_ERR_UNSUPPORTED;
+    }
+    for (int round = 0; round < 2; ++round)
+        for (QuadShape &c : cand) {
+            HUB_TRY(launch_quad<T>(s, A, st, c.tb, c.bs, c.xc, epi ? &E : nullptr));
+            HUB_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < 5; ++r) HUB_TRY(launch_quad<T>(s, A, st, c.tb, c.bs, c.xc, epi ? &E : nullptr));
+            HUB_HIP(hipEventRecord(e1, st));
+            HUB_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HUB_HIP(hipEventElapsedTime(&ms, e0, e1));
+            c.ms = std::min(c.ms, ms / 5.0f);
+        }
+    out = *std::min_element(cand.begin(), cand.end(),
+                            [](const QuadShape &a, const QuadShape &b) { return a.ms < b.ms; });
     return HUB_OK;
 }
 
@@ -1183,10 +1212,11 @@ hub_status tune_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, Qu
 struct ShapeKey {
     int device, dtype;
     int64_t cu, cd, nnz_up, nnz_dn;
+    int epi;
     bool operator<(const ShapeKey &o) const
     {
-        return std::tie(device, dtype, cu, cd, nnz_up, nnz_dn) <
-               std::tie(o.device, o.dtype, o.cu, o.cd, o.nnz_up, o.nnz_dn);
+        return std::tie(device, dtype, cu, cd, nnz_up, nnz_dn, epi) <
+               std::tie(o.device, o.dtype, o.cu, o.cd, o.nnz_up, o.nnz_dn, o.epi);
     }
 };
 std::mutex g_shape_mu;
@@ -1194,9 +1224,11 @@ std::map<ShapeKey, QuadShape> g_shapes;
 
 // Shape of the four-rows-per-lane product: forced by HUB_MATVEC_TB / _BS / _XC,
 // else the sector's tuned shape (tuning on first use, shared by sectors of
-// the same structure).
+// the same structure).  epi: the shape of the product fused with the Lanczos
+// update, tuned separately (apart: its partials buffer, used while tuning).
 template <typename T>
-hub_status quad_shape(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, QuadShape &out)
+hub_status quad_shape(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, QuadShape &out, bool epi = false,
+                      double *apart = nullptr)
 {
     const int di = (sizeof(T) == 8) ? 0 : 1;
     const int tb_env = env_int("HUB_MATVEC_TB", 0);
@@ -1207,16 +1239,16 @@ hub_status quad_shape(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, Q
         out.xc = env_int("HUB_MATVEC_XC", 1) != 0 ? 1 : 0;
         return HUB_OK;
     }
-    QuadShape &q = s->quad[di];
+    QuadShape &q = epi ? s->quad_lz[di] : s->quad[di];
     if (q.tb == 0) {
-        const ShapeKey key{s->device, di, (int64_t)A.cu, (int64_t)A.cd, s->spin[0].nnz, s->spin[1].nnz};
+        const ShapeKey key{s->device, di, (int64_t)A.cu, (int64_t)A.cd, s->spin[0].nnz, s->spin[1].nnz, epi ? 1 : 0};
         {
             std::lock_guard<std::mutex> lk(g_shape_mu);
             auto it = g_shapes.find(key);
             if (it != g_shapes.end()) q = it->second;
         }
         if (q.tb == 0) {
-            HUB_TRY(tune_quad<T>(s, A, st, q));
+            HUB_TRY(tune_quad<T>(s, A, st, q, epi, apart));
             std::lock_guard<std::mutex> lk(g_shape_mu);
             g_shapes[key] = q;
         }
@@ -1244,7 +1276,7 @@ hub_status run_kron_lz(const hub_sector *s, const void *x, void *w, const void *
     if (!lz_fusable<T>(s)) return HUB_ERR_UNSUPPORTED;
     MvArgs<T> A = make_args<T>(s, x, w);
     QuadShape q;
-    HUB_TRY(quad_shape<T>(s, A, st, q));
+    HUB_TRY(quad_shape<T>(s, A, st, q, true, apart));
     const int G = (int)(((A.cu >> 2) + 63) / 64);
     const LzEpi<T> E{(const T *)vprev, beta, apart, G, beta_prev, unnorm};
     *npart = (int64_t)A.cd;
