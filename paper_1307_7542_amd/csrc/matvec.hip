@@ -243,6 +243,8 @@ __device__ __forceinline__ void st_q4(T *p, const T (&v)[4])
 // vprev = beta_{k-1} v_{k-1} (beta_0 taken as 1, beta NULL at the first step),
 // and the epilogue forms w = (H x) / beta_k - (beta_k / beta_{k-1}) vprev in
 // FP64 before the one rounding; the partials are then of <w, x> = beta_k alpha_k.
+// Both updates are written as explicit fused multiply-adds, so every tile
+// shape (each its own template instance) rounds them the same way.
 template <typename T>
 struct LzEpi {
     const T *vprev;           // NULL at the first step
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
                         if (E.vprev) {
                             const Q4<T> &vp = vpq[t];
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) o[r] = (T)(sx * (double)o[r] - bt * (double)vp.v[r]);
+                            for (int r = 0; r < 4; ++r) o[r] = (T)fma(sx, (double)o[r], -(bt * (double)vp.v[r]));
                         } else {
 #pragma unroll
                             for (int r = 0; r < 4; ++r) o[r] = (T)(sx * (double)o[r]);
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
                     } else if (E.vprev) {
                         const Q4<T> &vp = vpq[t];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) o[r] = (T)((double)o[r] - bt * (double)vp.v[r]);
+                        for (int r = 0; r < 4; ++r) o[r] = (T)fma(-bt, (double)vp.v[r], (double)o[r]);
                     }
 #pragma unroll
                     for (int r = 0; r < 4; ++r) part += (double)o[r] * (double)xs[(a0 + r) * TB + t];

@@ -602,6 +602,35 @@ def test_unnormalised_recurrence_breakdown(hub):
     s.close()
 
 
+@pytest.mark.gpu
+def test_fused_solve_same_for_every_tile_shape(hub, monkeypatch):
+    """The fused product's tile shape (columns per workgroup, workgroup size,
+    tile order) is tuned in each process, so a solve must not depend on it.  On
+    a sector whose 91 down-spin columns leave a partial tile of two and of three
+    columns, and whose 3432 rows leave a partial group of 64 lane-quads, every
+    forced shape gives the same energy and step count bit for bit, on both
+    precisions, and that energy is the oracle's."""
+    m = W.ring(14, U=4.0, n_up=7, n_dn=2)
+    s = hub.Sector(m)
+    assert s.count_up % 4 == 0 and s.count_dn % 2 == 1 and s.count_dn % 3 != 0
+    assert (s.count_up // 4) % 64 != 0
+    _, e_ref, _ = oracle.ground_state(m, want_vector=False)
+    shapes = [(tb, bs, xc) for tb in (1, 2, 3) for bs in (512, 1024) for xc in (0, 1)]
+    for dt, tol, rel in ((hub.F64, 1e-12, 1e-10), (hub.F32, 1e-7, 1e-5)):
+        got = []
+        for tb, bs, xc in shapes:
+            monkeypatch.setenv("HUB_MATVEC_TB", str(tb))
+            monkeypatch.setenv("HUB_MATVEC_BS", str(bs))
+            monkeypatch.setenv("HUB_MATVEC_XC", str(xc))
+            g = s.ground_state(dtype=dt, tol=tol, want_vector=False)
+            got.append((g.e0, g.info["iters"]))
+        for k in ("HUB_MATVEC_TB", "HUB_MATVEC_BS", "HUB_MATVEC_XC"):
+            monkeypatch.delenv(k)
+        assert all(r == got[0] for r in got), (dt, list(zip(shapes, got)))
+        assert abs(got[0][0] - e_ref) <= rel * abs(e_ref), (dt, got[0], e_ref)
+    s.close()
+
+
 def _variant_model(which):
     if which == "ring10_eps":
         return W.ring(10, U=3.0, n_up=5, n_dn=4).with_params(eps=[0.1 * i for i in range(10)])
