@@ -412,10 +412,9 @@ def main():
         if ent and cj.get("matvec_source_sha256") == sha:
             out["roofline"]["traffic"] = ent["traffic_bytes"]
             out["roofline"]["traffic_note"] = ("FETCH_SIZE x %.3f + WRITE_SIZE x %.3f per launch (copy-kernel "
-                                               "calibration), U=4, counters taken on %s (the shape the tuner "
-                                               "kept in that process)" % (cj["calibration"]["fetch_scale"],
-                                                                          cj["calibration"]["write_scale"],
-                                                                          ent["kernel"]))
+                                               "calibration), U=4, counters taken on %s; %s"
+                                               % (cj["calibration"]["fetch_scale"], cj["calibration"]["write_scale"],
+                                                  ent["kernel"], cj.get("shape_note", "")))
     except (OSError, KeyError, ValueError):
         pass
     if not args.no_extra:
