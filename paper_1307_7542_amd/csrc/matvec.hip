@@ -527,12 +527,11 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_quad(MvArgs<T> A, const int
 // Row-chunked product with the output held in registers: work item (tile of TB
 // columns, row part j) owns quads [j BS QPL, (j+1) BS QPL) of its columns, QPL
 // per lane.  It stages every row chunk of its columns in turn (interleaved,
-// element (a, t) at a TB + t; the P parts of a tile are consecutive work items
-// of one XCD, so the chunks come from that XCD's L2) and accumulates the
-// chunk's H_up entries of its rows, each entry serving the TB columns; then the
-// H_dn term and one store.  Per element: diagonal, H_up entries in column
-// order, H_dn entries -- the order of k_kron_quad -- and no partial results in
-// memory.  Tiles are interleaved over the XCDs (tile = 8 k + xcd).
+// element (a, t) at a TB + t) and accumulates the chunk's H_up entries of its
+// rows, each entry serving the TB columns; then the H_dn term and one store.
+// Per element: diagonal, H_up entries in column order, H_dn entries -- the
+// order of k_kron_quad -- and no partial results in memory.  Tiles are
+// interleaved over the XCDs (tile = 8 k + xcd), row parts dispatched in turn.
 template <typename T, int BS, int QPL, int TB>
 __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const int32_t *__restrict__ ch_off,
                                                            const int64_t *__restrict__ ch_base,
@@ -544,9 +543,14 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const in
     T *tab = reinterpret_cast<T *>(smem_raw);
     T *xs = tab + 256;
     const int xcd = (int)(blockIdx.x & 7), r = (int)(blockIdx.x >> 3);
-    const int tile = 8 * (r / P) + xcd, part = r % P;
     const int cd = A.cd;
     const int ntiles = (cd + TB - 1) / TB;
+    // part-major: every tile's first row part, then every tile's second, ... so
+    // the neighbour rows the chip reads at a time are one part's (2x9 ladder:
+    // FP32 30.6 -> 30.0 ms, FP64 57.8 -> 56.1 ms against the parts of a tile
+    // dispatched together)
+    const int n8 = (ntiles + 7) / 8;
+    const int tile = 8 * (r % n8) + xcd, part = r / n8;
     if (tile >= ntiles) return;
     const int b0 = tile * TB;
     const int cu = A.cu, nq = cu >> 2;
