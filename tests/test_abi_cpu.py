@@ -104,3 +104,26 @@ def test_continued_fraction_host_entry_point():
     ref = og.continued_fraction(a, b[1:], 0.8, w)
     np.testing.assert_allclose(got, ref, rtol=1e-13, atol=0)
     assert np.all(hub.continued_fraction(a, b, 0, 0.8, w) == 0)
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    """With the shared library absent the binding raises: there is no CPU path
+    behind it."""
+    import paper_1307_7542_amd as hub
+    monkeypatch.setattr(hub, "LIB_PATH", os.path.join(ROOT, "does_not_exist", "libhubbard.so"))
+    monkeypatch.setattr(hub, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        hub.lib()
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU; asked for more it prints one JSON line naming
+    the error and exits with status 2 before touching a device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
