@@ -151,7 +151,11 @@ hub_status hub_start_vector(const hub_sector *sec, int32_t dtype, uint64_t seed,
  * y = H x as the Kronecker sum Y = H_up X + X H_dn^T + D o X (Sec. IV A), in
  * `dtype` arithmetic (FP32 accumulates in FP32).  dev_x and dev_y are dim-long
  * device vectors; they must not overlap (INVALID_ARG).  Asynchronous on
- * `stream`.
+ * `stream`, except that the first product of each dtype for a sector
+ * structure (lattice and particle numbers) on a device may first time the
+ * tile shapes on dev_x / dev_y (several launches, writing dev_y) and wait for
+ * them; the chosen shape is kept for the process and does not change the
+ * result.
  */
 hub_status hub_matvec(const hub_sector *sec, int32_t dtype, const void *dev_x, void *dev_y, void *stream);
 
@@ -165,9 +169,10 @@ hub_status hub_matvec(const hub_sector *sec, int32_t dtype, const void *dev_x, v
  *                        eigenproblem and the optional refinement in FP64.
  *   reorth = 0: plain recurrence; psi by a second pass over the same
  *               recurrence with the stored alpha/beta.
- *   reorth = 1: full classical Gram-Schmidt, applied twice per step, against
- *               all stored Lanczos vectors (needs max_iter vectors of memory);
- *               psi from the stored vectors.
+ *   reorth = 1: full classical Gram-Schmidt against all stored Lanczos
+ *               vectors, repeated in the same step when the first pass kept
+ *               less than 1/sqrt(2) of the norm (needs max_iter vectors of
+ *               memory); psi from the stored vectors.
  *   refine = 1: with psi promoted to FP64, an FP64 product gives the Rayleigh
  *               quotient (info.e0_refined, returned as *e0) and the true
  *               residual ||H psi - E psi|| (info.true_residual).
