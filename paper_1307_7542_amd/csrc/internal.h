@@ -190,8 +190,12 @@ hub_status launch_lz_replay(int dtype, void *w, const void *vprev, const double 
 // psi (= 0 if first) += ycoef[0] * v, or ycoef[0] / div[0] * v when div is given
 hub_status launch_psi_acc(int dtype, double *psi, const void *v, const double *ycoef, int64_t n, int first,
                           hipStream_t st, const double *div = nullptr);
+// classical Gram-Schmidt pass against the k stored vectors (skipped when *skip);
+// npart (or NULL): gram_norm_parts(n) partials of the new ||w||^2, left
+// unchanged by a skipped pass
 hub_status launch_gram(int dtype, const void *const *dQ, int k, void *w, int64_t n, double *partial,
-                       double *coef, hipStream_t st, const int *skip);
+                       double *coef, hipStream_t st, const int *skip, double *npart = nullptr);
+int gram_norm_parts(int64_t n);
 hub_status launch_dgks_flag(const double *before, const double *after, int *flag, hipStream_t st);
 hub_status launch_psi_from_basis(int dtype, const void *const *dQ, int k, const double *ycoef, double *psi,
                                  int64_t n, hipStream_t st);

@@ -244,8 +244,10 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         Q.push_back(*p);
         return HUB_OK;
     };
+    double *wpart = nullptr;  // reorth: partials of ||w||^2 left by the Gram update
     if (reorth) {
         HUB_TRY(new_q(&Va));
+        HUB_TRY(mem.alloc((void **)&wpart, sizeof(double) * (size_t)gram_norm_parts(n)));
     } else {
         HUB_TRY(mem.alloc(&Va, es * (size_t)n));
         HUB_TRY(mem.alloc(&Vb, es * (size_t)n));
@@ -461,12 +463,21 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             // runs only when the first removed more than 1 - 1/sqrt(2) of the norm
             HUB_TRY(lz_b(v, d_alpha + k, d_misc + 8));
             HUB_HIP(hipMemcpyAsync(dQ, Q.data(), sizeof(void *) * Q.size(), hipMemcpyHostToDevice, st));
-            HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, nullptr));
-            HUB_TRY(launch_dot(dt, W, W, n, partial, d_misc + 9, 1, st));
+            // the norms come from the update's partials: after the first pass, and
+            // (second pass run or skipped) after the second
+            const int nq = gram_norm_parts(n);
+            HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, nullptr,
+                                wpart));
+            HUB_TRY(launch_sum(wpart, nq, d_misc + 9, st, 1));
             HUB_TRY(launch_dgks_flag(d_misc + 8, d_misc + 9, d_flag, st));
-            HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, d_flag));
-            if (reproject) HUB_TRY(k0_project(s, dt, W, st));
-            HUB_TRY(launch_dot(dt, W, W, n, partial, d_beta + k + 1, 1, st));
+            HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, d_flag,
+                                wpart));
+            if (reproject) {
+                HUB_TRY(k0_project(s, dt, W, st));
+                HUB_TRY(launch_dot(dt, W, W, n, partial, d_beta + k + 1, 1, st));
+            } else {
+                HUB_TRY(launch_sum(wpart, nq, d_beta + k + 1, st, 1));
+            }
         } else {
             // beta_{k+1} is formed from the partials by the normalisation below
             // (or here, on the last step); with reprojection, from the projected W

@@ -389,12 +389,17 @@ __global__ __launch_bounds__(RB) void k_gram_final(const double *__restrict__ pa
 }
 
 // w <- w - sum_j c_j q_j, evaluated in FP64 per element; lanes take four
-// consecutive elements (the n % 4 tail element by element).
+// consecutive elements (the n % 4 tail element by element).  npart (or NULL):
+// one partial of the new ||w||^2 per block (RB threads), so the norm needs no
+// separate pass over w; a skipped launch leaves npart as it was.
 template <typename T>
-__global__ void k_gram_update(const T *const *__restrict__ Q, int k, const double *__restrict__ coef,
-                              T *__restrict__ w, int64_t n, const int *__restrict__ skip)
+__global__ __launch_bounds__(RB) void k_gram_update(const T *const *__restrict__ Q, int k,
+                                                    const double *__restrict__ coef, T *__restrict__ w, int64_t n,
+                                                    const int *__restrict__ skip, double *__restrict__ npart)
 {
     if (skip && *skip) return;
+    __shared__ double s[RB];
+    double nacc = 0.0;
     const int64_t n4 = n >> 2;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
@@ -408,14 +413,22 @@ __global__ void k_gram_update(const T *const *__restrict__ Q, int k, const doubl
         const E4<T> wv = ld_e4(w + 4 * i);
         T o[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) o[r] = (T)((double)wv.v[r] - acc[r]);
+        for (int r = 0; r < 4; ++r) {
+            o[r] = (T)((double)wv.v[r] - acc[r]);
+            nacc += (double)o[r] * (double)o[r];
+        }
         st_e4(w + 4 * i, o);
     }
     for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double acc = 0.0;
         for (int j = 0; j < k; ++j) acc += coef[j] * (double)Q[j][i];
-        w[i] = (T)((double)w[i] - acc);
+        const T o = (T)((double)w[i] - acc);
+        w[i] = o;
+        nacc += (double)o * (double)o;
     }
+    if (!npart) return;
+    const double r = block_sum(nacc, s);
+    if (threadIdx.x == 0) npart[blockIdx.x] = r;
 }
 
 // flag = 1 when the first pass kept more than 1/sqrt(2) of the norm (a second
@@ -508,6 +521,11 @@ inline unsigned ew_grid(int64_t n)
 }
 
 }  // namespace
+
+int gram_norm_parts(int64_t n)
+{
+    return (int)ew_grid(n);
+}
 
 int red_grid(int64_t n)
 {
@@ -687,9 +705,15 @@ hub_status launch_psi_acc(int dtype, double *psi, const void *v, const double *y
 
 // coef must hold k doubles; partial must hold red_grid(n) * kmax doubles with kmax >= k.
 hub_status launch_gram(int dtype, const void *const *dQ, int k, void *w, int64_t n, double *partial, double *coef,
-                       hipStream_t st, const int *skip)
+                       hipStream_t st, const int *skip, double *npart)
 {
-    if (k <= 0) return HUB_OK;
+    if (k <= 0) {
+        if (npart) {
+            set_error("gram: norm partials need at least one stored vector");
+            return HUB_ERR_INVALID_ARG;
+        }
+        return HUB_OK;
+    }
     const int G = red_grid(n);
     if (dtype == HUB_F64) {
         hipLaunchKernelGGL(k_gram_dot<double>, dim3(G), dim3(RB), 0, st, (const double *const *)dQ, k,
@@ -700,11 +724,11 @@ hub_status launch_gram(int dtype, const void *const *dQ, int k, void *w, int64_t
     }
     hipLaunchKernelGGL(k_gram_final, dim3(k), dim3(RB), 0, st, partial, G, k, k, coef, skip);
     if (dtype == HUB_F64)
-        hipLaunchKernelGGL(k_gram_update<double>, dim3(ew_grid(n)), dim3(256), 0, st, (const double *const *)dQ, k,
-                           coef, (double *)w, n, skip);
+        hipLaunchKernelGGL(k_gram_update<double>, dim3(ew_grid(n)), dim3(RB), 0, st, (const double *const *)dQ, k,
+                           coef, (double *)w, n, skip, npart);
     else
-        hipLaunchKernelGGL(k_gram_update<float>, dim3(ew_grid(n)), dim3(256), 0, st, (const float *const *)dQ, k,
-                           coef, (float *)w, n, skip);
+        hipLaunchKernelGGL(k_gram_update<float>, dim3(ew_grid(n)), dim3(RB), 0, st, (const float *const *)dQ, k,
+                           coef, (float *)w, n, skip, npart);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
