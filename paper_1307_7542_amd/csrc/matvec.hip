@@ -61,6 +61,7 @@ struct MvArgs {
     T U;
     int32_t uniform;
     uint32_t umask;
+    int32_t stream;  // vectors beyond the MALL: data read or written once bypasses retention (k_kron_quad)
 };
 
 template <typename T>
@@ -222,6 +223,45 @@ __device__ __forceinline__ Q4<T> ld_q4(const T *p)
     return r;
 }
 
+// streaming (non-temporal) variants for data read or written once
+template <typename T>
+__device__ __forceinline__ Q4<T> ld_q4_nt(const T *p)
+{
+    Q4<T> r;
+    if constexpr (sizeof(T) == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 q = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p));
+        r.v[0] = q.x;
+        r.v[1] = q.y;
+        r.v[2] = q.z;
+        r.v[3] = q.w;
+    } else {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 q0 = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p));
+        const d2 q1 = __builtin_nontemporal_load(reinterpret_cast<const d2 *>(p) + 1);
+        r.v[0] = q0.x;
+        r.v[1] = q0.y;
+        r.v[2] = q1.x;
+        r.v[3] = q1.y;
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void st_q4_nt(T *p, const T (&v)[4])
+{
+    if constexpr (sizeof(T) == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 q = {v[0], v[1], v[2], v[3]};
+        __builtin_nontemporal_store(q, reinterpret_cast<f4 *>(p));
+    } else {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 q0 = {v[0], v[1]}, q1 = {v[2], v[3]};
+        __builtin_nontemporal_store(q0, reinterpret_cast<d2 *>(p));
+        __builtin_nontemporal_store(q1, reinterpret_cast<d2 *>(p) + 1);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void st_q4(T *p, const T (&v)[4])
 {
@@ -332,7 +372,8 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
         if (EPI && live && E.vprev) {
 #pragma unroll
             for (int t = 0; t < TB; ++t)
-                vpq[t] = ld_q4(E.vprev + (int64_t)min(b0 + t, cd - 1) * cu64 + a0);
+                vpq[t] = A.stream ? ld_q4_nt(E.vprev + (int64_t)min(b0 + t, cd - 1) * cu64 + a0)
+                                  : ld_q4(E.vprev + (int64_t)min(b0 + t, cd - 1) * cu64 + a0);
         }
         const uint4 ub = *reinterpret_cast<const uint4 *>(A.up_basis + a0);
         const uint32_t uu[4] = {ub.x, ub.y, ub.z, ub.w};
@@ -418,7 +459,10 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
                 part = quad_wave_sum(part);
                 if (lane == 0) gpart[t * E.G + (q >> 6)] = part;
             }
-            if (live) st_q4(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
+            if (live) {
+                if (A.stream) st_q4_nt(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
+                else st_q4(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
+            }
         }
     }
     if (EPI) {
@@ -986,6 +1030,10 @@ MvArgs<T> make_args(const hub_sector *s, const void *x, void *y)
     A.dn_basis = D.basis;
     A.uniform = s->uniformU;
     A.umask = s->umask;
+    // non-temporal v_prev loads and output stores pay only where a vector is
+    // larger than half the 256 MB MALL (4x4 torus FP32 fused product -3 %,
+    // ring M=14 (47 MB) +2.6 %)
+    A.stream = (double)U.count * (double)D.count * sizeof(T) > 128.0 * 1024 * 1024;
     if constexpr (sizeof(T) == 8) {
         A.up_val = (const T *)U.val64;
         A.dn_val = (const T *)D.val64;
