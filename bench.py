@@ -107,6 +107,8 @@ def square_mixed_gradients(hub, torch, model):
     e_ref = sec.ground_state(dtype=hub.F64, want_vector=False, tol=1e-10, max_iter=2000).e0
     g64 = sec.ground_state(dtype=hub.F64, want_vector=False, tol=1e-8, max_iter=2000, e0_target=e_ref,
                            e0_target_rel=1e-6)
+    # the FP32 fused product's shape is tuned on its first use: keep that out of the timed solve
+    sec.ground_state(dtype=hub.F32, want_vector=False, max_iter=2, allow_not_converged=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g = sec.ground_state(dtype=hub.F32, reorth=False, refine=True, tol=1e-7, max_iter=600, e0_target=e_ref,
