@@ -14,6 +14,7 @@
 // buffers according to a device-resident step counter, so one step can be
 // captured once as a HIP graph and replayed.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <new>
 #include <cfloat>
@@ -521,7 +522,7 @@ hub_status launch_bk(hub_batch *b, int di, const T *x, T *y, T *const *ptrs, con
                      hipStream_t st, const double *beta, int kmax, double *ipart)
 {
     const size_t lds = (size_t)(256 + (size_t)b->max_cu * TB) * sizeof(T);
-    static bool attr = false;
+    static std::atomic<bool> attr{false};
     if (!attr) {
         HUB_HIP(hipFuncSetAttribute((const void *)k_batch_kron<T, TB, BS, SEL>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_max));

@@ -30,6 +30,7 @@
 // entry is {column : 24, code : 8} with the value looked up in a 256-entry
 // table in LDS.
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstdlib>
 #include <map>
@@ -1073,7 +1074,7 @@ hub_status launch_fused(const hub_sector *s, const MvArgs<T> &A, hipStream_t st,
     const unsigned grid = 8u * (unsigned)((ntiles + 7) / 8);
     if (cf && U.ell_c32) {
         const size_t lds = (size_t)(A.cu * TB + 256) * sizeof(T);
-        static bool attr = false;
+        static std::atomic<bool> attr{false};
         if (!attr) {
             HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, true>, s->lds_max));
             attr = true;
@@ -1087,7 +1088,7 @@ hub_status launch_fused(const hub_sector *s, const MvArgs<T> &A, hipStream_t st,
         return HUB_OK;
     }
     const size_t lds = (size_t)A.cu * TB * sizeof(T);
-    static bool attr = false;
+    static std::atomic<bool> attr{false};
     if (!attr) {
         HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, false>, s->lds_max));
         attr = true;
@@ -1130,7 +1131,7 @@ hub_status launch_two_pass(const hub_sector *s, const MvArgs<T> &A, hipStream_t 
         hipLaunchKernelGGL((k_kron_dn_tiles<T, BSD, false>), dim3(8 * per_xcd), dim3(BSD), 0, st, A, A.y, ntiles_d,
                            per_xcd);
     const size_t lds = (size_t)A.cu * TB * sizeof(T);
-    static bool attr = false;
+    static std::atomic<bool> attr{false};
     if (!attr) {
         HUB_TRY(allow_lds(k_kron_up_panels<T, TB, BS>, s->lds_max));
         attr = true;
@@ -1155,7 +1156,7 @@ hub_status launch_quad_e(const hub_sector *s, const MvArgs<T> &A, hipStream_t st
         set_error("fused product: tile does not fit in LDS");
         return HUB_ERR_UNSUPPORTED;
     }
-    static bool attr = false;
+    static std::atomic<bool> attr{false};
     if (!attr) {
         HUB_TRY(allow_lds(k_kron_quad<T, TB, BS, XC, EPI>, s->lds_max));
         attr = true;
@@ -1293,21 +1294,28 @@ hub_status quad_shape(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, Q
         out.xc = env_int("HUB_MATVEC_XC", 1) != 0 ? 1 : 0;
         return HUB_OK;
     }
+    // the sector's cached shape and the shared table are read and written under
+    // one mutex (a sector may serve products on several threads); tuning runs
+    // outside it, and two threads that tune at once both store a valid shape
     QuadShape &q = epi ? s->quad_lz[di] : s->quad[di];
-    if (q.tb == 0) {
-        const ShapeKey key{s->device, di, (int64_t)A.cu, (int64_t)A.cd, s->spin[0].nnz, s->spin[1].nnz, epi ? 1 : 0};
-        {
-            std::lock_guard<std::mutex> lk(g_shape_mu);
+    const ShapeKey key{s->device, di, (int64_t)A.cu, (int64_t)A.cd, s->spin[0].nnz, s->spin[1].nnz, epi ? 1 : 0};
+    {
+        std::lock_guard<std::mutex> lk(g_shape_mu);
+        if (q.tb == 0) {
             auto it = g_shapes.find(key);
             if (it != g_shapes.end()) q = it->second;
         }
-        if (q.tb == 0) {
-            HUB_TRY(tune_quad<T>(s, A, st, q, epi, apart));
-            std::lock_guard<std::mutex> lk(g_shape_mu);
-            g_shapes[key] = q;
+        if (q.tb != 0) {
+            out = q;
+            return HUB_OK;
         }
     }
-    out = q;
+    QuadShape t;
+    HUB_TRY(tune_quad<T>(s, A, st, t, epi, apart));
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shapes[key] = t;
+    q = t;
+    out = t;
     return HUB_OK;
 }
 
@@ -1358,7 +1366,7 @@ hub_status launch_chunked_parts_t(const hub_sector *s, const MvArgs<T> &A, hipSt
     const int nq = (int)(A.cu >> 2);
     const int P = (nq + BSC * QPL - 1) / (BSC * QPL);
     const int ntiles = (A.cd + TB - 1) / TB;
-    static bool attr = false;
+    static std::atomic<bool> attr{false};
     if (!attr) {
         HUB_TRY(allow_lds(k_kron_chunked_parts<T, BSC, QPL, TB>, s->lds_max));
         attr = true;
@@ -1422,7 +1430,7 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
     if (impl != 1 && (!fits || s->force_chunked) && U.ch_ell[di]) {
         constexpr int BSC = 1024;
         const size_t lds = (size_t)(U.chunk_rows[di] + 256) * sizeof(T);
-        static bool attr = false;
+        static std::atomic<bool> attr{false};
         if (!attr) {
             HUB_TRY(allow_lds(k_kron_chunked<T, BSC, 4>, s->lds_max));
             attr = true;
@@ -1439,7 +1447,7 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
             // neighbour columns are more often still in the MALL: 2x9 ladder FP32 39.3 -> 37.6 ms)
             // or XCD-contiguous ranges (HUB_CHUNK_XC=1)
             const bool xc = env_int("HUB_CHUNK_XC", 0) != 0;
-            static bool attrq = false;
+            static std::atomic<bool> attrq{false};
             if (!attrq) {
                 HUB_TRY(allow_lds(k_kron_chunked_quad<T, BSC, true>, s->lds_max));
                 HUB_TRY(allow_lds(k_kron_chunked_quad<T, BSC, false>, s->lds_max));

@@ -28,6 +28,7 @@
 // workgroup per down cycle stages that cycle's columns in LDS and reuses every
 // hop entry for all members of the cycle.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -394,7 +395,7 @@ hub_status k0_product_t(const hub_sector *s, const void *x, void *y, hipStream_t
     // the kernel also holds up to 2.2 KB of static LDS (cycle tables)
     const size_t dyn_max = s->lds_max - 4096;
     if (lds <= dyn_max) {
-        static bool attr = false;
+        static std::atomic<bool> attr{false};
         if (!attr) {
             HUB_HIP(hipFuncSetAttribute((const void *)k_k0_product<T, BS, true>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_max));

@@ -634,6 +634,49 @@ def test_fused_solve_same_for_every_tile_shape(hub, monkeypatch):
     s.close()
 
 
+@pytest.mark.gpu
+def test_concurrent_products_on_one_sector(hub):
+    """A sector serves products from several host threads on their own streams:
+    four threads start on a lattice whose tile shape is not tuned yet (so they
+    tune at the same time) and every product is bit-identical to a
+    single-thread one, in both precisions."""
+    import threading
+    import torch
+    m = W.ring(10, U=2.5, n_up=5, n_dn=3).with_params(eps=[0.03 * i for i in range(10)])
+    s = hub.Sector(m)
+    assert s.count_up % 4 == 0
+    xs = {dt: s.start_vector(seed=11, dtype=dt) for dt in (hub.F64, hub.F32)}
+    out, errors = {}, []
+
+    def work(tid):
+        try:
+            st = torch.cuda.Stream()
+            res = []
+            with torch.cuda.stream(st):
+                for rep in range(3):
+                    for dt in (hub.F32, hub.F64):
+                        y = s.empty(dt)
+                        s.matvec(xs[dt], y, stream=st)
+                        res.append((dt, y))
+            st.synchronize()
+            out[tid] = [(dt, y.cpu()) for dt, y in res]
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    assert len(out) == 4
+    ref = {dt: s.matvec(xs[dt]).cpu() for dt in (hub.F64, hub.F32)}
+    for tid, res in out.items():
+        for dt, y in res:
+            assert torch.equal(y, ref[dt]), (tid, dt)
+    s.close()
+
+
 def _variant_model(which):
     if which == "ring10_eps":
         return W.ring(10, U=3.0, n_up=5, n_dn=4).with_params(eps=[0.1 * i for i in range(10)])
