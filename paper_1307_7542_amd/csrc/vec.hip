@@ -176,7 +176,7 @@ __global__ void k_psi_acc(double *__restrict__ psi, const T *__restrict__ v, con
 // shuffles (fixed butterfly order), then one barrier combines the wavefronts.
 // partial layout: [block][j].  A non-null `skip` pointing at a non-zero flag
 // turns the launch into a no-op (second Gram-Schmidt pass not needed).
-constexpr int GJ = 8;
+constexpr int GJ = 16;
 
 __device__ __forceinline__ double wave_sum(double v)
 {
