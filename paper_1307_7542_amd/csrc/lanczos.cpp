@@ -19,6 +19,11 @@
 namespace hub {
 namespace {
 
+// Up to this many per-column partials of alpha, every block of the update
+// kernel sums them itself (the 4x4 torus: 11440, a few microseconds per
+// launch) instead of a separate single-block launch.
+constexpr int64_t kSumInUpdate = 65536;
+
 // Number of eigenvalues of T (diag a, off-diagonal b) smaller than x.
 int sturm_count(const double *a, const double *b, int m, double x, double pivmin)
 {
@@ -280,10 +285,6 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     double *apart = nullptr;
     if (fused) HUB_TRY(mem.alloc((void **)&apart, sizeof(double) * (size_t)matvec_lz_partials(s)));
     if (fused) inf.matvec_bytes += (int64_t)es * n;  // the update's read of v_prev
-    // Up to this many per-column partials, every block of the update kernel sums
-    // them itself (the 4x4 torus: 11440, a few microseconds per launch) instead
-    // of a separate single-block launch.
-    constexpr int64_t kSumInUpdate = 65536;
     // fused: alpha's per-column partials are left in apart[0 .. np_alpha) and
     // summed by the w -= alpha v update (lz_b below); otherwise alpha goes to aout
     int64_t np_alpha = 0;
@@ -647,11 +648,23 @@ hub_status lanczos_coefficients(const hub_sector *s, const double *f, int max_st
     std::vector<double> ha(kmax), hb(kmax + 1);
     int m = kmax;
     double tmax = 0.0;
+    // the product with the first update in its epilogue where available (its
+    // per-column partials of alpha summed inside the next kernel), else the
+    // product and a separate first update
+    const bool fused = matvec_lz_available(s, HUB_F64) && matvec_lz_partials(s) <= kSumInUpdate;
+    double *apart = nullptr;
+    if (fused) HUB_TRY(mem.alloc((void **)&apart, sizeof(double) * (size_t)matvec_lz_partials(s)));
     for (int k = 0; k < kmax; ++k) {
-        HUB_TRY(apply_h(s, HUB_F64, v, W, st));
-        // alpha's partials beside beta's; both summed inside the kernels that use them
-        HUB_TRY(launch_lz_a(HUB_F64, W, v_prev, d_beta + k, v, n, partial + kRedGrid, nullptr, st));
-        HUB_TRY(launch_lz_b_sum(HUB_F64, W, v, partial + kRedGrid, red_grid(n), d_alpha + k, n, partial, st));
+        if (fused) {
+            int64_t np = 0;
+            HUB_TRY(launch_matvec_lz(s, HUB_F64, v, W, v_prev, d_beta + k, apart, &np, st));
+            HUB_TRY(launch_lz_b_sum(HUB_F64, W, v, apart, np, d_alpha + k, n, partial, st));
+        } else {
+            HUB_TRY(apply_h(s, HUB_F64, v, W, st));
+            // alpha's partials beside beta's; both summed inside the kernels that use them
+            HUB_TRY(launch_lz_a(HUB_F64, W, v_prev, d_beta + k, v, n, partial + kRedGrid, nullptr, st));
+            HUB_TRY(launch_lz_b_sum(HUB_F64, W, v, partial + kRedGrid, red_grid(n), d_alpha + k, n, partial, st));
+        }
         const bool last = (k + 1 == kmax);
         const bool check_now = (k + 1) % 16 == 0 || last;
         if (check_now) HUB_TRY(launch_sum(partial, red_grid(n), d_beta + k + 1, st, 1));
