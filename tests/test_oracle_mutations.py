@@ -1,0 +1,66 @@
+"""The pins catch planted mistakes.  Each case copies oracle/oracle.c, plants
+one plausible error by a textual substitution (a dropped or wrong term, a
+wrong sign, an off-by-one), builds the copy with gcc into a temporary folder,
+points the oracle at it, and checks that the Jordan-Wigner entry pin (every
+entry of H against an independent Fock-space construction, all sectors)
+rejects it.  The oracle's own source and library are not touched."""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from test_oracle_pins import _jordan_wigner_H
+
+MUTATIONS = [
+    ("sign counts an endpoint", "for (int k = p + 1; k < q; ++k)", "for (int k = p; k < q; ++k)"),
+    ("fermionic sign dropped", "*sign = (between & 1) ? -1.0 : 1.0;", "*sign = 1.0;"),
+    ("U on n_up + n_dn", "d += m->U[i] * (double)(nu * nd);", "d += m->U[i] * (double)(nu + nd);"),
+    ("eps of the down spin dropped", "if (m->eps) d += m->eps[i] * (double)(nu + nd);",
+     "if (m->eps) d += m->eps[i] * (double)(nu);"),
+    ("hopping sign flipped", "e[n].val = -m->t[b] * sg;", "e[n].val = m->t[b] * sg;"),
+    ("spins mixed in a hop", "int q = m->bj[b] + s * m->M;", "int q = m->bj[b] + (1 - s) * m->M;"),
+]
+
+
+def _pin_holds(model):
+    """The entry pin of test_jordan_wigner_entries on one lattice, all sectors."""
+    Hf = _jordan_wigner_H(model).tocsr()
+    M = model.n_sites
+    for n_up in range(M + 1):
+        for n_dn in range(M + 1):
+            sec = oracle.Sector(model.with_params(n_up=n_up, n_dn=n_dn))
+            keys = sec.keys.astype(np.int64)
+            if not np.allclose(sec.dense(), Hf[keys][:, keys].toarray(), rtol=0, atol=1e-14):
+                return False
+    return True
+
+
+def _model():
+    base = W.random_graph(4, 5, seed=2, site_U=True)
+    return base.with_params(eps=[0.3, -0.7, 0.11, 0.5])
+
+
+def test_unmutated_oracle_passes_the_pin():
+    assert _pin_holds(_model())
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_rejects_planted_mistake(tmp_path, monkeypatch, name, old, new):
+    src = open(oracle._SRC).read()
+    assert src.count(old) == 1, name
+    mut = tmp_path / "oracle_mutant.c"
+    mut.write_text(src.replace(old, new))
+    so = tmp_path / "liboracle_mutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", str(so), str(mut),
+                           "-lm"])
+    monkeypatch.setattr(oracle, "_SRC", str(mut))
+    monkeypatch.setattr(oracle, "_LIB", str(so))
+    monkeypatch.setattr(oracle, "_lib", None)
+    try:
+        held = _pin_holds(_model())
+    except Exception:  # a mutant may also fail loudly (e.g. a target state outside the sector)
+        held = False
+    assert not held, f"the pin did not catch: {name}"
