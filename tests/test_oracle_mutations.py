@@ -1,9 +1,11 @@
 """The pins catch planted mistakes.  Each case copies oracle/oracle.c, plants
 one plausible error by a textual substitution (a dropped or wrong term, a
 wrong sign, an off-by-one), builds the copy with gcc into a temporary folder,
-points the oracle at it, and checks that the Jordan-Wigner entry pin (every
-entry of H against an independent Fock-space construction, all sectors)
-rejects it.  The oracle's own source and library are not touched."""
+points the oracle at it, and checks that a pin rejects it: the Jordan-Wigner
+entry pin (every entry of H against an independent Fock-space construction,
+all sectors) for mistakes in H, the finite-difference pin for mistakes in the
+parameter bilinear forms.  The oracle's own source and library are not
+touched."""
 import os
 import subprocess
 
@@ -12,7 +14,7 @@ import pytest
 
 import oracle
 import workloads as W
-from test_oracle_pins import _jordan_wigner_H
+from test_oracle_pins import _jordan_wigner_H, test_hellmann_feynman_vs_finite_differences
 
 MUTATIONS = [
     ("sign counts an endpoint", "for (int k = p + 1; k < q; ++k)", "for (int k = p; k < q; ++k)"),
@@ -22,6 +24,14 @@ MUTATIONS = [
      "if (m->eps) d += m->eps[i] * (double)(nu);"),
     ("hopping sign flipped", "e[n].val = -m->t[b] * sg;", "e[n].val = m->t[b] * sg;"),
     ("spins mixed in a hop", "int q = m->bj[b] + s * m->M;", "int q = m->bj[b] + (1 - s) * m->M;"),
+]
+
+# mistakes in the parameter bilinear forms only (H itself intact): caught by
+# the finite-difference pin of the Hellmann-Feynman derivatives
+BILINEAR_MUTATIONS = [
+    ("dU on n_up + n_dn", "a[nb + i] += (double)(nu * nd) * gx;", "a[nb + i] += (double)(nu + nd) * gx;"),
+    ("bond form sign flipped", "a[b] += -sg * g[r] * x[c];", "a[b] += sg * g[r] * x[c];"),
+    ("deps without the down spin", "a[nb + M + i] += (double)(nu + nd) * gx;", "a[nb + M + i] += (double)(nu) * gx;"),
 ]
 
 
@@ -47,10 +57,10 @@ def test_unmutated_oracle_passes_the_pin():
     assert _pin_holds(_model())
 
 
-@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_pin_rejects_planted_mistake(tmp_path, monkeypatch, name, old, new):
+def _use_mutant(tmp_path, monkeypatch, old, new):
+    """Build oracle.c with `old` replaced by `new` and make the oracle load it."""
     src = open(oracle._SRC).read()
-    assert src.count(old) == 1, name
+    assert src.count(old) == 1, old
     mut = tmp_path / "oracle_mutant.c"
     mut.write_text(src.replace(old, new))
     so = tmp_path / "liboracle_mutant.so"
@@ -59,8 +69,20 @@ def test_pin_rejects_planted_mistake(tmp_path, monkeypatch, name, old, new):
     monkeypatch.setattr(oracle, "_SRC", str(mut))
     monkeypatch.setattr(oracle, "_LIB", str(so))
     monkeypatch.setattr(oracle, "_lib", None)
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_rejects_planted_mistake(tmp_path, monkeypatch, name, old, new):
+    _use_mutant(tmp_path, monkeypatch, old, new)
     try:
         held = _pin_holds(_model())
     except Exception:  # a mutant may also fail loudly (e.g. a target state outside the sector)
         held = False
     assert not held, f"the pin did not catch: {name}"
+
+
+@pytest.mark.parametrize("name,old,new", BILINEAR_MUTATIONS, ids=[m[0] for m in BILINEAR_MUTATIONS])
+def test_finite_difference_pin_rejects_planted_mistake(tmp_path, monkeypatch, name, old, new):
+    _use_mutant(tmp_path, monkeypatch, old, new)
+    with pytest.raises(AssertionError):
+        test_hellmann_feynman_vs_finite_differences()
