@@ -31,7 +31,8 @@ MUTATIONS = [
 BILINEAR_MUTATIONS = [
     ("dU on n_up + n_dn", "a[nb + i] += (double)(nu * nd) * gx;", "a[nb + i] += (double)(nu + nd) * gx;"),
     ("bond form sign flipped", "a[b] += -sg * g[r] * x[c];", "a[b] += sg * g[r] * x[c];"),
-    ("deps without the down spin", "a[nb + M + i] += (double)(nu + nd) * gx;", "a[nb + M + i] += (double)(nu) * gx;"),
+    ("deps without the down spin", "a[nb + M + i] += (double)(nu + nd) * gx;",
+     "a[nb + M + i] += (double)(nu) * gx;"),
 ]
 
 
@@ -86,3 +87,29 @@ def test_finite_difference_pin_rejects_planted_mistake(tmp_path, monkeypatch, na
     _use_mutant(tmp_path, monkeypatch, old, new)
     with pytest.raises(AssertionError):
         test_hellmann_feynman_vs_finite_differences()
+
+
+# mistakes in the Green's-function oracle's fermion operator (Python): caught by
+# its pin against the Jordan-Wigner Fock-space operators
+OPERATOR_MUTATIONS = [
+    ("sign counts the mode itself", "keys[cols] & (bit - np.uint64(1))",
+     "keys[cols] & ((bit << np.uint64(1)) - np.uint64(1))"),
+    ("sign counts the modes above", "keys[cols] & (bit - np.uint64(1))",
+     "keys[cols] & ~((bit << np.uint64(1)) - np.uint64(1))"),
+    ("create and annihilate swapped", "take = ~occupied if create else occupied", "take = occupied if create else ~occupied"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", OPERATOR_MUTATIONS, ids=[m[0] for m in OPERATOR_MUTATIONS])
+def test_operator_pin_rejects_planted_mistake(monkeypatch, name, old, new):
+    import inspect
+    import textwrap
+    import oracle.greens as og
+    from test_oracle_greens import test_fermion_operator_matches_jordan_wigner
+    src = textwrap.dedent(inspect.getsource(og.fermion_operator))
+    assert src.count(old) == 1, name
+    ns = dict(vars(og))
+    exec(compile(src.replace(old, new), og.__file__, "exec"), ns)
+    monkeypatch.setattr(og, "fermion_operator", ns["fermion_operator"])
+    with pytest.raises(AssertionError):
+        test_fermion_operator_matches_jordan_wigner(12, 4)
