@@ -96,7 +96,8 @@ OPERATOR_MUTATIONS = [
      "keys[cols] & ((bit << np.uint64(1)) - np.uint64(1))"),
     ("sign counts the modes above", "keys[cols] & (bit - np.uint64(1))",
      "keys[cols] & ~((bit << np.uint64(1)) - np.uint64(1))"),
-    ("create and annihilate swapped", "take = ~occupied if create else occupied", "take = occupied if create else ~occupied"),
+    ("create and annihilate swapped", "take = ~occupied if create else occupied",
+     "take = occupied if create else ~occupied"),
 ]
 
 
