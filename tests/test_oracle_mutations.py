@@ -114,3 +114,48 @@ def test_operator_pin_rejects_planted_mistake(monkeypatch, name, old, new):
     monkeypatch.setattr(og, "fermion_operator", ns["fermion_operator"])
     with pytest.raises(AssertionError):
         test_fermion_operator_matches_jordan_wigner(12, 4)
+
+
+def _mutate_function(module, fname, old, new, monkeypatch):
+    """Replace module.fname by a copy of its source with `old` replaced by `new`."""
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(getattr(module, fname)))
+    assert src.count(old) == 1, (fname, old)
+    ns = dict(vars(module))
+    exec(compile(src.replace(old, new), module.__file__, "exec"), ns)
+    monkeypatch.setattr(module, fname, ns[fname])
+
+
+def _fails(*checks):
+    """True when any of the pin functions raises an AssertionError."""
+    for check in checks:
+        try:
+            check()
+        except AssertionError:
+            return True
+    return False
+
+
+# mistakes in the translation oracle's signs: caught by the Table VI fixture and
+# T^2 |0101> = -|0101> (one-spin cycles) or by [H, T] = 0 and the group-projector
+# construction (two-spin translation operator)
+def test_translation_pins_reject_planted_sign_mistakes(monkeypatch):
+    import oracle.translation as ot
+    import test_oracle_translation as tt
+    with monkeypatch.context() as mp:
+        _mutate_function(ot, "gsign", "(k * (N - k)) % 2", "(k * N) % 2", mp)
+        assert _fails(tt.test_table6_spin_table, tt.test_t_squared_on_0101)
+    projector = [lambda i=i: tt.test_k0_block_against_group_projector(i) for i in range(7)]
+    with monkeypatch.context() as mp:
+        _mutate_function(ot, "_key_rotate", "np.where((k * (N - k)) % 2 == 1, -1.0, 1.0)",
+                         "np.where(k % 2 == 1, -1.0, 1.0)", mp)
+        assert _fails(*projector)
+    with monkeypatch.context() as mp:
+        _mutate_function(ot, "_key_rotate", "sgn(up, n_up) * sgn(dn, n_dn)", "sgn(up, n_up)", mp)
+        assert _fails(*projector)
+    # and the unmutated oracle passes them all
+    tt.test_table6_spin_table()
+    tt.test_t_squared_on_0101()
+    for check in projector:
+        check()
