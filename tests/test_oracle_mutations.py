@@ -159,3 +159,23 @@ def test_translation_pins_reject_planted_sign_mistakes(monkeypatch):
     tt.test_t_squared_on_0101()
     for check in projector:
         check()
+
+
+def test_solver_and_generator_pins_reject_planted_mistakes(tmp_path, monkeypatch):
+    """The oracle's Lanczos without the beta term fails the LAPACK pin; a
+    continued fraction with b instead of b^2 fails the closed forms; a SplitMix64
+    with a wrong shift fails the reference outputs."""
+    import oracle.greens as og
+    import test_oracle_greens as tg
+    import test_oracle_pins as tp
+    with monkeypatch.context() as mp:
+        _mutate_function(oracle, "lanczos", "w = matvec(v) - beta * v_prev\n        a = float(",
+                         "w = matvec(v)\n        a = float(", mp)
+        assert _fails(lambda: tp.test_lanczos_matches_dense(21), lambda: tp.test_lanczos_matches_dense(22))
+    with monkeypatch.context() as mp:
+        _mutate_function(og, "continued_fraction", "betas[j] ** 2 / d", "betas[j] / d", mp)
+        assert _fails(tg.test_continued_fraction_closed_forms, tg.test_continued_fraction_matches_lehmann)
+    with monkeypatch.context() as mp:
+        _use_mutant(tmp_path, mp, "z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",
+                    "z = (z ^ (z >> 28)) * 0x94D049BB133111EBull;")
+        assert _fails(tp.test_splitmix64_reference_outputs)
