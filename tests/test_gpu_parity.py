@@ -677,6 +677,36 @@ def test_concurrent_products_on_one_sector(hub):
     s.close()
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("which", ["ring8_n44", "ring8_n54"])
+def test_first_steps_match_the_oracle_recurrence(hub, which):
+    """One and two steps from the seeded start vector: with max_iter = 1 the
+    Ritz value is alpha_0 = <v0, H v0> of the normalised start vector, with 2 the
+    lowest eigenvalue of the 2 x 2 tridiagonal matrix of the oracle's recurrence.
+    The 70-state up spin takes the one-row product; the 56-state one the fused,
+    unnormalised path, whose last step fetches beta instead of publishing it."""
+    import numpy as np
+    n_up = 4 if which == "ring8_n44" else 5
+    m = W.ring(8, U=3.0, n_up=n_up, n_dn=4).with_params(eps=[0.02 * i for i in range(8)])
+    s = hub.Sector(m)
+    assert (s.count_up % 4 == 0) == (which == "ring8_n54")
+    osec = oracle.Sector(m)
+    csr = osec.csr()
+    v0 = oracle.start_vector(7542, osec.dim)
+    r = oracle.lanczos(lambda x: oracle.spmv(csr, x), osec.dim, v0, max_iter=2, tol=0.0, reorth=False,
+                       want_vector=False)
+    a, b = r.alphas, r.betas
+    t2 = np.linalg.eigvalsh(np.array([[a[0], b[0]], [b[0], a[1]]]))[0]
+    for dt, tol in ((hub.F64, 1e-13), (hub.F32, 1e-6)):
+        g1 = s.ground_state(dtype=dt, max_iter=1, want_vector=False, allow_not_converged=True)
+        assert g1.info["iters"] == 1
+        assert abs(g1.e0 - a[0]) <= tol * abs(a[0]), (dt, g1.e0, a[0])
+        g2 = s.ground_state(dtype=dt, max_iter=2, want_vector=False, allow_not_converged=True)
+        assert g2.info["iters"] == 2
+        assert abs(g2.e0 - t2) <= tol * abs(t2), (dt, g2.e0, t2)
+    s.close()
+
+
 def _variant_model(which):
     if which == "ring10_eps":
         return W.ring(10, U=3.0, n_up=5, n_dn=4).with_params(eps=[0.1 * i for i in range(10)])
