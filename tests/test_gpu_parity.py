@@ -707,6 +707,47 @@ def test_first_steps_match_the_oracle_recurrence(hub, which):
     s.close()
 
 
+@pytest.mark.gpu
+def test_thirty_two_sites(hub):
+    """The widest lattice the 32-bit patterns allow: a 32-site ring with two up
+    and one down electron (496 x 32 states; the up count is a multiple of 4, so
+    the four-rows-per-lane product and the fused solver run).  The wrap bond's
+    sign spans all 30 sites between its ends, and per-site U and eps include
+    site 31.  Products and E0 against the oracle."""
+    import torch
+    M = 32
+    U = [2.0 + 0.25 * ((5 * i) % 7) for i in range(M)]
+    eps = [0.1 * ((3 * i) % 5) - 0.2 for i in range(M)]
+    m = W.ring(M, U=2.0, n_up=2, n_dn=1).with_params(U=U, eps=eps)
+    s = hub.Sector(m)
+    assert s.count_up == 496 and s.count_dn == 32 and s.count_up % 4 == 0
+    osec = oracle.Sector(m)
+    xr = oracle.start_vector(3, osec.dim)
+    bound = _row_abs(osec, xr)
+    yr = oracle.spmv(osec.csr(), xr)
+    for dt, tol in ((hub.F64, 1e-13), (hub.F32, 1e-5)):
+        x = torch.from_numpy(xr).cuda()
+        ref = yr
+        if dt == hub.F32:
+            x = x.float()
+            ref = oracle.spmv(osec.csr(), x.cpu().numpy().astype(np.float64))
+        y = s.matvec(x).cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(y - ref) <= tol * bound + 1e-30), dt
+    # E0 of the oracle's H by ARPACK (a gap ratio of 1.6e-4 makes the oracle's
+    # own reorthogonalised Lanczos take minutes here); the solves get the steps
+    # such a gap needs
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    rp, col, val = osec.csr()
+    e_ref = float(np.min(sla.eigsh(sp.csr_matrix((val, col, rp), shape=(osec.dim, osec.dim)), k=1,
+                                   which="SA", tol=1e-13)[0]))
+    g64 = s.ground_state(dtype=hub.F64, want_vector=False, max_iter=3000)
+    g32 = s.ground_state(dtype=hub.F32, refine=True, max_iter=3000)
+    assert abs(g64.e0 - e_ref) <= 1e-10 * abs(e_ref), (g64.e0, e_ref)
+    assert abs(g32.e0 - e_ref) <= 1e-9 * abs(e_ref), (g32.e0, e_ref)
+    s.close()
+
+
 def _variant_model(which):
     if which == "ring10_eps":
         return W.ring(10, U=3.0, n_up=5, n_dn=4).with_params(eps=[0.1 * i for i in range(10)])
