@@ -748,6 +748,31 @@ def test_thirty_two_sites(hub):
     s.close()
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("which", ["ring8_n44", "ring8_n53"])
+def test_algorithmic_bytes_formula(hub, which):
+    """The bytes every GB/s figure divides by: read x and write y once (2 dim s)
+    plus, per distinct spin table, row pointers 4 (c + 1), entries nnz (4 + s),
+    basis integers 4 c and site sums s c; one table when N_up = N_dn.  The
+    counts come from the oracle (C(M, N) and the entries of H_sigma projected
+    out of its full H)."""
+    from math import comb
+    n_up, n_dn = (4, 4) if which == "ring8_n44" else (5, 3)
+    m = W.ring(8, U=3.0, n_up=n_up, n_dn=n_dn)
+    s = hub.Sector(m)
+    osec = oracle.Sector(m)
+    spins = [0] if n_up == n_dn else [0, 1]
+    for dt, es in ((hub.F64, 8), (hub.F32, 4)):
+        want = 2 * osec.dim * es
+        for sp_ in spins:
+            c = comb(8, n_up if sp_ == 0 else n_dn)
+            rows = _project_sigma(osec, sp_)
+            nnz = sum(len(v) for v in rows)
+            want += 4 * (c + 1) + nnz * (4 + es) + 4 * c + es * c
+        assert s.matvec_bytes(dt) == want, (which, dt, s.matvec_bytes(dt), want)
+    s.close()
+
+
 def _variant_model(which):
     if which == "ring10_eps":
         return W.ring(10, U=3.0, n_up=5, n_dn=4).with_params(eps=[0.1 * i for i in range(10)])
