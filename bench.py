@@ -1,21 +1,21 @@
 #!/usr/bin/env python3
-"""Benchmark of the Kronecker-sum Hubbard ground-state path on one MI355X.
+"""Benchmark of the Kronecker-sum Hubbard product and ground-state solve on one MI355X.
 
-Workload (default): periodic chain M=14, t=1, N_up=N_dn=7 (dim 3432^2 =
-11,778,624), U in {2, 4, 8} -- the chain of the paper's Table IV.
-One step = the whole hot path for the three U values, model parameters on the
-host, everything else on the GPU:
-  1. sector set-up: bases, H_up = H_dn in CSR and sliced ELL, site energies;
-  2. plain FP64 Lanczos to E0 (Ritz residual <= 1e-12 |E0|);
-  3. mixed Lanczos: FP32 vectors and products, FP64 alpha/beta, full
-     reorthogonalisation with FP64 coefficients, FP64 tridiagonal solve,
-     eigenvector from the stored basis, FP64 refinement (Rayleigh quotient);
-  4. mixed Lanczos without reorthogonalisation (eigenvector by second pass,
-     FP64 refinement).
-Every product launch inside the timed steps is bracketed by HIP events on the
-stream it runs on (the caller's current stream).  Time-to-E0 is the wall time
-until the lowest Ritz value is within 1e-6 relative of the oracle's E0 (the
-solves then continue to their stopping tests).  Prints one JSON line.
+Headline workload: the 2x9 two-leg ladder (periodic legs, t_leg = 1, one rung
+amplitude per rung ~ U(0.5, 1.5), U = 6, N_up = N_dn = 9; dim 48620^2 =
+2,363,904,400), the largest single-GPU configuration.  One step = one FP64
+product Y = H_up V + V H_dn^T + D o V (Sec. IV A) on a resident vector, in the
+schedule the library tuned on its first product; the FP32 product is timed
+the same way beside it.  Every product is bracketed by HIP events on the stream
+it runs on (torch's current stream).  `value` = FP64 algorithmic bytes of the
+timed products / wall time of the timed steps.
+
+Also measured once, outside the step loop: time-to-E0 of the plain FP64
+Lanczos and of the mixed (FP32 vectors, FP64 scalars) Lanczos on the ladder
+(reference: the FP64 GPU energy), and, unless --no-extra, the ring M=14 solves
+of Table IV against the oracle's energies, the 4x4 torus products and
+gradients, the impurity-model batch, the Green's function and the k = 0 block.
+Prints one JSON line.
 """
 import argparse
 import json
@@ -31,22 +31,25 @@ HBM_PEAK_GBPS = 8000.0
 # record between kernels delays the next one by a few microseconds)
 TIME_EVERY = 8
 TABLE4_M14_U4 = -8.0883491038  # Sec. V, Table IV (printed digits)
+HEADLINE = "ladder2x9"
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle sample time")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target time of each oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 4x4-torus product timing")
+    ap.add_argument("--no-extra", action="store_true", help="skip the measurements beyond the ladder")
+    ap.add_argument("--no-solve", action="store_true", help="skip the ladder time-to-E0 solves")
     ap.add_argument("--copy-reference", type=int, default=0,
                     help="profiling aid: copy a buffer of this many MiB three times (counter calibration)")
     ap.add_argument("--lanczos-only", type=str, default="",
                     help="run one FP64 and one mixed solve of the named workload and exit (counter runs)")
     ap.add_argument("--matvec-only", type=str, default="",
-                    help="profiling aid: 'workload:count' times count back-to-back products per dtype")
+                    help="profiling aid: 'workload:count[:dtype]' runs count back-to-back products "
+                         "(dtype f32 or f64; both by default) in the tuned schedule")
     return ap.parse_args()
 
 
@@ -71,26 +74,6 @@ def product_timing(hub, torch, model, reps=10):
         out[name] = {"avg_ms": ms, "bytes_per_launch": b, "GBps": b / ms / 1e6, "frac": b / ms / 1e6 / HBM_PEAK_GBPS}
         del x, y
     out["dim"] = sec.dim
-    sec.close()
-    return out
-
-
-def ladder_mixed(hub, torch, model):
-    """The 2x9 ladder (N = 9/9, dim 2.36e9): FP32 vectors and products with FP64
-    scalars, plain recurrence, then the FP64 refinement of the eigenpair; the
-    FP32 Ritz value against the FP64 Rayleigh quotient."""
-    sec = hub.Sector(model)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g = sec.ground_state(dtype=hub.F32, reorth=False, refine=True, tol=1e-7, max_iter=400)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    i = g.info
-    out = {"dim": sec.dim, "iters": i["iters"], "solve_s": dt, "e0_ritz_fp32": i["e0_ritz"],
-           "e0_refined_fp64": i["e0_refined"],
-           "rel_err_ritz_vs_refined": abs(i["e0_ritz"] - i["e0_refined"]) / abs(i["e0_refined"]),
-           "true_residual_fp64": i["true_residual"]}
-    del g
     sec.close()
     return out
 
@@ -220,6 +203,135 @@ def k0_timing(hub, torch, model):
     return out
 
 
+
+
+def kernel_name(sched, es):
+    """Name of the product kernel a tuned schedule launches (the dominant one)."""
+    T = "double" if es == 8 else "float"
+    if sched["family"] == 1:
+        return (f"k_kron_quad<{T}, {sched['tile_cols']}, {sched['block']}, {bool(sched['order'])}, false, "
+                f"{'false' if sched['band_rows'] else 'true'}>")
+    if sched["family"] == 2:
+        dn = "false" if sched["band_rows"] else "true"
+        tm = "true" if (sched["band_rows"] and sched["order"]) else "false"
+        return f"k_kron_chunked_parts<{T}, 1024, {sched['quads_per_lane']}, {sched['tile_cols']}, {dn}, {tm}>"
+    return {3: "k_kron_fused", 4: "k_kron_csr"}.get(sched["family"], "?")
+
+
+def headline_products(hub, torch, model, steps, warmup):
+    """FP64 and FP32 products on the ladder: `warmup` untimed products after the
+    tuning one, then `steps` products, each between HIP events on the current
+    stream, the whole loop between synchronisations."""
+    sec = hub.Sector(model)
+    out = {"dim": sec.dim}
+    for dt, key in ((hub.F64, "f64"), (hub.F32, "f32")):
+        es = 8 if dt == hub.F64 else 4
+        x = sec.start_vector(seed=1, dtype=dt)
+        y = sec.empty(dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sec.matvec(x, y)  # first product of the dtype: tunes the schedule
+        torch.cuda.synchronize()
+        tune_s = time.perf_counter() - t0
+        for _ in range(warmup):
+            sec.matvec(x, y)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record()
+            sec.matvec(x, y)
+            e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+        b = sec.matvec_bytes(dt)
+        avg = sum(ms) / len(ms)
+        sched = sec.schedule(dt)
+        out[key] = {"wall_s": wall, "ms_per_product": wall / steps * 1e3, "avg_launch_ms": avg,
+                    "min_launch_ms": min(ms), "max_launch_ms": max(ms), "bytes_per_launch": b,
+                    "GBps": b / avg / 1e6, "frac": b / avg / 1e6 / HBM_PEAK_GBPS, "tune_s": tune_s,
+                    "schedule": sched, "kernel": kernel_name(sched, es)}
+        del x, y
+        torch.cuda.empty_cache()
+    sec.close()
+    return out
+
+
+def ladder_time_to_e0(hub, torch, model):
+    """Time-to-E0 on the ladder: the FP64 energy (Ritz residual <= 1e-12 |E0|)
+    is the reference; then the plain FP64 and the mixed Lanczos run again with
+    the target |theta - E_ref| <= 1e-6 |E_ref| recorded; the mixed solve ends with
+    the second pass for psi and the FP64 refinement."""
+    sec = hub.Sector(model)
+    g = sec.ground_state(dtype=hub.F64, want_vector=False, tol=1e-12, max_iter=600, check_every=2)
+    e_ref = g.e0
+    torch.cuda.empty_cache()
+    tgt = dict(e0_target=e_ref, e0_target_rel=1e-6)
+    g64 = sec.ground_state(dtype=hub.F64, want_vector=False, tol=1e-12, max_iter=600, check_every=2,
+                           time_kernels=TIME_EVERY, **tgt)
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    g32 = sec.ground_state(dtype=hub.F32, refine=True, tol=1e-7, max_iter=600, check_every=2,
+                           time_kernels=TIME_EVERY, **tgt)
+    torch.cuda.synchronize()
+    i64, i32 = g64.info, g32.info
+    out = {"dim": sec.dim, "e0_ref_fp64_gpu": e_ref, "reference": "FP64 GPU Lanczos, Ritz residual <= 1e-12 |E0| "
+           "(no oracle value exists at this size: the two-spin matrix would take ~0.8 TB)",
+           "fp64_plain": {"e0": g64.e0, "iters": i64["iters"], "solve_s": i64["seconds"],
+                          "seconds_to_target": i64["seconds_to_target"], "iters_to_target": i64["iters_to_target"],
+                          "product_ms": i64["matvec_ms"] / max(1, i64["matvec_timed"])},
+           "mixed_plain": {"e0_refined_fp64": g32.e0, "e0_ritz_fp32": i32["e0_ritz"], "iters": i32["iters"],
+                           "solve_s_with_psi_and_refinement": i32["seconds"],
+                           "seconds_to_target": i32["seconds_to_target"], "iters_to_target": i32["iters_to_target"],
+                           "true_residual_fp64": i32["true_residual"],
+                           "product_ms": i32["matvec_ms"] / max(1, i32["matvec_timed"])},
+           "rel_err_mixed_refined_vs_fp64": abs(g32.e0 - e_ref) / abs(e_ref),
+           "rel_err_mixed_ritz_vs_fp64": abs(i32["e0_ritz"] - e_ref) / abs(e_ref)}
+    if i64["seconds_to_target"] > 0:
+        out["mixed_over_fp64_time_to_e0"] = i32["seconds_to_target"] / i64["seconds_to_target"]
+    del g32
+    sec.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def ring14_solves(hub, torch, oracle_e0):
+    """Table IV's chain, U = 2, 4, 8: plain FP64, mixed with full
+    reorthogonalisation and plain mixed Lanczos, time-to-E0 against the oracle."""
+    import workloads as W
+    out = {}
+    for U in (2, 4, 8):
+        model = W.config(f"ring14_u{U}")
+        sec = hub.Sector(model)
+        sec.ground_state(dtype=hub.F64, want_vector=False, max_iter=2, allow_not_converged=True)
+        sec.ground_state(dtype=hub.F32, want_vector=False, max_iter=2, allow_not_converged=True)
+        tgt = dict(e0_target=oracle_e0.get(U), e0_target_rel=1e-6) if U in oracle_e0 else {}
+        runs = {
+            "fp64_plain": sec.ground_state(dtype=hub.F64, want_vector=False, tol=1e-12, time_kernels=TIME_EVERY,
+                                           **tgt),
+            "mixed_reorth": sec.ground_state(dtype=hub.F32, reorth=True, refine=True, tol=1e-7,
+                                             time_kernels=TIME_EVERY, **tgt),
+            "mixed_plain": sec.ground_state(dtype=hub.F32, reorth=False, refine=True, tol=1e-7,
+                                            time_kernels=TIME_EVERY, **tgt),
+        }
+        torch.cuda.synchronize()
+        e64 = runs["fp64_plain"].e0
+        r = {"e0_fp64": e64, "e0_oracle": oracle_e0.get(U),
+             "rel_err_fp64_vs_oracle": abs(e64 - oracle_e0[U]) / abs(oracle_e0[U]) if U in oracle_e0 else None,
+             "time_to_e0_s": {k: v.info["seconds_to_target"] for k, v in runs.items()},
+             "iters_to_e0": {k: v.info["iters_to_target"] for k, v in runs.items()},
+             "solve_s": {k: v.info["seconds"] for k, v in runs.items()},
+             "iters": {k: v.info["iters"] for k, v in runs.items()},
+             "rel_err_vs_fp64": {k: abs(v.e0 - e64) / abs(e64) for k, v in runs.items()},
+             "product_ms": {k: v.info["matvec_ms"] / max(1, v.info["matvec_timed"]) for k, v in runs.items()}}
+        if r["time_to_e0_s"]["fp64_plain"] > 0:
+            r["mixed_plain_over_fp64"] = r["time_to_e0_s"]["mixed_plain"] / r["time_to_e0_s"]["fp64_plain"]
+        out[f"U={U}"] = r
+        sec.close()
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -248,7 +360,6 @@ def main():
         return
 
     if args.lanczos_only:
-        # the solver path alone (for counter runs of the fused product): one FP64 and one mixed solve
         name = args.lanczos_only
         sec = hub.Sector(W.config(name))
         for dt in (F64, F32):
@@ -259,142 +370,53 @@ def main():
         return
 
     if args.matvec_only:
-        name, cnt = args.matvec_only.split(":")
+        parts = args.matvec_only.split(":")
+        name, cnt = parts[0], int(parts[1])
+        dts = [F64 if parts[2] == "f64" else F32] if len(parts) > 2 else [F32, F64]
         sec = hub.Sector(W.config(name))
-        for dt in (F32, F64):
+        for dt in dts:
             x = sec.start_vector(seed=1, dtype=dt)
             y = sec.empty(dt)
-            for _ in range(int(cnt)):
+            sec.matvec(x, y)
+            torch.cuda.synchronize()
+            print(f"{name} tuned schedule dtype={'f32' if dt == F32 else 'f64'}: {json.dumps(sec.schedule(dt))}",
+                  flush=True)
+            for _ in range(cnt):
                 sec.matvec(x, y)
             torch.cuda.synchronize()
             print(f"{name} matvec dtype={'f32' if dt == F32 else 'f64'} launches={cnt}", flush=True)
+            del x, y
+            torch.cuda.empty_cache()
         sec.close()
         return
 
-    Us = (2, 4, 8)
-    models = {U: W.config(f"ring14_u{U}") for U in Us}
-
-    # E_ref for time-to-E0 (|theta - E_ref| <= 1e-6 |E_ref|): the stored oracle energies
-    oracle_e0 = {}
-    try:
-        with open(os.path.join(ROOT, "tests", "golden", "oracle_values.json")) as f:
-            ov = json.load(f)["entries"]
-        oracle_e0 = {U: ov[f"ring14_u{U}"]["e0"] for U in Us}
-    except (OSError, KeyError, ValueError):
-        pass
-    tgt = {U: dict(e0_target=oracle_e0.get(U), e0_target_rel=1e-6) for U in Us}
-
-    def one_step():
-        rec = {}
-        for U, model in models.items():
-            r = {}
-            t0 = time.perf_counter()
-            sec = hub.Sector(model)
-            torch.cuda.synchronize()
-            r["setup_s"] = time.perf_counter() - t0
-            runs = {
-                "fp64_plain": sec.ground_state(dtype=F64, want_vector=False, tol=1e-12, time_kernels=TIME_EVERY,
-                                               **tgt[U]),
-                "mixed_reorth": sec.ground_state(dtype=F32, reorth=True, refine=True, tol=1e-7,
-                                                 time_kernels=TIME_EVERY, **tgt[U]),
-                "mixed_plain": sec.ground_state(dtype=F32, reorth=False, refine=True, tol=1e-7,
-                                                time_kernels=TIME_EVERY, **tgt[U]),
-            }
-            torch.cuda.synchronize()
-            r["runs"] = {k: {"e0": v.e0, **v.info} for k, v in runs.items()}
-            r["bytes"] = {"f64": sec.matvec_bytes(F64), "f32": sec.matvec_bytes(F32)}
-            r["dim"] = sec.dim
-            sec.close()
-            rec[U] = r
-        return rec
-
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    recs = [one_step() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-
-    # per dtype: event time, launches and algorithmic bytes of the launched product kernels
-    # (when the first Lanczos update is fused into the product, its kernel also reads v_prev)
-    agg = {"f64": [0.0, 0, 0, 0], "f32": [0.0, 0, 0, 0]}
-    total_bytes = 0
-    fused = {"f64": False, "f32": False}
-    for rec in recs:
-        for U, r in rec.items():
-            for k, v in r["runs"].items():
-                key = "f64" if k.startswith("fp64") else "f32"
-                agg[key][0] += v["matvec_ms"]
-                agg[key][1] += v["matvec_count"]
-                agg[key][2] += v["matvec_count"] * v["matvec_bytes"]
-                agg[key][3] += v["matvec_timed"]
-                fused[key] = fused[key] or v["matvec_bytes"] > r["bytes"][key]
-                total_bytes += v["matvec_count"] * r["bytes"][key]
-    last = recs[-1]
-    kern = {}
-    for key in ("f64", "f32"):
-        ms, cnt, kb, timed = agg[key]
-        if cnt and timed:
-            avg = ms / timed
-            kern[key] = {"avg_ms": avg, "launches": cnt, "timed_launches": timed, "est_total_ms": avg * cnt,
-                         "bytes_per_launch": kb / cnt, "GBps": (kb / cnt) / (avg * 1e-3) / 1e9,
-                         "fused_lanczos_update": fused[key]}
-    dom = max(kern, key=lambda k: kern[k]["est_total_ms"])
-
-    per_U = {}
-    for U in Us:
-        r = last[U]
-        e_ref = r["runs"]["fp64_plain"]["e0"]
-        per_U[f"U={U}"] = {
-            "e0_fp64": e_ref,
-            "e0_oracle": oracle_e0.get(U),
-            "rel_err_fp64_vs_oracle": (abs(e_ref - oracle_e0[U]) / abs(oracle_e0[U])) if U in oracle_e0 else None,
-            "time_to_e0_s": {k: v["seconds_to_target"] for k, v in r["runs"].items()},
-            "iters_to_e0": {k: v["iters_to_target"] for k, v in r["runs"].items()},
-            "time_to_stop_test_s": {k: v["seconds_to_e0"] for k, v in r["runs"].items()},
-            "solve_s": {k: v["seconds"] for k, v in r["runs"].items()},
-            "iters": {k: v["iters"] for k, v in r["runs"].items()},
-            "rel_err_vs_fp64": {k: abs(v["e0"] - e_ref) / abs(e_ref) for k, v in r["runs"].items()},
-            "rel_err_ritz_vs_fp64": {k: abs(v["e0_ritz"] - e_ref) / abs(e_ref) for k, v in r["runs"].items()},
-            "setup_s": r["setup_s"],
-        }
-
+    model = W.config(HEADLINE)
+    head = headline_products(hub, torch, model, args.steps, args.warmup)
+    h64, h32 = head["f64"], head["f32"]
     out = {
         "metric": "H·v GB/s & %HBM peak; Lanczos time-to-E0 mixed vs FP64 at |ΔE0|≤1e-6",
-        "value": total_bytes / wall / 1e9,
+        "value": h64["bytes_per_launch"] * args.steps / h64["wall_s"] / 1e9,
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": h64["ms_per_product"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "ring14 (periodic chain M=14, t=1, U in {2,4,8}, N_up=N_dn=7)",
-                   "dim": last[Us[0]]["dim"], "start_seed": 7542, "vector_bytes_f32": last[Us[0]]["dim"] * 4,
-                   "note": "vectors (47 MB FP32 / 94 MB FP64) fit in the 256 MB MALL"},
-        "roofline": {"bound": "hbm", "achieved": kern[dom]["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": kern[dom]["GBps"] / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": (f"k_kron_quad<{'double' if dom == 'f64' else 'float'}> "
-                                + ("fused with the first Lanczos update (reads v, v_prev; writes w)"
-                                   if fused[dom] else "(reads v; writes H v)")),
-                     "bytes_per_launch": kern[dom]["bytes_per_launch"], "avg_launch_ms": kern[dom]["avg_ms"]},
-        "products": kern,
-        "per_U": per_U,
-        "time_to_e0": {
-            "definition": "wall time from hub_ground_state entry until the lowest Ritz value is within 1e-6 "
-                          "relative of the oracle E0 (checked every step, overlapped with the next step)",
-            **{f"U={U}": {**per_U[f"U={U}"]["time_to_e0_s"],
-                          "mixed_plain_over_fp64": (per_U[f"U={U}"]["time_to_e0_s"]["mixed_plain"] /
-                                                    per_U[f"U={U}"]["time_to_e0_s"]["fp64_plain"])
-                          if per_U[f"U={U}"]["time_to_e0_s"]["fp64_plain"] > 0 else None}
-               for U in Us},
-        },
-        "table4_check": {"U": 4, "printed_E_min": TABLE4_M14_U4,
-                         "e0_fp64": last[4]["runs"]["fp64_plain"]["e0"]},
+        "config": {"workload": "ladder2x9: 2x9 two-leg ladder, legs periodic, t_leg=1, t_rung~U(0.5,1.5) per rung "
+                               "(params seed 1307), U=6, N_up=N_dn=9, dim 48620^2 = 2,363,904,400; one step = one "
+                               "FP64 product Y = H_up V + V H_dn^T + D o V on a resident vector",
+                   "dim": head["dim"], "vector_bytes_f64": head["dim"] * 8, "start_seed": 1,
+                   "schedule_f64": h64["schedule"]},
+        "roofline": {"bound": "hbm", "achieved": h64["GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": h64["frac"], "traffic": None, "kernel": h64["kernel"],
+                     "bytes_per_launch": h64["bytes_per_launch"], "avg_launch_ms": h64["avg_launch_ms"],
+                     "bytes_note": "algorithmic: read V once, write Y once (2 dim s) + one spin's tables "
+                                   "(row pointers, entries, values, basis, site sums); D generated in the kernel"},
+        "products": {"f64": h64, "f32": h32},
         "paper_context": {"note": "one intel i7 (model, cores, precision unstated); not like-for-like",
                           "table4_ring14_lanczos_s": {"two_spin_binary_search": 3459.85,
                                                       "one_spin_binary_search": 702.15,
@@ -402,60 +424,123 @@ def main():
                           "table2_ring14_offdiag_generation_s": {"two_spin": 5.02, "one_spin": 0.55},
                           "generation_speedup_claim": "1/9 to 1/11"},
     }
-    # HBM traffic of the dominant product from the committed counter run, only
-    # while the product source is unchanged since the counters were taken
-    try:
-        import hashlib
-        with open(os.path.join(ROOT, "profiles", "k_kron_fused_counters.json")) as f:
-            cj = json.load(f)
-        with open(os.path.join(ROOT, "paper_1307_7542_amd", "csrc", "matvec.hip"), "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
-        ent = cj["kernels"].get(f"ring14_u4:{dom}" + (":fused" if fused[dom] else ""))
-        if ent and cj.get("matvec_source_sha256") == sha:
-            out["roofline"]["traffic"] = ent["traffic_bytes"]
-            out["roofline"]["traffic_note"] = ("FETCH_SIZE x %.3f + WRITE_SIZE x %.3f per launch (copy-kernel "
-                                               "calibration), U=4, counters taken on %s; %s"
-                                               % (cj["calibration"]["fetch_scale"], cj["calibration"]["write_scale"],
-                                                  ent["kernel"], cj.get("shape_note", "")))
-    except (OSError, KeyError, ValueError):
-        pass
+    traffic = committed_traffic(h64["kernel"])
+    if traffic:
+        out["roofline"]["traffic"] = traffic["bytes"]
+        out["roofline"]["traffic_note"] = traffic["note"]
+    if not args.no_solve:
+        out["time_to_e0_ladder2x9"] = ladder_time_to_e0(hub, torch, model)
     if not args.no_extra:
+        oracle_e0 = {}
+        try:
+            with open(os.path.join(ROOT, "tests", "golden", "oracle_values.json")) as f:
+                ov = json.load(f)["entries"]
+            oracle_e0 = {U: ov[f"ring14_u{U}"]["e0"] for U in (2, 4, 8)}
+        except (OSError, KeyError, ValueError):
+            pass
+        out["ring14_solves"] = ring14_solves(hub, torch, oracle_e0)
+        out["table4_check"] = {"U": 4, "printed_E_min": TABLE4_M14_U4,
+                               "e0_fp64": out["ring14_solves"]["U=4"]["e0_fp64"]}
+        out["products_ring14_u4"] = product_timing(hub, torch, W.config("ring14_u4"))
         out["products_square4x4"] = product_timing(hub, torch, W.config("square4x4"))
         out["lanczos_square4x4_mixed_gradients"] = square_mixed_gradients(hub, torch, W.config("square4x4"))
-        out["products_ladder2x9"] = product_timing(hub, torch, W.config("ladder2x9"), reps=3)
-        out["lanczos_ladder2x9_mixed"] = ladder_mixed(hub, torch, W.config("ladder2x9"))
         out["aim_batch64"] = batch_timing(hub, torch)
-        out["greens_ring14_u4"] = greens_timing(hub, torch, models[4])
-        out["k0_ring14_u4"] = k0_timing(hub, torch, models[4])
+        out["greens_ring14_u4"] = greens_timing(hub, torch, W.config("ring14_u4"))
+        out["k0_ring14_u4"] = k0_timing(hub, torch, W.config("ring14_u4"))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(models[4], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(model, W.config("ring14_u4"), args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(model, target_s):
-    """The oracle as it stands (two-spin basis, binary-search indexing, FP64),
-    timed on a bounded sample of the same workload: whole products (all rows,
-    matrix-free) repeated until about target_s seconds of CPU work."""
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, only
+    while the product source is unchanged since the counters were taken."""
+    try:
+        import hashlib
+        with open(os.path.join(ROOT, "profiles", "product_counters.json")) as f:
+            cj = json.load(f)
+        with open(os.path.join(ROOT, "paper_1307_7542_amd", "csrc", "matvec.hip"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        ent = cj["kernels"].get(f"{HEADLINE}:{kernel}")
+        if not ent or cj.get("matvec_source_sha256") != sha:
+            return None
+        return {"bytes": ent["traffic_bytes"],
+                "note": "FETCH_SIZE x %.3f + WRITE_SIZE x %.3f per launch (copy-kernel calibration), counters "
+                        "from %s" % (cj["calibration"]["fetch_scale"], cj["calibration"]["write_scale"],
+                                     cj.get("command", "?"))}
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(ladder, ring, target_s):
+    """The oracle as it stands (two-spin basis, binary-search indexing, FP64, all
+    host threads), on bounded samples:
+      * the headline product: matrix-free rows of the 2x9 ladder (a contiguous
+        block of rows, repeated to about target_s seconds), as GB/s of the same
+        2 x 8 bytes per row the GPU figure counts;
+      * the ring M=14 (U=4): the full two-spin H built in CSR (the paper's
+        generation step, Tables II/III) and the oracle's FP64 Lanczos on it, with
+        the time until the lowest Ritz value is within 1e-6 of the stored oracle
+        E0 (the GPU time-to-E0 measure)."""
     import numpy as np
+    from scipy.linalg import eigh_tridiagonal
 
     import oracle
-    osec = oracle.Sector(model, explicit_keys=False)
-    rows = np.arange(osec.dim, dtype=np.int64)
-    x = oracle.start_vector(7542, osec.dim)
-    t = time.perf_counter()
-    osec.apply_rows(rows, x)
-    one = time.perf_counter() - t
-    reps = max(1, int(round(target_s / max(one, 1e-9))) - 1)
+    osec = oracle.Sector(ladder, explicit_keys=False)
+    x = None
+    nrows = 1 << 16
+    while True:
+        rows = np.arange(nrows, dtype=np.int64)
+        t = time.perf_counter()
+        osec.apply_rows(rows, x, seed=1)
+        one = time.perf_counter() - t
+        if one >= 0.5 or nrows >= (1 << 24):
+            break
+        nrows *= 4
+    reps = max(1, int(round(target_s / max(one, 1e-9))))
     t = time.perf_counter()
     for _ in range(reps):
-        osec.apply_rows(rows, x)
+        osec.apply_rows(rows, x, seed=1)
     dt = time.perf_counter() - t
-    rate = reps * osec.dim / dt
-    return {"value": rate * 16 / 1e9, "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{reps} whole FP64 products of ring14 U=4 ({osec.dim} rows each; two-spin matrix-free rows "
-                      f"with binary-search indexing) after one warm-up product, {dt:.1f} s; GB/s = rows/s x 16 B "
-                      f"(8 B read + 8 B written per element)",
-            "rows_per_s": rate, "product_s": dt / reps}
+    rate = reps * nrows / dt
+    out = {"value": rate * 16 / 1e9, "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{reps} x {nrows} rows of the 2x9 ladder product (of {osec.dim}), two-spin matrix-free rows "
+                     f"with binary-search indexing, FP64, on the start vector of seed 1, {dt:.1f} s; GB/s = rows/s x "
+                     f"16 B (8 B read + 8 B written per element, as the GPU figure counts)",
+           "rows_per_s": rate, "projected_full_product_s": osec.dim / rate}
+    # ring M=14: generation and Lanczos time-to-E0
+    t = time.perf_counter()
+    rsec = oracle.Sector(ring)
+    csr = rsec.csr()
+    build = time.perf_counter() - t
+    e_ref = None
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "oracle_values.json")) as f:
+            e_ref = json.load(f)["entries"]["ring14_u4"]["e0"]
+    except (OSError, KeyError, ValueError):
+        pass
+    stamps = []
+    t0 = time.perf_counter()
+
+    def mv(v):
+        y = oracle.spmv(csr, v)
+        stamps.append(time.perf_counter() - t0)
+        return y
+    r = oracle.lanczos(mv, rsec.dim, oracle.start_vector(7542, rsec.dim), tol=1e-10, max_iter=300,
+                       reorth=False, want_vector=False)
+    total = time.perf_counter() - t0
+    t_e0, k_e0 = None, None
+    if e_ref is not None:
+        for k in range(1, len(r.alphas) + 1):
+            w = eigh_tridiagonal(r.alphas[:k], r.betas[:k - 1], select="i", select_range=(0, 0))[0][0]
+            if abs(w - e_ref) <= 1e-6 * abs(e_ref):
+                t_e0, k_e0 = stamps[k - 1], k
+                break
+    out["ring14_u4"] = {"two_spin_csr_build_s": build, "nnz": int(len(csr[1])), "lanczos_steps": int(r.iters),
+                        "lanczos_s": total, "time_to_e0_s": t_e0, "iters_to_e0": k_e0, "e0": r.e0,
+                        "note": "oracle FP64 Lanczos without reorthogonalisation on its CSR; time-to-E0 = first "
+                                "step whose lowest Ritz value is within 1e-6 relative of the stored oracle E0"}
+    return out
 
 
 if __name__ == "__main__":

@@ -29,7 +29,10 @@ EXPORTED = [
     "hub_last_error", "hub_version", "hub_batch_create", "hub_batch_destroy", "hub_batch_offsets",
     "hub_batch_matvec", "hub_batch_ground_state", "hub_apply_fermion", "hub_lanczos_coefficients",
     "hub_continued_fraction", "hub_greens_function", "hub_sector_create_k0", "hub_k0_layout",
+    "hub_set_schedule", "hub_get_schedule",
 ]
+
+SCHED_AUTO, SCHED_COLUMNS, SCHED_CHUNKED, SCHED_ROWS, SCHED_CSR = 0, 1, 2, 3, 4
 
 
 class HubError(RuntimeError):
@@ -44,6 +47,19 @@ class _Model(ctypes.Structure):
         ("bond_i", ctypes.c_void_p), ("bond_j", ctypes.c_void_p),
         ("t", ctypes.c_void_p), ("U", ctypes.c_void_p), ("eps", ctypes.c_void_p),
     ]
+
+
+class Schedule(ctypes.Structure):
+    """hub_schedule: product schedule (family, tile shape, optional row-band pass)."""
+    _fields_ = [
+        ("family", ctypes.c_int32), ("tile_cols", ctypes.c_int32), ("block", ctypes.c_int32),
+        ("order", ctypes.c_int32), ("quads_per_lane", ctypes.c_int32), ("chunk_rows", ctypes.c_int32),
+        ("band_rows", ctypes.c_int32), ("band_block", ctypes.c_int32), ("band_chunk", ctypes.c_int32),
+        ("no_fused_update", ctypes.c_int32), ("ms", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class LanczosOpts(ctypes.Structure):
@@ -107,6 +123,8 @@ def lib():
             "hub_greens_function": (i32, [P, ctypes.c_double, P, i32, i32, i32, i32, P, P, P, P, P, P, P]),
             "hub_sector_create_k0": (i32, [P, i32, i32, i32, P]),
             "hub_k0_layout": (i32, [P, P, P, P]),
+            "hub_set_schedule": (i32, [P, i32, P]),
+            "hub_get_schedule": (i32, [P, i32, i32, P]),
             "hub_status_str": (ctypes.c_char_p, [i32]),
             "hub_last_error": (ctypes.c_char_p, []),
             "hub_version": (ctypes.c_char_p, []),
@@ -244,6 +262,23 @@ class Sector:
         bond = np.zeros(max(nnz, 1), dtype=np.int32)
         _check(lib().hub_hopping_csr(self._h, spin, _ptr(rp), _ptr(col), _ptr(val), _ptr(bond)), "hub_hopping_csr")
         return rp, col[:nnz], val[:nnz], bond[:nnz]
+
+    def set_schedule(self, dtype: int, family: Optional[int] = None, *, tile_cols: int = 1, block: int = 1024,
+                     order: int = 1, quads_per_lane: int = 4, chunk_rows: int = 0, band_rows: int = 0,
+                     band_block: int = 1024, band_chunk: int = 0, no_fused_update: bool = False):
+        """Force the product schedule of `dtype` (family None: back to the tuned one)."""
+        if family is None:
+            _check(lib().hub_set_schedule(self._h, dtype, None), "hub_set_schedule")
+            return
+        sc = Schedule(family, tile_cols, block, order, quads_per_lane, chunk_rows, band_rows, band_block,
+                      band_chunk, int(no_fused_update), 0.0)
+        _check(lib().hub_set_schedule(self._h, dtype, ctypes.byref(sc)), "hub_set_schedule")
+
+    def schedule(self, dtype: int = F64, fused: bool = False) -> dict:
+        """The product schedule in use (family 0: not chosen yet)."""
+        sc = Schedule()
+        _check(lib().hub_get_schedule(self._h, dtype, int(fused), ctypes.byref(sc)), "hub_get_schedule")
+        return sc.as_dict()
 
     def matvec_bytes(self, dtype: int = F64) -> int:
         b = ctypes.c_int64()

@@ -172,30 +172,6 @@ hub_status create(const hub_model *m, int32_t n_up, int32_t n_dn, hub_sector **o
     }
     const int64_t cu = s->spin[0].count, cd = s->spin[1].count;
     if (cu > INT32_MAX || cd > INT32_MAX) return fail(HUB_ERR_RANGE, "one-spin dimension exceeds 2^31");
-    // columns that do not fit in one workgroup's LDS get row-chunked tables;
-    // HUB_CHUNK_ROWS=<n> forces them (chunks of n rows) for testing
-    // Chunks are sized for several columns per work item (each entry then serves
-    // them all): 4 in FP32, 2 in FP64 (2x9 ladder FP32 36.8 -> 30.1 ms, FP64
-    // 63.5 -> 58.4 ms against one column); HUB_CHUNK_TB=<1|2|4> overrides.
-    const char *force = getenv("HUB_CHUNK_ROWS");
-    const int force_rows = force ? atoi(force) : 0;
-    const char *tbs = getenv("HUB_CHUNK_TB");
-    const int tb_env = tbs ? (atoi(tbs) >= 4 ? 4 : atoi(tbs) >= 2 ? 2 : 1) : 0;
-    for (int dt : {HUB_F64, HUB_F32}) {
-        const size_t es = (dt == HUB_F64) ? 8 : 4;
-        const int di = (dt == HUB_F64) ? 0 : 1;
-        const int ctb = tb_env ? (dt == HUB_F64 ? std::min(tb_env, 2) : tb_env) : (dt == HUB_F64 ? 2 : 4);
-        if (!s->spin[0].ell_c32) break;
-        if (force_rows > 0) {
-            HUB_TRY(build_chunked_tables(s, HUB_SPIN_UP, dt, force_rows, st));
-            s->force_chunked = true;
-        } else if ((size_t)(cu + 256) * es > s->lds_max) {
-            const int rows = (int)((s->lds_max / es - 256) / ctb / 64 * 64);
-            HUB_TRY(build_chunked_tables(s, HUB_SPIN_UP, dt, rows, st));
-        }
-        s->spin[0].chunk_tb[di] = ctb;
-        s->spin[1].chunk_tb[di] = ctb;
-    }
     s->dim = cu * cd;
     HUB_HIP(hipDeviceSynchronize());
     guard.s = nullptr;
@@ -350,6 +326,23 @@ hub_status hub_matvec(const hub_sector *sec, int32_t dtype, const void *dev_x, v
     const uintptr_t es = (dtype == HUB_F64) ? 8 : 4;
     if (((uintptr_t)x | (uintptr_t)y) % es) return fail(HUB_ERR_INVALID_ARG, "x or y not aligned to its element");
     return apply_h(sec, dtype, dev_x, dev_y, (hipStream_t)stream);
+}
+
+hub_status hub_set_schedule(hub_sector *sec, int32_t dtype, const hub_schedule *sched)
+{
+    HUB_TRY(check_sector(sec));
+    HUB_TRY(check_dtype(dtype));
+    if (sec->k0) return fail(HUB_ERR_UNSUPPORTED, "k = 0 sectors have a product of their own");
+    HUB_HIP(hipSetDevice(sec->device));
+    return set_schedule(sec, dtype, sched);
+}
+
+hub_status hub_get_schedule(const hub_sector *sec, int32_t dtype, int32_t fused, hub_schedule *out)
+{
+    HUB_TRY(check_sector(sec));
+    HUB_TRY(check_dtype(dtype));
+    if (!out) return fail(HUB_ERR_INVALID_ARG, "out is NULL");
+    return get_schedule(sec, dtype, fused, out);
 }
 
 hub_status hub_matvec_bytes(const hub_sector *sec, int32_t dtype, int64_t *bytes)

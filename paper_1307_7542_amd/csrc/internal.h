@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <deque>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -48,15 +50,6 @@ struct SpinTables {
     uint32_t *ell_c32 = nullptr;
     double *code_v64 = nullptr;  // [256]
     float *code_v32 = nullptr;   // [256]
-    // Row-chunked compact copies for columns larger than the LDS: chunk p holds,
-    // for every row, the entries whose column lies in [p*chunk_rows, (p+1)*chunk_rows)
-    // (a contiguous sub-range of the sorted CSR row), columns relative to the chunk.
-    int nchunks[2] = {0, 0};        // per dtype (0: FP64, 1: FP32)
-    int chunk_rows[2] = {0, 0};
-    int chunk_tb[2] = {1, 1};       // columns per work item the chunks were sized for
-    int32_t *ch_off[2] = {nullptr, nullptr};   // [nchunks * (nslices + 1)] entry offsets / 64
-    int64_t *ch_base[2] = {nullptr, nullptr};  // host-side copy not needed; device [nchunks]
-    uint32_t *ch_ell[2] = {nullptr, nullptr};
 };
 
 // Translation symmetry, k = 0 (Sec. VI), in the layout phi[i + b R] =
@@ -87,9 +80,28 @@ struct K0Tables {
     int32_t *short_sigma = nullptr;  // [n_short] G^P_i |R_i> = sigma |R_i>
 };
 
-// Tuned shape of the four-rows-per-lane product (0 = not tuned yet).
-struct QuadShape {
-    int tb = 0, bs = 0, xc = 0;
+// Compact entries of H_sigma split by column chunk (for products whose staged
+// data covers one chunk of columns at a time): chunk p holds, for every row,
+// the entries whose column lies in [p rows, (p+1) rows) -- a contiguous
+// sub-range of the sorted CSR row -- with columns relative to the chunk, in the
+// sliced-ELL layout (slice offsets in units of 64 entries).
+struct ChunkSet {
+    int spin = 0;
+    int rows = 0;               // columns per chunk
+    int n = 0;                  // chunks
+    int32_t *off = nullptr;     // [n * (nslices + 1)]
+    int64_t *base = nullptr;    // [n] first entry of chunk p
+    uint32_t *ell = nullptr;    // entries {column - p rows : 24, code : 8}
+};
+
+// Product schedule (see hub_schedule in hubbard.h): fam 0 = not chosen yet.
+struct Sched {
+    int fam = 0;
+    int tb = 0, bs = 0, xc = 0;  // column pass: columns per workgroup, lanes, tile order
+    int qpl = 0;                 // row-chunked column pass: lane-quads per lane
+    int crows = 0;               // row-chunked column pass: rows per staged chunk
+    int br = 0, bbs = 0, bch = 0;  // row-band pass: rows per band, lanes, columns per staged chunk
+    int nofuse = 0;              // forced: keep the Lanczos update out of the product
     float ms = 0.f;
 };
 
@@ -116,12 +128,17 @@ struct hub_sector {
     double *d_U64 = nullptr;          // [M] per-site U
     float *d_U32 = nullptr;           // [M]
     size_t lds_max = 65536;           // dynamic LDS a workgroup may request
-    bool force_chunked = false;       // use the row-chunked product even when a column fits
     int cu_count = 256;
     std::vector<void *> owned;        // every device allocation, freed by destroy
     hub::K0Tables *k0 = nullptr;      // set for a translation-symmetric k = 0 sector
-    mutable hub::QuadShape quad[2];   // per dtype (0: FP64, 1: FP32), set by the first product
-    mutable hub::QuadShape quad_lz[2];  // the same for the product fused with the Lanczos update
+    // Product schedules per dtype (0: FP64, 1: FP32): the tuner's pick for the
+    // plain product and for the product fused with the Lanczos update, or one
+    // forced through hub_set_schedule; chunk tables built on first use.  The
+    // sector is immutable to callers; these caches are guarded by `mu`.
+    mutable std::mutex mu;
+    mutable hub::Sched sched[2], sched_lz[2];
+    mutable bool forced[2] = {false, false};
+    mutable std::deque<hub::ChunkSet> chunks;  // stable addresses
 };
 
 namespace hub {
@@ -130,7 +147,8 @@ namespace hub {
 hub_status build_spin_tables(hub_sector *s, int spin, int N, hipStream_t st);
 // rp[0] = 0, rp[k + 1] = len[0] + ... + len[k] (temporaries owned by s)
 hub_status scan_lengths(hub_sector *s, const int32_t *len, int64_t n, int32_t *rp, hipStream_t st);
-hub_status build_chunked_tables(hub_sector *s, int spin, int dtype, int chunk_rows, hipStream_t st);
+// chunk tables of H_spin with `rows` columns per chunk (built once, then cached)
+hub_status chunk_set(const hub_sector *s, int spin, int rows, const ChunkSet **out, hipStream_t st);
 hub_status rank_device(const hub_sector *s, int spin, const uint64_t *dx, int64_t n, int64_t *dout,
                        hipStream_t st);
 
@@ -151,6 +169,10 @@ hub_status launch_matvec_lz(const hub_sector *s, int dtype, const void *x, void 
 hub_status launch_sum(const double *partial, int64_t np, double *out, hipStream_t st, int sqrt_result = 0);
 hub_status launch_diagonal(const hub_sector *s, int dtype, void *out, hipStream_t st);
 int64_t matvec_bytes(const hub_sector *s, int dtype);
+// force a product schedule (NULL: back to the tuned one); the schedule in use
+// (fused: the one of the product fused with the Lanczos update)
+hub_status set_schedule(const hub_sector *s, int dtype, const hub_schedule *h);
+hub_status get_schedule(const hub_sector *s, int dtype, int fused, hub_schedule *h);
 
 // ---- vectors (vec.hip) -------------------------------------------------
 constexpr int kRedBlock = 256;

@@ -225,6 +225,24 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     tm.st = st;
 
     const int kmax = max_iter + 1;
+    // Refuse before allocating anything when the vectors cannot fit in the free
+    // device memory: three (plain recurrence) or up to max_iter + 1 stored
+    // Lanczos vectors plus the update's (full reorthogonalisation), an FP64 psi
+    // when the caller passes none, and the refinement's FP64 H psi.
+    {
+        size_t free_b = 0, total_b = 0;
+        HUB_HIP(hipMemGetInfo(&free_b, &total_b));
+        const double vec = (double)es * (double)n;
+        double need = vec * (reorth ? (double)kmax + 1.0 : 3.0);
+        if (want_vec && !dev_psi) need += 8.0 * (double)n;
+        if (o->refine) need += 8.0 * (double)n;
+        if (need > (double)free_b) {
+            set_error("Lanczos workspace of " + std::to_string(need / 1e9) + " GB exceeds the " +
+                      std::to_string((double)free_b / 1e9) + " GB of free device memory" +
+                      (reorth ? " (full reorthogonalisation stores up to max_iter + 1 vectors)" : ""));
+            return HUB_ERR_OOM;
+        }
+    }
     double *dscal = nullptr;  // alpha[kmax] beta[kmax+1] misc[16] ycoef[kmax]
     HUB_TRY(mem.alloc((void **)&dscal, sizeof(double) * (size_t)(3 * kmax + 32)));
     double *d_alpha = dscal, *d_beta = dscal + kmax, *d_misc = dscal + 2 * kmax + 1,

@@ -2,37 +2,42 @@
 //
 //     Y = H_up V + V H_dn^T + D o V,   V, Y: count_up x count_dn, column-major.
 //
-// H_dn is real symmetric, so column b of V H_dn^T is sum_l H_dn[b, l] V[:, l].
-// D(a, b) = U-part(basis_up[a] & basis_dn[b]) + e_up[a] + e_dn[b] is generated
-// from the bit patterns (the doubly occupied sites of Sec. III B) and never
-// stored.
+// H_dn is real symmetric, so column b of V H_dn^T is sum_l H_dn[b, l] V[:, l]
+// and row a of it is H_dn applied to row a of V.  D(a, b) = U-part(basis_up[a]
+// & basis_dn[b]) + e_up[a] + e_dn[b] is generated from the bit patterns (the
+// doubly occupied sites of Sec. III B) and never stored.
 //
-// The two terms want orthogonal access patterns.  In column-major storage the
-// H_dn term combines whole neighbouring columns (coalesced, with a row of H_dn
-// that is uniform over a workgroup), while the H_up term gathers inside one
-// column along a different row of H_up for every lane.  Schedules:
+// The two terms want orthogonal access patterns: the H_up term gathers inside
+// one column of V, the H_dn term inside one row.  Schedules (hub_schedule in
+// hubbard.h; the tuner times the candidates on the first product):
 //
-//   k_kron_quad (default when count_up % 4 == 0 and a column fits in LDS): one
-//             workgroup per TB output columns, the TB input columns staged in
-//             LDS for the H_up gathers, the H_dn neighbour columns read through
-//             L2 / MALL; each lane owns four consecutive rows (16-byte accesses).
-//             The tile shape is timed on the first product and cached; the
-//             first Lanczos update can be fused into its epilogue.
-//   k_kron_fused: the same schedule with one row per lane (count_up % 4 != 0).
-//   k_kron_chunked_parts (a column larger than the LDS): work items of TB
-//             columns x a part of the rows; the row chunks of the columns are
-//             staged in turn and the output rows stay in registers.
-//   two-pass, csr, one-row chunked: kept for measurement and for sectors whose
-//             entries do not fit the compact format (csr fallback).
+//   columns   whole columns of V staged in LDS (k_kron_quad, four rows per
+//             lane): the H_up term gathers from LDS; in one pass the H_dn term
+//             reads its neighbour columns through L2 / MALL.
+//   chunked   columns larger than the LDS (k_kron_chunked_parts): the columns
+//             are staged chunk by chunk while the output rows stay in registers.
+//   two-pass  either of the above without the H_dn term (writes Y = D o V +
+//             H_up V), then the row-band pass k_kron_dn_band: bands of R rows
+//             of V are staged in LDS chunk by chunk, slot of R elements per
+//             column, and each lane adds the H_dn entries of its output columns
+//             from LDS into Y, accumulators in registers.  Every element of V is
+//             then read from HBM twice instead of once plus deg_dn times
+//             through the caches.
+//   rows      one row per lane (k_kron_fused), for count_up % 4 != 0 or
+//             vectors that are not 16-byte aligned.
+//   csr       rows of the CSR gathered from global memory (no compact entries).
+//
+// Every schedule computes each element as: diagonal, then the H_up entries in
+// column order, then the H_dn entries in column order, one rounding per term, so
+// all give bit-identical products (tested).
 //
 // H_up is read from its sliced-ELL copy: lane r of a wavefront owns row
 // 64*s + r of slice s and loads entry k from a coalesced address; the default
 // entry is {column : 24, code : 8} with the value looked up in a 256-entry
-// table in LDS.
+// table in LDS (code = 2 bond + (esign < 0), 255 = padding).
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
-#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -46,7 +51,7 @@ namespace {
 template <typename T>
 struct MvArgs {
     const T *__restrict__ x;
-    T *y;  // may alias the intermediate of the two-pass product
+    T *y;
     int32_t cu, cd;
     const int32_t *__restrict__ up_rp;
     const int32_t *__restrict__ up_col;
@@ -116,7 +121,12 @@ __device__ __forceinline__ void up_term(T (&acc)[TB], const T *xs, const Pk<T> *
         const Vec<T, TB> x2 = *reinterpret_cast<const Vec<T, TB> *>(xs + c2 * TB);
         const Vec<T, TB> x3 = *reinterpret_cast<const Vec<T, TB> *>(xs + c3 * TB);
 #pragma unroll
-        for (int t = 0; t < TB; ++t) acc[t] += (v0 * x0.v[t] + v1 * x1.v[t]) + (v2 * x2.v[t] + v3 * x3.v[t]);
+        for (int t = 0; t < TB; ++t) {
+            acc[t] += v0 * x0.v[t];
+            acc[t] += v1 * x1.v[t];
+            acc[t] += v2 * x2.v[t];
+            acc[t] += v3 * x3.v[t];
+        }
     }
     for (; k < len; ++k) {
         int c0;
@@ -144,7 +154,12 @@ __device__ __forceinline__ void up_term_c(T (&acc)[TB], const T *xs, const T *ta
         const Vec<T, TB> x2 = *reinterpret_cast<const Vec<T, TB> *>(xs + (e2 & 0xFFFFFFu) * TB);
         const Vec<T, TB> x3 = *reinterpret_cast<const Vec<T, TB> *>(xs + (e3 & 0xFFFFFFu) * TB);
 #pragma unroll
-        for (int t = 0; t < TB; ++t) acc[t] += (v0 * x0.v[t] + v1 * x1.v[t]) + (v2 * x2.v[t] + v3 * x3.v[t]);
+        for (int t = 0; t < TB; ++t) {
+            acc[t] += v0 * x0.v[t];
+            acc[t] += v1 * x1.v[t];
+            acc[t] += v2 * x2.v[t];
+            acc[t] += v3 * x3.v[t];
+        }
     }
     for (; k < len; ++k) {
         const uint32_t e0 = ell[o0 + 64 * k];
@@ -155,20 +170,12 @@ __device__ __forceinline__ void up_term_c(T (&acc)[TB], const T *xs, const T *ta
     }
 }
 
-// sum_k H_dn[b, k] x[a + col_k * cu] over row b of H_dn (uniform over the wavefront).
+// acc += sum_k H_dn[b, k] x[a + col_k * cu] over row b of H_dn (uniform over the wavefront).
 template <typename T>
-__device__ __forceinline__ T dn_term(const MvArgs<T> &A, int ks, int ke, const T *__restrict__ xa)
+__device__ __forceinline__ void dn_term(T &acc, const MvArgs<T> &A, int ks, int ke, const T *__restrict__ xa)
 {
     const int64_t cu = A.cu;
-    T s = (T)0;
-    int k = ks;
-    for (; k + 4 <= ke; k += 4) {
-        const int64_t l0 = A.dn_col[k], l1 = A.dn_col[k + 1], l2 = A.dn_col[k + 2], l3 = A.dn_col[k + 3];
-        const T y0 = xa[l0 * cu], y1 = xa[l1 * cu], y2 = xa[l2 * cu], y3 = xa[l3 * cu];
-        s += (A.dn_val[k] * y0 + A.dn_val[k + 1] * y1) + (A.dn_val[k + 2] * y2 + A.dn_val[k + 3] * y3);
-    }
-    for (; k < ke; ++k) s += A.dn_val[k] * xa[(int64_t)A.dn_col[k] * cu];
-    return s;
+    for (int k = ks; k < ke; ++k) acc += A.dn_val[k] * xa[(int64_t)A.dn_col[k] * cu];
 }
 
 // Block -> tile with every XCD (workgroup i runs on XCD i mod 8) owning a
@@ -191,14 +198,7 @@ __device__ __forceinline__ void stage_columns(const MvArgs<T> &A, T *xs, int b0,
     }
 }
 
-// ---- fused, four consecutive rows per lane ------------------------------
-// Same schedule and per-element arithmetic order as k_kron_fused, but lane q
-// owns rows 4q .. 4q+3 (count_up % 4 == 0): the column staging, the H_dn
-// neighbour reads and the stores become 16-byte (FP32) or 2 x 16-byte (FP64)
-// accesses, and the four rows' sliced-ELL entries k are four consecutive
-// lanes of the slice, read with one 16-byte load.  XC: XCD-contiguous tile
-// order (workgroup i on XCD i mod 8 takes the i-th tile of that XCD's range)
-// or plain launch order.
+// ---- 16-byte accesses ---------------------------------------------------
 template <typename T>
 struct Q4 {
     T v[4];
@@ -274,11 +274,32 @@ __device__ __forceinline__ void st_q4(T *p, const T (&v)[4])
     }
 }
 
+// one 16-byte piece: 4 FP32 or 2 FP64 elements
+template <typename T>
+struct P16 {
+    static constexpr int N = 16 / (int)sizeof(T);
+    T v[N];
+};
+
+template <typename T>
+__device__ __forceinline__ P16<T> ld16(const T *p)
+{
+    P16<T> r;
+    const uint4 q = *reinterpret_cast<const uint4 *>(p);
+    __builtin_memcpy(r.v, &q, 16);
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void st16(T *p, const P16<T> &v)
+{
+    uint4 q;
+    __builtin_memcpy(&q, v.v, 16);
+    *reinterpret_cast<uint4 *>(p) = q;
+}
+
 // First Lanczos update fused into the product's epilogue: w = (H x) - beta v_prev
-// (rounded as the separate update kernel does) and the sum of w * x per column:
-// each group of 64 lane-quads (256 rows) is summed by one wavefront in a fixed
-// order, then the groups of a column in increasing order, so the per-column
-// partials do not depend on the tile shape.
+// (rounded as the separate update kernel does) and partial sums of w * x.
 //
 // unnorm: the Lanczos vectors are kept unnormalised, x = beta_k v_k and
 // vprev = beta_{k-1} v_{k-1} (beta_0 taken as 1, beta NULL at the first step),
@@ -290,7 +311,7 @@ template <typename T>
 struct LzEpi {
     const T *vprev;           // NULL at the first step
     const double *beta;       // beta_k (device)
-    double *apart;            // [cd] per-column partials
+    double *apart;            // partials (per column or per band item)
     int G;                    // lane-quad groups per column: ceil(count_up / 256)
     const double *beta_prev;  // unnorm: beta_{k-1} (device), NULL for beta_0
     int unnorm;
@@ -310,11 +331,54 @@ __device__ __forceinline__ double quad_wave_sum(double v)
     return v;
 }
 
-template <typename T, int TB, int BS, bool XC, bool EPI>
+template <typename T>
+struct EpiCoef {
+    double sx = 1.0, bt = 0.0;
+};
+
+template <typename T>
+__device__ __forceinline__ EpiCoef<T> epi_coef(const LzEpi<T> &E)
+{
+    EpiCoef<T> c;
+    if (E.unnorm) {
+        c.sx = inv_beta(E.beta);
+        c.bt = E.vprev ? *E.beta * inv_beta(E.beta_prev) : 0.0;
+    } else if (E.vprev) {
+        c.bt = *E.beta;
+    }
+    return c;
+}
+
+// w from the product value o and the v_prev value vp (see LzEpi)
+template <typename T>
+__device__ __forceinline__ T epi_w(const LzEpi<T> &E, const EpiCoef<T> &c, T o, T vp)
+{
+    if (E.unnorm) {
+        if (E.vprev) return (T)fma(c.sx, (double)o, -(c.bt * (double)vp));
+        return (T)(c.sx * (double)o);
+    }
+    if (E.vprev) return (T)fma(-c.bt, (double)vp, (double)o);
+    return o;
+}
+
+// ---- whole columns in LDS, four consecutive rows per lane -----------------
+// One workgroup per TB output columns; lane q owns rows 4q .. 4q+3 (count_up %
+// 4 == 0): the column staging, the H_dn neighbour reads and the stores are
+// 16-byte (FP32) or 2 x 16-byte (FP64) accesses, and the four rows' sliced-ELL
+// entries k are four consecutive lanes of the slice, read with one 16-byte
+// load.  XC: XCD-contiguous tile order (workgroup i on XCD i mod 8 takes the
+// i-th tile of that XCD's range) or plain launch order.  DN: add the H_dn term
+// (one pass); without it the kernel is the column pass of the two-pass
+// schedule.  EPI (with DN): the first Lanczos update, each group of 64
+// lane-quads (256 rows) summed by one wavefront in a fixed order, then the
+// groups of a column in increasing order, so the per-column partials do not
+// depend on the tile shape.
+template <typename T, int TB, int BS, bool XC, bool EPI, bool DN>
 __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__restrict__ sl_off,
                                                   const uint32_t *__restrict__ ellc, const T *__restrict__ code_v,
                                                   int ntiles, LzEpi<T> E)
 {
+    static_assert(DN || !EPI, "the fused update needs the whole product");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tab = reinterpret_cast<T *>(smem_raw);  // 256 code values
     T *xs = tab + 256;                         // TB staged columns, interleaved
@@ -352,15 +416,8 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
     }
     const int64_t cu64 = cu;
     const int lane = threadIdx.x & 63;
-    double bt = 0.0, sx = 1.0;
-    if (EPI) {
-        if (E.unnorm) {
-            sx = inv_beta(E.beta);
-            bt = E.vprev ? *E.beta * inv_beta(E.beta_prev) : 0.0;
-        } else if (E.vprev) {
-            bt = *E.beta;
-        }
-    }
+    EpiCoef<T> ec;
+    if (EPI) ec = epi_coef(E);
     // with the epilogue every lane of a wavefront runs the same iterations (it
     // reduces over the wavefront); without it a lane stops after its last quad
     for (int q = threadIdx.x; EPI ? (q - lane < nq) : (q < nq); q += BS) {
@@ -411,26 +468,28 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
                 for (int t = 0; t < TB; ++t) acc[i][t] += v * xr[t];
             }
         }
-        // H_dn term: whole neighbour columns, four rows per load
+        if constexpr (DN) {
+            // H_dn term: whole neighbour columns, four rows per load
 #pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            int kk = ds[t];
-            for (; kk + 4 <= de[t]; kk += 4) {
-                Q4<T> v[4];
+            for (int t = 0; t < TB; ++t) {
+                int kk = ds[t];
+                for (; kk + 4 <= de[t]; kk += 4) {
+                    Q4<T> v[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
+                    for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const T w = A.dn_val[kk + u];
+                    for (int u = 0; u < 4; ++u) {
+                        const T w = A.dn_val[kk + u];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[r][t] += w * v[u].v[r];
+                        for (int r = 0; r < 4; ++r) acc[r][t] += w * v[u].v[r];
+                    }
                 }
-            }
-            for (; kk < de[t]; ++kk) {
-                const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
-                const T w = A.dn_val[kk];
+                for (; kk < de[t]; ++kk) {
+                    const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
+                    const T w = A.dn_val[kk];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r][t] += w * v.v[r];
+                    for (int r = 0; r < 4; ++r) acc[r][t] += w * v.v[r];
+                }
             }
         }
 #pragma unroll
@@ -440,20 +499,8 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
             if (EPI) {
                 double part = 0.0;
                 if (live) {
-                    if (E.unnorm) {
-                        if (E.vprev) {
-                            const Q4<T> &vp = vpq[t];
 #pragma unroll
-                            for (int r = 0; r < 4; ++r) o[r] = (T)fma(sx, (double)o[r], -(bt * (double)vp.v[r]));
-                        } else {
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) o[r] = (T)(sx * (double)o[r]);
-                        }
-                    } else if (E.vprev) {
-                        const Q4<T> &vp = vpq[t];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) o[r] = (T)fma(-bt, (double)vp.v[r], (double)o[r]);
-                    }
+                    for (int r = 0; r < 4; ++r) o[r] = epi_w(E, ec, o[r], E.vprev ? vpq[t].v[r] : (T)0);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) part += (double)o[r] * (double)xs[(a0 + r) * TB + t];
                 }
@@ -477,107 +524,18 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
     }
 }
 
-// Row-chunked product with four consecutive rows per lane (count_up and the
-// chunk length multiples of 4): the access pattern of k_kron_quad applied to
-// the phases of k_kron_chunked.
-template <typename T, int BS, bool XC>
-__global__ __launch_bounds__(BS) void k_kron_chunked_quad(MvArgs<T> A, const int32_t *__restrict__ ch_off,
-                                                          const int64_t *__restrict__ ch_base,
-                                                          const uint32_t *__restrict__ ch_ell,
-                                                          const T *__restrict__ code_v, int nchunks, int chunk_rows,
-                                                          int nslices)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *tab = reinterpret_cast<T *>(smem_raw);
-    T *xs = tab + 256;
-    const int tile = XC ? xcd_tile(A.cd) : ((int)blockIdx.x < A.cd ? (int)blockIdx.x : -1);
-    if (tile < 0) return;
-    const int cu = A.cu, nq = cu >> 2;
-    const int b = tile;
-    const int64_t cu64 = cu;
-    const T *__restrict__ xb = A.x + (int64_t)b * cu;
-    T *yb = A.y + (int64_t)b * cu;
-    for (int i = threadIdx.x; i < 256; i += BS) tab[i] = code_v[i];
-    const int ds = A.dn_rp[b], de = A.dn_rp[b + 1];
-    const uint32_t dnb = A.dn_basis[b];
-    const T edn = A.e_dn[b];
-    for (int p = 0; p < nchunks; ++p) {
-        const int q0 = (p * chunk_rows) >> 2;
-        const int q1 = min(nq, q0 + (chunk_rows >> 2));
-        __syncthreads();  // previous phase done with xs
-        for (int q = q0 + threadIdx.x; q < q1; q += BS) {
-            const Q4<T> v = ld_q4(xb + 4 * q);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) xs[4 * (q - q0) + r] = v.v[r];
-        }
-        __syncthreads();
-        const int32_t *off = ch_off + (int64_t)p * (nslices + 1);
-        const uint32_t *ell = ch_ell + ch_base[p];
-        for (int q = threadIdx.x; q < nq; q += BS) {
-            const int a0 = 4 * q;
-            T acc[4];
-            if (p == 0) {
-                const uint4 ub = *reinterpret_cast<const uint4 *>(A.up_basis + a0);
-                const uint32_t uu[4] = {ub.x, ub.y, ub.z, ub.w};
-                const Q4<T> eu = ld_q4(A.e_up + a0);
-                const Q4<T> xv = ld_q4(xb + a0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] = (diag_u(A, uu[r] & dnb) + eu.v[r] + edn) * xv.v[r];
-            } else {
-                const Q4<T> yv = ld_q4(yb + a0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] = yv.v[r];
-            }
-            const int s = a0 >> 6;
-            const uint4 *__restrict__ e4 = reinterpret_cast<const uint4 *>(ell + (int64_t)off[s] * 64 + (a0 & 63));
-            const int len = off[s + 1] - off[s];
-            int k = 0;
-            for (; k + 2 <= len; k += 2) {
-                const uint4 ea = e4[16 * k], eb = e4[16 * (k + 1)];
-                const uint32_t e[8] = {ea.x, ea.y, ea.z, ea.w, eb.x, eb.y, eb.z, eb.w};
-#pragma unroll
-                for (int i = 0; i < 8; ++i) acc[i & 3] += tab[e[i] >> 24] * xs[e[i] & 0xFFFFFFu];
-            }
-            if (k < len) {
-                const uint4 ea = e4[16 * k];
-                const uint32_t e[4] = {ea.x, ea.y, ea.z, ea.w};
-#pragma unroll
-                for (int i = 0; i < 4; ++i) acc[i] += tab[e[i] >> 24] * xs[e[i] & 0xFFFFFFu];
-            }
-            if (p == 0) {
-                int kk = ds;
-                for (; kk + 4 <= de; kk += 4) {
-                    Q4<T> v[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const T w = A.dn_val[kk + u];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[r] += w * v[u].v[r];
-                    }
-                }
-                for (; kk < de; ++kk) {
-                    const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
-                    const T w = A.dn_val[kk];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[r] += w * v.v[r];
-                }
-            }
-            st_q4(yb + a0, acc);
-        }
-    }
-}
-
-// Row-chunked product with the output held in registers: work item (tile of TB
-// columns, row part j) owns quads [j BS QPL, (j+1) BS QPL) of its columns, QPL
-// per lane.  It stages every row chunk of its columns in turn (interleaved,
-// element (a, t) at a TB + t) and accumulates the chunk's H_up entries of its
-// rows, each entry serving the TB columns; then the H_dn term and one store.
-// Per element: diagonal, H_up entries in column order, H_dn entries -- the
-// order of k_kron_quad -- and no partial results in memory.  Tiles are
-// interleaved over the XCDs (tile = 8 k + xcd), row parts dispatched in turn.
-template <typename T, int BS, int QPL, int TB>
+// ---- columns larger than the LDS: row-chunked staging --------------------
+// Work item (tile of TB columns, row part j) owns quads [j BS QPL, (j+1) BS
+// QPL) of its columns, QPL per lane.  It stages every row chunk of its columns
+// in turn (interleaved, element (a, t) at a TB + t) and accumulates the chunk's
+// H_up entries of its rows, each entry serving the TB columns; then (DN) the
+// H_dn term and one store.  No partial results go through memory.  Tiles are
+// interleaved over the XCDs (tile = 8 k + xcd); TM = 0: row parts dispatched in
+// turn (every tile's first part, then every tile's second, ...: the neighbour
+// rows read at a time by the one-pass H_dn term are one part's), TM = 1: the
+// parts of a tile consecutively on one XCD (its staged columns are then read
+// from that XCD's L2 by the later parts).
+template <typename T, int BS, int QPL, int TB, bool DN, bool TM>
 __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const int32_t *__restrict__ ch_off,
                                                            const int64_t *__restrict__ ch_base,
                                                            const uint32_t *__restrict__ ch_ell,
@@ -590,12 +548,9 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const in
     const int xcd = (int)(blockIdx.x & 7), r = (int)(blockIdx.x >> 3);
     const int cd = A.cd;
     const int ntiles = (cd + TB - 1) / TB;
-    // part-major: every tile's first row part, then every tile's second, ... so
-    // the neighbour rows the chip reads at a time are one part's (2x9 ladder:
-    // FP32 30.6 -> 30.0 ms, FP64 57.8 -> 56.1 ms against the parts of a tile
-    // dispatched together)
     const int n8 = (ntiles + 7) / 8;
-    const int tile = 8 * (r % n8) + xcd, part = r / n8;
+    const int tile = TM ? 8 * (r / P) + xcd : 8 * (r % n8) + xcd;
+    const int part = TM ? r % P : r / n8;
     if (tile >= ntiles) return;
     const int b0 = tile * TB;
     const int cu = A.cu, nq = cu >> 2;
@@ -687,23 +642,25 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const in
         const int a0 = 4 * q;
 #pragma unroll
         for (int t = 0; t < TB; ++t) {
-            int kk = ds[t];
-            for (; kk + 4 <= de[t]; kk += 4) {
-                Q4<T> v[4];
+            if constexpr (DN) {
+                int kk = ds[t];
+                for (; kk + 4 <= de[t]; kk += 4) {
+                    Q4<T> v[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
+                    for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const T w = A.dn_val[kk + u];
+                    for (int u = 0; u < 4; ++u) {
+                        const T w = A.dn_val[kk + u];
 #pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v[u].v[rr];
+                        for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v[u].v[rr];
+                    }
                 }
-            }
-            for (; kk < de[t]; ++kk) {
-                const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
-                const T w = A.dn_val[kk];
+                for (; kk < de[t]; ++kk) {
+                    const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
+                    const T w = A.dn_val[kk];
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v.v[rr];
+                    for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v.v[rr];
+                }
             }
             if (b0 + t < cd) {
                 const T o[4] = {acc[i][0][t], acc[i][1][t], acc[i][2][t], acc[i][3][t]};
@@ -713,9 +670,169 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const in
     }
 }
 
-// ---- fused ------------------------------------------------------------
+// ---- row-band pass of the two-pass schedule: y += V H_dn^T ---------------
+// Work item (band j, column group g): rows [R j, R j + R) of the output
+// columns b = g BS NC + lane + BS i (i < NC), accumulated in registers from
+// their value in y (the column pass's diagonal + H_up term), so each element
+// sees the operations of the one-pass kernels in the same order.  The band of
+// V is staged chunk by chunk in LDS, a slot of R elements (one 16- or 32-byte
+// segment of a column) per column, and the H_dn entries of every output column
+// whose column lies in the chunk are added from LDS (the chunk tables of H_dn:
+// entry k of row b at off[b >> 6] 64 + 64 k + (b & 63)).  The 128 / (R s)
+// bands that share a 128-byte line of every column run back to back on one
+// XCD, so its L2 merges their segments of V, y and v_prev.  EPI: the first
+// Lanczos update as in k_kron_quad, with one partial per work item (its lanes
+// in a fixed order) at apart[j ngroups + g].
+template <typename T>
+struct BandArgs {
+    const int32_t *__restrict__ off;
+    const int64_t *__restrict__ base;
+    const uint32_t *__restrict__ ell;
+    const T *__restrict__ code_v;
+    int nchunks, chunk, nslices;
+    int nbands, ngroups;
+};
+
+template <typename T, int R, int NC, int BS, bool EPI>
+__global__ __launch_bounds__(BS) void k_kron_dn_band(MvArgs<T> A, BandArgs<T> B, LzEpi<T> E)
+{
+    constexpr int PN = P16<T>::N;                     // elements per 16-byte piece
+    constexpr int PPS = R / PN;                       // pieces per slot
+    constexpr int LB = 128 / (R * (int)sizeof(T));    // bands per 128-byte line
+    static_assert(PPS >= 1 && PPS * PN == R, "a slot is whole 16-byte pieces");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *tab = reinterpret_cast<T *>(smem_raw);
+    T *xs = tab + 256;
+    double *wpart = reinterpret_cast<double *>(xs + (size_t)B.chunk * R);  // EPI: one partial per wavefront
+    const int xcd = (int)(blockIdx.x & 7), r = (int)(blockIdx.x >> 3);
+    const int per = LB * B.ngroups;
+    const int band = ((r / per) * 8 + xcd) * LB + (r % per) / B.ngroups;
+    const int group = (r % per) % B.ngroups;
+    if (band >= B.nbands) return;
+    const int cu = A.cu, cd = A.cd;
+    const int64_t cu64 = cu;
+    const int a0 = band * R;
+    const int npv = min(PPS, (cu - a0) / PN);  // whole pieces in the band (count_up % 4 == 0)
+    const int gb0 = group * (BS * NC);
+    for (int i = threadIdx.x; i < 256; i += BS) tab[i] = B.code_v[i];
+    T acc[NC][R];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const int b = gb0 + (int)threadIdx.x + i * BS;
+#pragma unroll
+        for (int j = 0; j < PPS; ++j) {
+            P16<T> v = {};
+            if (b < cd && j < npv) v = ld16(A.y + (int64_t)b * cu64 + a0 + j * PN);
+#pragma unroll
+            for (int e = 0; e < PN; ++e) acc[i][j * PN + e] = v.v[e];
+        }
+    }
+    for (int p = 0; p < B.nchunks; ++p) {
+        const int c0 = p * B.chunk;
+        const int nc = min(B.chunk, cd - c0);
+        __syncthreads();  // the previous chunk's gathers are done
+        // four 16-byte loads in flight per lane before their LDS stores
+        for (int i0 = threadIdx.x; i0 < nc * PPS; i0 += 4 * BS) {
+            P16<T> v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i0 + u * BS;
+                const int c = idx / PPS, j = idx - c * PPS;
+                v[u] = P16<T>{};
+                if (idx < nc * PPS && j < npv) v[u] = ld16(A.x + (int64_t)(c0 + c) * cu64 + a0 + j * PN);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i0 + u * BS;
+                const int c = idx / PPS, j = idx - c * PPS;
+                if (idx < nc * PPS) st16(xs + c * R + j * PN, v[u]);
+            }
+        }
+        __syncthreads();
+        const int32_t *__restrict__ off = B.off + (int64_t)p * (B.nslices + 1);
+        const uint32_t *__restrict__ ell = B.ell + B.base[p];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const int b = gb0 + (int)threadIdx.x + i * BS;
+            if (b >= cd) continue;
+            const int sl = b >> 6;
+            const uint32_t *__restrict__ e = ell + (int64_t)off[sl] * 64 + (b & 63);
+            const int len = off[sl + 1] - off[sl];
+            int k = 0;
+            for (; k + 2 <= len; k += 2) {
+                const uint32_t e0 = e[64 * k], e1 = e[64 * (k + 1)];
+                const T h0 = tab[e0 >> 24], h1 = tab[e1 >> 24];
+                const T *x0 = xs + (e0 & 0xFFFFFFu) * R, *x1 = xs + (e1 & 0xFFFFFFu) * R;
+                P16<T> v0[PPS], v1[PPS];
+#pragma unroll
+                for (int j = 0; j < PPS; ++j) {
+                    v0[j] = ld16(x0 + j * PN);
+                    v1[j] = ld16(x1 + j * PN);
+                }
+#pragma unroll
+                for (int j = 0; j < PPS; ++j)
+#pragma unroll
+                    for (int u = 0; u < PN; ++u) acc[i][j * PN + u] += h0 * v0[j].v[u];
+#pragma unroll
+                for (int j = 0; j < PPS; ++j)
+#pragma unroll
+                    for (int u = 0; u < PN; ++u) acc[i][j * PN + u] += h1 * v1[j].v[u];
+            }
+            if (k < len) {
+                const uint32_t e0 = e[64 * k];
+                const T h0 = tab[e0 >> 24];
+                const T *x0 = xs + (e0 & 0xFFFFFFu) * R;
+#pragma unroll
+                for (int j = 0; j < PPS; ++j) {
+                    const P16<T> v0 = ld16(x0 + j * PN);
+#pragma unroll
+                    for (int u = 0; u < PN; ++u) acc[i][j * PN + u] += h0 * v0.v[u];
+                }
+            }
+        }
+    }
+    double part = 0.0;
+    EpiCoef<T> ec;
+    if (EPI) ec = epi_coef(E);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const int b = gb0 + (int)threadIdx.x + i * BS;
+        if (b >= cd) continue;
+        const int64_t o0 = (int64_t)b * cu64 + a0;
+#pragma unroll
+        for (int j = 0; j < npv && j < PPS; ++j) {
+            P16<T> o;
+#pragma unroll
+            for (int u = 0; u < PN; ++u) o.v[u] = acc[i][j * PN + u];
+            if (EPI) {
+                P16<T> vp = {};
+                if (E.vprev) vp = ld16(E.vprev + o0 + j * PN);
+                const P16<T> xv = ld16(A.x + o0 + j * PN);
+#pragma unroll
+                for (int u = 0; u < PN; ++u) {
+                    o.v[u] = epi_w(E, ec, o.v[u], vp.v[u]);
+                    part += (double)o.v[u] * (double)xv.v[u];
+                }
+            }
+            st16(A.y + o0 + j * PN, o);
+        }
+    }
+    if (EPI) {
+        part = quad_wave_sum(part);
+        if ((threadIdx.x & 63) == 0) wpart[threadIdx.x >> 6] = part;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < BS / 64; ++w) sum += wpart[w];
+            E.apart[(int64_t)band * B.ngroups + group] = sum;
+        }
+    }
+}
+
+// ---- one row per lane (count_up % 4 != 0, or unaligned vectors) ------------
 // Each lane owns R rows (a, a + BS, ...) at once so the H_dn neighbour reads
-// of all R rows are in flight together.
+// of all R rows are in flight together.  CF: compact entries (else packed
+// {column, value} entries, for sectors without the compact format).
 template <typename T, int TB, int BS, int R, bool CF>
 __global__ __launch_bounds__(BS) void k_kron_fused(MvArgs<T> A, const int32_t *__restrict__ sl_off,
                                                    const Pk<T> *__restrict__ ell, const uint32_t *__restrict__ ellc,
@@ -788,203 +905,6 @@ __global__ __launch_bounds__(BS) void k_kron_fused(MvArgs<T> A, const int32_t *_
     }
 }
 
-// ---- row-chunked fused product (columns larger than the LDS) -------------
-// One workgroup per output column b.  The column is processed in P row
-// chunks: phase p stages V[chunk p, b] in LDS and adds, for every row, the
-// H_up entries whose column lies in chunk p; phase 0 also adds the diagonal and
-// the H_dn term.  Y[:, b] is written in phase 0 and updated in place by the
-// later phases of the same workgroup (the column is still in L2 by then).
-template <typename T, int BS, int R>
-__global__ __launch_bounds__(BS) void k_kron_chunked(MvArgs<T> A, const int32_t *__restrict__ ch_off,
-                                                     const int64_t *__restrict__ ch_base,
-                                                     const uint32_t *__restrict__ ch_ell, const T *__restrict__ code_v,
-                                                     int nchunks, int chunk_rows, int nslices)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *tab = reinterpret_cast<T *>(smem_raw);
-    T *xs = tab + 256;
-    const int tile = xcd_tile(A.cd);
-    if (tile < 0) return;
-    const int cu = A.cu;
-    const int b = tile;
-    const int64_t cu64 = cu;
-    const T *__restrict__ xb = A.x + (int64_t)b * cu;
-    T *yb = A.y + (int64_t)b * cu;
-    for (int i = threadIdx.x; i < 256; i += BS) tab[i] = code_v[i];
-    const int ds = A.dn_rp[b], de = A.dn_rp[b + 1];
-    const uint32_t dnb = A.dn_basis[b];
-    const T edn = A.e_dn[b];
-    const int lane = threadIdx.x & 63;
-    for (int p = 0; p < nchunks; ++p) {
-        const int r0 = p * chunk_rows;
-        const int r1 = min(cu, r0 + chunk_rows);
-        __syncthreads();  // previous phase done with xs
-        for (int i = r0 + threadIdx.x; i < r1; i += BS) xs[i - r0] = xb[i];
-        __syncthreads();
-        const int32_t *off = ch_off + (int64_t)p * (nslices + 1);
-        const uint32_t *ell = ch_ell + ch_base[p];
-        for (int a0 = threadIdx.x; a0 < cu; a0 += BS * R) {
-            T acc[R][1];
-            int as[R];
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const int a = min(a0 + j * BS, cu - 1);
-                as[j] = a;
-                if (p == 0) acc[j][0] = (diag_u(A, A.up_basis[a] & dnb) + A.e_up[a] + edn) * xb[a];
-                else acc[j][0] = yb[a];
-                const int s = a >> 6;
-                up_term_c<T, 1>(acc[j], xs, tab, ell, off[s] * 64 + lane, off[s + 1] - off[s]);
-            }
-            if (p == 0) {
-                int k = ds;
-                for (; k + 4 <= de; k += 4) {
-                    T y[4][R];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int j = 0; j < R; ++j) y[u][j] = A.x[(int64_t)A.dn_col[k + u] * cu64 + as[j]];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int j = 0; j < R; ++j) acc[j][0] += A.dn_val[k + u] * y[u][j];
-                }
-                for (; k < de; ++k)
-#pragma unroll
-                    for (int j = 0; j < R; ++j) acc[j][0] += A.dn_val[k] * A.x[(int64_t)A.dn_col[k] * cu64 + as[j]];
-            }
-#pragma unroll
-            for (int j = 0; j < R; ++j)
-                if (a0 + j * BS < cu) yb[a0 + j * BS] = acc[j][0];
-        }
-    }
-}
-
-// ---- two-pass, pass 1: Z = V H_dn^T on XCD-cooperative row tiles --------
-// A tile is TA = 128 B / sizeof(T) rows (one cache line per column), so two
-// tiles in flight stay well inside one XCD's 4 MB L2 for count_dn ~ 10^4.  A
-// wavefront covers 64 / TA output columns of the tile; each group of TA lanes
-// walks its own row of H_dn with 8 neighbour reads in flight.
-template <typename T, int BS, bool NT>
-__global__ __launch_bounds__(BS) void k_kron_dn_tiles(MvArgs<T> A, T *z, int ntiles, int per_xcd)
-{
-    constexpr int TA = 128 / (int)sizeof(T);
-    constexpr int CPW = 64 / TA;                // output columns per wavefront
-    constexpr int CPB = (BS / 64) * CPW;        // output columns per workgroup step
-    const int64_t cu = A.cu;
-    const int cd = A.cd;
-    const int xcd = blockIdx.x & 7;
-    const int r = blockIdx.x >> 3;  // rank of this workgroup within its XCD
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int sub = lane / TA, row = lane % TA;
-    const int cols_per = (cd + per_xcd - 1) / per_xcd;
-    const int c0 = r * cols_per, c1 = min(cd, c0 + cols_per);
-    for (int tile = xcd; tile < ntiles; tile += 8) {
-        const int a = tile * TA + row;
-        const bool live = a < cu;
-        const T *__restrict__ xa = A.x + (live ? a : 0);
-        for (int b = c0 + wave * CPW + sub; b < c1; b += CPB) {
-            const int ks = A.dn_rp[b], ke = A.dn_rp[b + 1];
-            T acc = (T)0;
-            int k = ks;
-            for (; k + 8 <= ke; k += 8) {
-                T y[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) y[u] = xa[(int64_t)A.dn_col[k + u] * cu];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) acc += A.dn_val[k + u] * y[u];
-            }
-            for (; k < ke; ++k) acc += A.dn_val[k] * xa[(int64_t)A.dn_col[k] * cu];
-            if (live) {
-                if (NT) __builtin_nontemporal_store(acc, z + (int64_t)b * cu + a);
-                else z[(int64_t)b * cu + a] = acc;
-            }
-        }
-    }
-}
-
-// Pass 1 in dispatch order: workgroup g takes (row tile, column chunk) with
-// the tiles of XCD g mod 8 in increasing order and the chunks of one tile
-// consecutive.  Workgroups are dispatched in index order, so the ones resident
-// on an XCD at any moment share one or two row tiles (TA rows of every
-// column), which stay in that XCD's L2 while the neighbour reads hit them.
-template <typename T, int BS, bool NT>
-__global__ __launch_bounds__(BS) void k_kron_dn_otiles(MvArgs<T> A, T *z, int ntiles, int nchunks, int chunk_cols)
-{
-    constexpr int TA = 128 / (int)sizeof(T);
-    constexpr int CPW = 64 / TA;
-    constexpr int CPB = (BS / 64) * CPW;
-    const int64_t cu = A.cu;
-    const int cd = A.cd;
-    const int xcd = blockIdx.x & 7;
-    const int r = blockIdx.x >> 3;
-    const int tile = (r / nchunks) * 8 + xcd;
-    if (tile >= ntiles) return;
-    const int chunk = r - (r / nchunks) * nchunks;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int sub = lane / TA, row = lane % TA;
-    const int c0 = chunk * chunk_cols, c1 = min(cd, c0 + chunk_cols);
-    const int a = tile * TA + row;
-    const bool live = a < cu;
-    const T *__restrict__ xa = A.x + (live ? a : 0);
-    for (int b = c0 + wave * CPW + sub; b < c1; b += CPB) {
-        const int ks = A.dn_rp[b], ke = A.dn_rp[b + 1];
-        T acc = (T)0;
-        int k = ks;
-        for (; k + 8 <= ke; k += 8) {
-            T y[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) y[u] = xa[(int64_t)A.dn_col[k + u] * cu];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc += A.dn_val[k + u] * y[u];
-        }
-        for (; k < ke; ++k) acc += A.dn_val[k] * xa[(int64_t)A.dn_col[k] * cu];
-        if (live) {
-            if (NT) __builtin_nontemporal_store(acc, z + (int64_t)b * cu + a);
-            else z[(int64_t)b * cu + a] = acc;
-        }
-    }
-}
-
-// ---- two-pass, pass 2: Y = Z + H_up V + D o V on LDS column panels --------
-template <typename T, int TB, int BS>
-__global__ __launch_bounds__(BS) void k_kron_up_panels(MvArgs<T> A, const T *z, const int32_t *__restrict__ sl_off,
-                                                       const Pk<T> *__restrict__ ell, int ntiles)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *xs = reinterpret_cast<T *>(smem_raw);
-    const int tile = xcd_tile(ntiles);
-    if (tile < 0) return;
-    const int cu = A.cu, cd = A.cd;
-    const int b0 = tile * TB;
-    stage_columns<T, TB>(A, xs, b0, BS);
-    __syncthreads();
-    uint32_t dnb[TB];
-    T edn[TB];
-#pragma unroll
-    for (int t = 0; t < TB; ++t) {
-        const int b = min(b0 + t, cd - 1);
-        dnb[t] = A.dn_basis[b];
-        edn[t] = A.e_dn[b];
-    }
-    const int lane = threadIdx.x & 63;
-    for (int a = threadIdx.x; a < cu; a += BS) {
-        const uint32_t ua = A.up_basis[a];
-        const T eua = A.e_up[a];
-        const Vec<T, TB> xa = *reinterpret_cast<const Vec<T, TB> *>(xs + a * TB);
-        T acc[TB];
-#pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            const int b = min(b0 + t, cd - 1);
-            acc[t] = z[(int64_t)b * cu + a] + (diag_u(A, ua & dnb[t]) + eua + edn[t]) * xa.v[t];
-        }
-        const int s = a >> 6;
-        up_term<T, TB>(acc, xs, ell, sl_off[s] * 64 + lane, sl_off[s + 1] - sl_off[s]);
-#pragma unroll
-        for (int t = 0; t < TB; ++t)
-            if (b0 + t < cd) A.y[(int64_t)(b0 + t) * cu + a] = acc[t];
-    }
-}
-
 // ---- fallback: CSR rows, H_up gathered from global memory ----------------
 template <typename T, int BS>
 __global__ __launch_bounds__(BS) void k_kron_csr(MvArgs<T> A)
@@ -998,7 +918,7 @@ __global__ __launch_bounds__(BS) void k_kron_csr(MvArgs<T> A)
     for (int a = threadIdx.x; a < cu; a += BS) {
         T acc = (diag_u(A, A.up_basis[a] & dnb) + A.e_up[a] + edn) * xb[a];
         for (int k = A.up_rp[a]; k < A.up_rp[a + 1]; ++k) acc += A.up_val[k] * xb[A.up_col[k]];
-        acc += dn_term(A, ds, de, A.x + a);
+        dn_term(acc, A, ds, de, A.x + a);
         A.y[(int64_t)b * cu + a] = acc;
     }
 }
@@ -1012,6 +932,10 @@ __global__ void k_diag(MvArgs<T> A, T *__restrict__ out)
         out[i] = diag_u(A, A.up_basis[a] & A.dn_basis[b]) + A.e_up[a] + A.e_dn[b];
     }
 }
+
+// ========================================================================
+// Host side
+// ========================================================================
 
 template <typename T>
 MvArgs<T> make_args(const hub_sector *s, const void *x, void *y)
@@ -1053,217 +977,502 @@ MvArgs<T> make_args(const hub_sector *s, const void *x, void *y)
 }
 
 template <typename T>
+const T *code_table(const SpinTables &S)
+{
+    if constexpr (sizeof(T) == 8) return (const T *)S.code_v64;
+    else return (const T *)S.code_v32;
+}
+
+template <typename T>
 const Pk<T> *ell_of(const SpinTables &U)
 {
     if constexpr (sizeof(T) == 8) return (const Pk<T> *)U.ell_pk64;
     else return (const Pk<T> *)U.ell_pk32;
 }
 
+// Dynamic LDS beyond 64 KB has to be allowed per kernel (once per process).
 template <typename K>
 hub_status allow_lds(K kernel, size_t bytes)
 {
+    static std::mutex mu;
+    static std::map<const void *, size_t> done;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = done.find((const void *)kernel);
+    if (it != done.end() && it->second >= bytes) return HUB_OK;
     HUB_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    done[(const void *)kernel] = bytes;
     return HUB_OK;
 }
 
+template <typename T>
+LzEpi<T> no_epi()
+{
+    return LzEpi<T>{nullptr, nullptr, nullptr, 0, nullptr, 0};
+}
+
+// ---- geometry -------------------------------------------------------------
+
+constexpr int kF64 = 0, kF32 = 1;
+
+template <typename T>
+constexpr int dix()
+{
+    return sizeof(T) == 8 ? kF64 : kF32;
+}
+
+// A sector whose product can use the 16-byte-access kernels.
+bool quad_ok(const hub_sector *s)
+{
+    return !s->k0 && s->spin[0].ell_c32 && s->spin[1].ell_c32 && (s->spin[0].count % 4) == 0;
+}
+
+template <typename T>
+bool column_fits(const hub_sector *s, int tb, bool epi)
+{
+    const int64_t cu = s->spin[0].count;
+    const size_t g = (size_t)((cu / 4 + 63) / 64);
+    return (size_t)(cu * tb + 256) * sizeof(T) + (epi ? (size_t)tb * g * sizeof(double) : 0) <= s->lds_max;
+}
+
+// balanced chunks of at most `maxc` (a multiple of 64) for `n` columns
+int balanced_chunk(int64_t n, int64_t maxc)
+{
+    if (maxc < 64) return 0;
+    const int64_t nch = (n + maxc - 1) / maxc;
+    const int64_t c = (n + nch - 1) / nch;
+    return (int)std::min<int64_t>(maxc, (c + 63) / 64 * 64);
+}
+
+// rows per staged chunk of the row-chunked column pass for TB columns
+template <typename T>
+int chunked_rows(const hub_sector *s, int tb)
+{
+    const int64_t maxr = ((int64_t)(s->lds_max / sizeof(T)) - 256) / tb / 64 * 64;
+    return balanced_chunk(s->spin[0].count, maxr);
+}
+
+// Row-band pass geometry: R rows (slots of 16 or 32 bytes), BS lanes, at most
+// kBandRegs accumulator registers per lane (NC R s / 4 <= 48), so that 16
+// wavefronts per CU fit in the register file without spills.
+constexpr int kBandRegs = 48;
+
+struct BandGeom {
+    int nc = 0, nbands = 0, ngroups = 0, chunk = 0;
+};
+
+template <typename T>
+bool band_geom(const hub_sector *s, int R, int bs, int chunk_force, BandGeom &g)
+{
+    const int64_t cu = s->spin[0].count, cd = s->spin[1].count;
+    if (R * (int)sizeof(T) != 16 && R * (int)sizeof(T) != 32) return false;
+    if (bs != 512 && bs != 1024) return false;
+    const int ncmax = kBandRegs * 4 / (R * (int)sizeof(T));  // 6 for 32-byte slots, 12 for 16-byte
+    const int64_t ng = (cd + (int64_t)bs * ncmax - 1) / ((int64_t)bs * ncmax);
+    const int64_t need = (cd + (int64_t)bs * ng - 1) / ((int64_t)bs * ng);
+    // instantiated column counts per lane: 4 or ncmax
+    g.nc = need <= 4 ? 4 : ncmax;
+    g.ngroups = (int)((cd + (int64_t)bs * g.nc - 1) / ((int64_t)bs * g.nc));
+    g.nbands = (int)((cu + R - 1) / R);
+    // LDS: code table, slots, one partial per wavefront; two workgroups per CU at 512 lanes
+    const int64_t avail = (int64_t)(s->lds_max * bs / 1024) - 256 * (int64_t)sizeof(T) - 16 * 8;
+    const int64_t maxc = avail / (R * (int64_t)sizeof(T)) / 64 * 64;
+    if (chunk_force > 0) {
+        if (chunk_force > maxc && chunk_force > 64) return false;
+        g.chunk = chunk_force;
+    } else {
+        g.chunk = balanced_chunk(cd, maxc);
+    }
+    return g.chunk > 0 && (int64_t)g.nbands * g.ngroups < ((int64_t)1 << 31);
+}
+
+// ---- launchers --------------------------------------------------------------
+
+template <typename T, int TB, int BS, bool XC, bool EPI, bool DN>
+hub_status launch_quad_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const LzEpi<T> &E)
+{
+    const SpinTables &U = s->spin[0];
+    const int ntiles = (A.cd + TB - 1) / TB;
+    const unsigned grid = XC ? 8u * (unsigned)((ntiles + 7) / 8) : (unsigned)ntiles;
+    const size_t lds = (size_t)(A.cu * TB + 256) * sizeof(T) + (EPI ? (size_t)TB * E.G * sizeof(double) : 0);
+    if (lds > s->lds_max) {
+        set_error("column product: tile does not fit in LDS");
+        return HUB_ERR_UNSUPPORTED;
+    }
+    HUB_TRY(allow_lds(k_kron_quad<T, TB, BS, XC, EPI, DN>, s->lds_max));
+    hipLaunchKernelGGL((k_kron_quad<T, TB, BS, XC, EPI, DN>), dim3(grid), dim3(BS), lds, st, A, U.sl_off, U.ell_c32,
+                       code_table<T>(U), ntiles, E);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+// column product of shape (tb in 1..3, bs in {512, 1024}, xc); E: fused
+// Lanczos update (one pass only) or NULL; dn: include the H_dn term
+template <typename T>
+hub_status launch_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, int bs, int xc,
+                       const LzEpi<T> *E, bool dn)
+{
+    const LzEpi<T> ne = no_epi<T>();
+#define HUB_QUAD(TBV, BSV, XCV)                                                                        \
+    if (tb == TBV && bs == BSV && xc == XCV) {                                                         \
+        if (!dn) return launch_quad_k<T, TBV, BSV, XCV, false, false>(s, A, st, ne);                  \
+        if (E) return launch_quad_k<T, TBV, BSV, XCV, true, true>(s, A, st, *E);                      \
+        return launch_quad_k<T, TBV, BSV, XCV, false, true>(s, A, st, ne);                            \
+    }
+    HUB_QUAD(1, 512, 0) HUB_QUAD(1, 512, 1) HUB_QUAD(1, 1024, 0) HUB_QUAD(1, 1024, 1)
+    HUB_QUAD(2, 512, 0) HUB_QUAD(2, 512, 1) HUB_QUAD(2, 1024, 0) HUB_QUAD(2, 1024, 1)
+    HUB_QUAD(3, 512, 0) HUB_QUAD(3, 512, 1) HUB_QUAD(3, 1024, 0) HUB_QUAD(3, 1024, 1)
+#undef HUB_QUAD
+    set_error("unsupported column product shape");
+    return HUB_ERR_UNSUPPORTED;
+}
+
+template <typename T, int QPL, int TB, bool DN, bool TM>
+hub_status launch_chunked_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const ChunkSet &C)
+{
+    constexpr int BSC = 1024;
+    const SpinTables &U = s->spin[0];
+    const size_t lds = ((size_t)C.rows * TB + 256) * sizeof(T);
+    if (lds > s->lds_max) {
+        set_error("row-chunked product: chunk does not fit in LDS");
+        return HUB_ERR_UNSUPPORTED;
+    }
+    const int nq = (int)(A.cu >> 2);
+    const int P = (nq + BSC * QPL - 1) / (BSC * QPL);
+    const int ntiles = (A.cd + TB - 1) / TB;
+    HUB_TRY(allow_lds(k_kron_chunked_parts<T, BSC, QPL, TB, DN, TM>, s->lds_max));
+    const unsigned grid = 8u * (unsigned)P * (unsigned)((ntiles + 7) / 8);
+    hipLaunchKernelGGL((k_kron_chunked_parts<T, BSC, QPL, TB, DN, TM>), dim3(grid), dim3(BSC), lds, st, A, C.off,
+                       C.base, C.ell, code_table<T>(U), C.n, C.rows, (int)U.nslices, P);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+// the row-chunked shapes: (TB, QPL) with at most 64 FP32 / 32 FP64 accumulators
+template <typename T>
+bool chunked_shape_ok(int tb, int qpl)
+{
+    if (tb != 1 && tb != 2 && tb != 4) return false;
+    if (qpl != 4 && qpl != 8) return false;
+    return tb * qpl <= (sizeof(T) == 8 ? 8 : 16);
+}
+
+template <typename T>
+hub_status launch_chunked(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, int qpl, int tm,
+                          bool dn, const ChunkSet &C)
+{
+#define HUB_CH(TBV, QV)                                                                                    \
+    if (tb == TBV && qpl == QV) {                                                                          \
+        if (dn) return launch_chunked_k<T, QV, TBV, true, false>(s, A, st, C);                             \
+        if (tm) return launch_chunked_k<T, QV, TBV, false, true>(s, A, st, C);                             \
+        return launch_chunked_k<T, QV, TBV, false, false>(s, A, st, C);                                    \
+    }
+    HUB_CH(1, 4) HUB_CH(1, 8) HUB_CH(2, 4)
+    if constexpr (sizeof(T) == 4) {
+        HUB_CH(2, 8) HUB_CH(4, 4)
+    }
+#undef HUB_CH
+    set_error("unsupported row-chunked product shape");
+    return HUB_ERR_UNSUPPORTED;
+}
+
+template <typename T, int R, int NC, int BS, bool EPI>
+hub_status launch_band_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const BandGeom &g,
+                         const ChunkSet &C, const LzEpi<T> &E)
+{
+    const SpinTables &D = s->spin[1];
+    const size_t lds = ((size_t)g.chunk * R + 256) * sizeof(T) + 16 * sizeof(double);
+    if (lds > s->lds_max) {
+        set_error("row-band pass: chunk does not fit in LDS");
+        return HUB_ERR_UNSUPPORTED;
+    }
+    constexpr int LB = 128 / (R * (int)sizeof(T));
+    const int64_t lines = (g.nbands + LB - 1) / LB;
+    const int64_t grid = 8 * ((lines + 7) / 8) * LB * (int64_t)g.ngroups;
+    if (grid >= ((int64_t)1 << 31)) {
+        set_error("row-band pass: too many work items");
+        return HUB_ERR_RANGE;
+    }
+    BandArgs<T> B{C.off, C.base, C.ell, code_table<T>(D), C.n, C.rows, (int)D.nslices, g.nbands, g.ngroups};
+    HUB_TRY(allow_lds(k_kron_dn_band<T, R, NC, BS, EPI>, s->lds_max));
+    hipLaunchKernelGGL((k_kron_dn_band<T, R, NC, BS, EPI>), dim3((unsigned)grid), dim3(BS), lds, st, A, B, E);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+template <typename T>
+hub_status launch_band(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int R, int bs, int chunk_force,
+                       const LzEpi<T> *E)
+{
+    BandGeom g;
+    if (!band_geom<T>(s, R, bs, chunk_force, g)) {
+        set_error("unsupported row-band pass shape");
+        return HUB_ERR_UNSUPPORTED;
+    }
+    const ChunkSet *C = nullptr;
+    HUB_TRY(chunk_set(s, HUB_SPIN_DN, g.chunk, &C, st));
+    const LzEpi<T> ne = no_epi<T>();
+    constexpr int R32 = 32 / (int)sizeof(T), R16 = 16 / (int)sizeof(T);
+#define HUB_BAND(RV, NCV, BSV)                                                                             \
+    if (R == RV && g.nc == NCV && bs == BSV) {                                                            \
+        if (E) return launch_band_k<T, RV, NCV, BSV, true>(s, A, st, g, *C, *E);                           \
+        return launch_band_k<T, RV, NCV, BSV, false>(s, A, st, g, *C, ne);                                 \
+    }
+    HUB_BAND(R32, 4, 512) HUB_BAND(R32, 6, 512) HUB_BAND(R32, 4, 1024) HUB_BAND(R32, 6, 1024)
+    HUB_BAND(R16, 4, 512) HUB_BAND(R16, 12, 512) HUB_BAND(R16, 4, 1024) HUB_BAND(R16, 12, 1024)
+#undef HUB_BAND
+    set_error("unsupported row-band pass shape");
+    return HUB_ERR_UNSUPPORTED;
+}
+
 template <typename T, int TB, int BS, int R = 4>
-hub_status launch_fused(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, bool cf)
+hub_status launch_rows(const hub_sector *s, const MvArgs<T> &A, hipStream_t st)
 {
     const SpinTables &U = s->spin[0];
     const int ntiles = (A.cd + TB - 1) / TB;
     const unsigned grid = 8u * (unsigned)((ntiles + 7) / 8);
-    if (cf && U.ell_c32) {
+    if (U.ell_c32) {
         const size_t lds = (size_t)(A.cu * TB + 256) * sizeof(T);
-        static std::atomic<bool> attr{false};
-        if (!attr) {
-            HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, true>, s->lds_max));
-            attr = true;
-        }
-        const T *cv;
-        if constexpr (sizeof(T) == 8) cv = (const T *)U.code_v64;
-        else cv = (const T *)U.code_v32;
+        HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, true>, s->lds_max));
         hipLaunchKernelGGL((k_kron_fused<T, TB, BS, R, true>), dim3(grid), dim3(BS), lds, st, A, U.sl_off,
-                           ell_of<T>(U), U.ell_c32, cv, ntiles);
+                           ell_of<T>(U), U.ell_c32, code_table<T>(U), ntiles);
         HUB_HIP(hipGetLastError());
         return HUB_OK;
     }
     const size_t lds = (size_t)A.cu * TB * sizeof(T);
-    static std::atomic<bool> attr{false};
-    if (!attr) {
-        HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, false>, s->lds_max));
-        attr = true;
-    }
+    HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, false>, s->lds_max));
     hipLaunchKernelGGL((k_kron_fused<T, TB, BS, R, false>), dim3(grid), dim3(BS), lds, st, A, U.sl_off,
                        ell_of<T>(U), (const uint32_t *)nullptr, (const T *)nullptr, ntiles);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
 
-int env_int(const char *name, int dflt)
-{
-    const char *v = getenv(name);
-    return v ? atoi(v) : dflt;
-}
-
-template <typename T, int TB, int BS>
-hub_status launch_two_pass(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int occ, int nt)
-{
-    constexpr int BSD = 256;
-    const SpinTables &U = s->spin[0];
-    const int ntiles_d = (A.cu + (128 / (int)sizeof(T)) - 1) / (128 / (int)sizeof(T));
-    const int per_xcd = (s->cu_count / 8) * occ;
-    static const int ordered = env_int("HUB_DN_ORDER", 1);
-    static const int chunk_env = env_int("HUB_DN_CH", 256);
-    if (ordered) {
-        const int chunk_cols = std::max(1, chunk_env);
-        const int nchunks = (A.cd + chunk_cols - 1) / chunk_cols;
-        const unsigned grid = 8u * (unsigned)((ntiles_d + 7) / 8) * (unsigned)nchunks;
-        if (nt)
-            hipLaunchKernelGGL((k_kron_dn_otiles<T, BSD, true>), dim3(grid), dim3(BSD), 0, st, A, A.y, ntiles_d,
-                               nchunks, chunk_cols);
-        else
-            hipLaunchKernelGGL((k_kron_dn_otiles<T, BSD, false>), dim3(grid), dim3(BSD), 0, st, A, A.y, ntiles_d,
-                               nchunks, chunk_cols);
-    } else if (nt)
-        hipLaunchKernelGGL((k_kron_dn_tiles<T, BSD, true>), dim3(8 * per_xcd), dim3(BSD), 0, st, A, A.y, ntiles_d,
-                           per_xcd);
-    else
-        hipLaunchKernelGGL((k_kron_dn_tiles<T, BSD, false>), dim3(8 * per_xcd), dim3(BSD), 0, st, A, A.y, ntiles_d,
-                           per_xcd);
-    const size_t lds = (size_t)A.cu * TB * sizeof(T);
-    static std::atomic<bool> attr{false};
-    if (!attr) {
-        HUB_TRY(allow_lds(k_kron_up_panels<T, TB, BS>, s->lds_max));
-        attr = true;
-    }
-    const int ntiles = (A.cd + TB - 1) / TB;
-    const unsigned grid = 8u * (unsigned)((ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_kron_up_panels<T, TB, BS>), dim3(grid), dim3(BS), lds, st, A, (const T *)A.y, U.sl_off,
-                       ell_of<T>(U), ntiles);
-    HUB_HIP(hipGetLastError());
-    return HUB_OK;
-}
-
-template <typename T, int TB, int BS, bool XC, bool EPI>
-hub_status launch_quad_e(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const LzEpi<T> &E)
-{
-    const SpinTables &U = s->spin[0];
-    const int ntiles = (A.cd + TB - 1) / TB;
-    const unsigned grid = XC ? 8u * (unsigned)((ntiles + 7) / 8) : (unsigned)ntiles;
-    // columns (cu % 4 == 0 keeps the FP32 case 8-byte aligned), then the group partials
-    const size_t lds = (size_t)(A.cu * TB + 256) * sizeof(T) + (EPI ? (size_t)TB * E.G * sizeof(double) : 0);
-    if (lds > s->lds_max) {
-        set_error("fused product: tile does not fit in LDS");
-        return HUB_ERR_UNSUPPORTED;
-    }
-    static std::atomic<bool> attr{false};
-    if (!attr) {
-        HUB_TRY(allow_lds(k_kron_quad<T, TB, BS, XC, EPI>, s->lds_max));
-        attr = true;
-    }
-    const T *cv;
-    if constexpr (sizeof(T) == 8) cv = (const T *)U.code_v64;
-    else cv = (const T *)U.code_v32;
-    hipLaunchKernelGGL((k_kron_quad<T, TB, BS, XC, EPI>), dim3(grid), dim3(BS), lds, st, A, U.sl_off, U.ell_c32, cv,
-                       ntiles, E);
-    HUB_HIP(hipGetLastError());
-    return HUB_OK;
-}
-
-template <typename T, int TB, int BS, bool XC>
-hub_status launch_quad_t(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const LzEpi<T> *E)
-{
-    if (E) return launch_quad_e<T, TB, BS, XC, true>(s, A, st, *E);
-    return launch_quad_e<T, TB, BS, XC, false>(s, A, st, LzEpi<T>{nullptr, nullptr, nullptr, 0, nullptr, 0});
-}
-
-// shape code: TB in 1..3, BS in {512, 1024}, XC in {0, 1}; E: fused Lanczos epilogue or NULL
+// one row per lane: two columns per workgroup when they fit in half of the LDS
 template <typename T>
-hub_status launch_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, int bs, int xc,
-                       const LzEpi<T> *E = nullptr)
+hub_status launch_rows_auto(const hub_sector *s, const MvArgs<T> &A, hipStream_t st)
 {
-#define HUB_QUAD(TBV, BSV, XCV)                                                                       \
-    if (tb == TBV && bs == BSV && xc == XCV) return launch_quad_t<T, TBV, BSV, XCV>(s, A, st, E);
-    HUB_QUAD(1, 512, 0) HUB_QUAD(1, 512, 1) HUB_QUAD(1, 1024, 0) HUB_QUAD(1, 1024, 1)
-    HUB_QUAD(2, 512, 0) HUB_QUAD(2, 512, 1) HUB_QUAD(2, 1024, 0) HUB_QUAD(2, 1024, 1)
-    HUB_QUAD(3, 512, 0) HUB_QUAD(3, 512, 1) HUB_QUAD(3, 1024, 0) HUB_QUAD(3, 1024, 1)
-#undef HUB_QUAD
-    set_error("untuned product shape");
+    const size_t col = (size_t)A.cu * sizeof(T), extra = 256 * sizeof(T);
+    if (2 * col + extra <= s->lds_max / 2) return launch_rows<T, 2, 1024, 2>(s, A, st);
+    if (col + extra <= s->lds_max) return launch_rows<T, 1, 1024, 4>(s, A, st);
+    hipLaunchKernelGGL((k_kron_csr<T, 512>), dim3((unsigned)A.cd), dim3(512), 0, st, A);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+// Run schedule q (fam, shapes); E: the fused Lanczos update (q must support it)
+template <typename T>
+hub_status launch_sched(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const Sched &q, const LzEpi<T> *E)
+{
+    switch (q.fam) {
+    case HUB_SCHED_COLUMNS:
+        if (q.br > 0) {
+            HUB_TRY(launch_quad<T>(s, A, st, q.tb, q.bs, q.xc, nullptr, false));
+            return launch_band<T>(s, A, st, q.br, q.bbs, q.bch, E);
+        }
+        return launch_quad<T>(s, A, st, q.tb, q.bs, q.xc, E, true);
+    case HUB_SCHED_CHUNKED: {
+        if (E && q.br <= 0) {
+            set_error("the one-pass row-chunked product has no fused Lanczos update");
+            return HUB_ERR_UNSUPPORTED;
+        }
+        const ChunkSet *C = nullptr;
+        HUB_TRY(chunk_set(s, HUB_SPIN_UP, q.crows > 0 ? q.crows : chunked_rows<T>(s, q.tb), &C, st));
+        if (q.br > 0) {
+            HUB_TRY(launch_chunked<T>(s, A, st, q.tb, q.qpl, q.xc, false, *C));
+            return launch_band<T>(s, A, st, q.br, q.bbs, q.bch, E);
+        }
+        return launch_chunked<T>(s, A, st, q.tb, q.qpl, 0, true, *C);
+    }
+    case HUB_SCHED_ROWS:
+        if (!E) return launch_rows_auto<T>(s, A, st);
+        break;
+    case HUB_SCHED_CSR:
+        if (!E) {
+            hipLaunchKernelGGL((k_kron_csr<T, 512>), dim3((unsigned)A.cd), dim3(512), 0, st, A);
+            HUB_HIP(hipGetLastError());
+            return HUB_OK;
+        }
+        break;
+    default:
+        break;
+    }
+    set_error("product schedule cannot run here");
     return HUB_ERR_UNSUPPORTED;
 }
 
-// First product of a dtype on a sector: time every shape whose columns fit in
-// the LDS (1 warm-up + 5 timed launches on the caller's x and y; every shape
-// computes the same values in the same order) and keep the fastest; a later
-// candidate must win by 3 % so that timing noise rarely changes the pick.
-// Times every shape that fits, in two interleaved rounds of five launches,
-// and keeps the one with the smallest time (each shape's better round).  epi: the shapes are timed as the
-// product fused with the first Lanczos update, whose ranking differs from the
-// plain product's (on the ring M=14, FP32 with two columns per workgroup:
-// 57 vs 55 us plain but 90 vs 75 us fused for 1024 vs 512 lanes); the epilogue
-// then reads x as v_prev with beta = 0 and writes its partials to apart
-// (count_dn doubles), all overwritten by the caller's own launch.
-template <typename T>
-hub_status tune_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, QuadShape &out, bool epi,
-                     double *apart)
+// ---- tuner ----------------------------------------------------------------
+
+// Times each candidate launch in two interleaved rounds (one warm-up launch,
+// then 5 timed launches, or 2 when one launch takes over 4 ms) and returns the
+// index of the fastest (its better round), with its time in ms.
+template <typename F>
+hub_status time_candidates(hipStream_t st, int n, F launch, int &best, float &best_ms)
 {
     hipEvent_t e0, e1;
     HUB_HIP(hipEventCreate(&e0));
     HUB_HIP(hipEventCreate(&e1));
     struct Ev {
         hipEvent_t a, b;
-        ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+        ~Ev()
+        {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
     } ev{e0, e1};
-    const int G = (int)(((A.cu >> 2) + 63) / 64);
+    std::vector<float> ms((size_t)n, 1e30f);
+    for (int round = 0; round < 2; ++round)
+        for (int c = 0; c < n; ++c) {
+            HUB_HIP(hipEventRecord(e0, st));
+            HUB_TRY(launch(c));
+            HUB_HIP(hipEventRecord(e1, st));
+            HUB_HIP(hipEventSynchronize(e1));
+            float one = 0.f;
+            HUB_HIP(hipEventElapsedTime(&one, e0, e1));
+            const int reps = one > 4.0f ? 2 : 5;
+            HUB_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) HUB_TRY(launch(c));
+            HUB_HIP(hipEventRecord(e1, st));
+            HUB_HIP(hipEventSynchronize(e1));
+            HUB_HIP(hipEventElapsedTime(&one, e0, e1));
+            ms[(size_t)c] = std::min(ms[(size_t)c], one / (float)reps);
+        }
+    best = (int)(std::min_element(ms.begin(), ms.end()) - ms.begin());
+    best_ms = ms[(size_t)best];
+    return HUB_OK;
+}
+
+// Candidate column passes of a sector (the part before the H_dn term).
+template <typename T>
+std::vector<Sched> column_candidates(const hub_sector *s, bool dn, bool epi)
+{
+    std::vector<Sched> v;
+    if (column_fits<T>(s, 1, epi && dn)) {
+        for (int tb = 1; tb <= 3; ++tb) {
+            if (!column_fits<T>(s, tb, epi && dn)) break;
+            for (int bs : {512, 1024})
+                for (int xc : {0, 1}) {
+                    Sched c;
+                    c.fam = HUB_SCHED_COLUMNS;
+                    c.tb = tb;
+                    c.bs = bs;
+                    c.xc = xc;
+                    v.push_back(c);
+                }
+        }
+        return v;
+    }
+    if (epi && dn) return v;  // the one-pass row-chunked product has no epilogue
+    for (int tb : {1, 2, 4})
+        for (int qpl : {4, 8})
+            for (int tm : {0, 1}) {
+                if (!chunked_shape_ok<T>(tb, qpl)) continue;
+                if (dn && (qpl != 4 || tm != 0)) continue;  // one pass: the measured part-major layout
+                if (chunked_rows<T>(s, tb) <= 0) continue;
+                Sched c;
+                c.fam = HUB_SCHED_CHUNKED;
+                c.tb = tb;
+                c.qpl = qpl;
+                c.xc = tm;
+                c.bs = 1024;
+                c.crows = chunked_rows<T>(s, tb);
+                v.push_back(c);
+            }
+    return v;
+}
+
+template <typename T>
+std::vector<Sched> band_candidates(const hub_sector *s, bool epi)
+{
+    std::vector<Sched> v;
+    for (int R : {32 / (int)sizeof(T), 16 / (int)sizeof(T)})
+        for (int bs : {512, 1024}) {
+            BandGeom g;
+            if (!band_geom<T>(s, R, bs, 0, g)) continue;
+            // the fused update's partials are summed inside the update kernel: at most 65536
+            if (epi && (int64_t)g.nbands * g.ngroups > 65536) continue;
+            Sched c;
+            c.br = R;
+            c.bbs = bs;
+            c.bch = g.chunk;
+            v.push_back(c);
+        }
+    return v;
+}
+
+// Tune the product (epi = false) or the product fused with the Lanczos update
+// (epi = true, apart: its partials buffer) on the caller's x and y: the
+// one-pass schedules and the two-pass ones (best column pass + best row-band
+// pass, each timed on its own).  The epilogue's timing launches read x as
+// v_prev with beta = 0.
+template <typename T>
+hub_status tune(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, bool epi, double *apart, Sched &out)
+{
     double *zero = nullptr;
     struct Buf {
         double *p = nullptr;
         ~Buf() { (void)hipFree(p); }
     } zb;
-    LzEpi<T> E{};
+    LzEpi<T> E = no_epi<T>();
     if (epi) {
         HUB_HIP(hipMalloc((void **)&zero, sizeof(double)));
         zb.p = zero;
         HUB_HIP(hipMemsetAsync(zero, 0, sizeof(double), st));
-        E = LzEpi<T>{A.x, zero, apart, G, nullptr, 0};
+        E = LzEpi<T>{A.x, zero, apart, (int)(((A.cu >> 2) + 63) / 64), nullptr, 0};
     }
-    std::vector<QuadShape> cand;
-    for (int tb = 1; tb <= 3; ++tb) {
-        const size_t lds = (size_t)(A.cu * tb + 256) * sizeof(T) + (epi ? (size_t)tb * G * sizeof(double) : 0);
-        if (lds > s->lds_max) break;
-        for (int bs : {512, 1024})
-            for (int xc : {0, 1}) {
-                QuadShape c;
-                c.tb = tb;
-                c.bs = bs;
-                c.xc = xc;
-                c.ms = 1e30f;
-                cand.push_back(c);
-            }
+    Sched best;
+    best.ms = 1e30f;
+    // one pass
+    std::vector<Sched> one = column_candidates<T>(s, true, epi);
+    if (!one.empty()) {
+        int bi = 0;
+        float ms = 0.f;
+        HUB_TRY(time_candidates(st, (int)one.size(),
+                                [&](int c) { return launch_sched<T>(s, A, st, one[(size_t)c], epi ? &E : nullptr); },
+                                bi, ms));
+        best = one[(size_t)bi];
+        best.ms = ms;
     }
-    if (cand.empty()) {
-        set_error("no product shape fits in LDS");
+    // two passes
+    std::vector<Sched> p1 = column_candidates<T>(s, false, false);
+    std::vector<Sched> p2 = band_candidates<T>(s, epi);
+    if (!p1.empty() && !p2.empty()) {
+        int b1 = 0, b2 = 0;
+        float ms1 = 0.f, ms2 = 0.f;
+        HUB_TRY(time_candidates(
+            st, (int)p1.size(),
+            [&](int c) {
+                const Sched &q = p1[(size_t)c];
+                if (q.fam == HUB_SCHED_COLUMNS) return launch_quad<T>(s, A, st, q.tb, q.bs, q.xc, nullptr, false);
+                const ChunkSet *C = nullptr;
+                HUB_TRY(chunk_set(s, HUB_SPIN_UP, q.crows, &C, st));
+                return launch_chunked<T>(s, A, st, q.tb, q.qpl, q.xc, false, *C);
+            },
+            b1, ms1));
+        HUB_TRY(time_candidates(
+            st, (int)p2.size(),
+            [&](int c) {
+                const Sched &q = p2[(size_t)c];
+                return launch_band<T>(s, A, st, q.br, q.bbs, q.bch, epi ? &E : nullptr);
+            },
+            b2, ms2));
+        if (ms1 + ms2 < best.ms) {
+            best = p1[(size_t)b1];
+            best.br = p2[(size_t)b2].br;
+            best.bbs = p2[(size_t)b2].bbs;
+            best.bch = p2[(size_t)b2].bch;
+            best.ms = ms1 + ms2;
+        }
+    }
+    if (best.fam == 0) {
+        set_error("no product schedule fits this sector");
         return HUB_ERR_UNSUPPORTED;
     }
-    for (int round = 0; round < 2; ++round)
-        for (QuadShape &c : cand) {
-            HUB_TRY(launch_quad<T>(s, A, st, c.tb, c.bs, c.xc, epi ? &E : nullptr));
-            HUB_HIP(hipEventRecord(e0, st));
-            for (int r = 0; r < 5; ++r) HUB_TRY(launch_quad<T>(s, A, st, c.tb, c.bs, c.xc, epi ? &E : nullptr));
-            HUB_HIP(hipEventRecord(e1, st));
-            HUB_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HUB_HIP(hipEventElapsedTime(&ms, e0, e1));
-            c.ms = std::min(c.ms, ms / 5.0f);
-        }
-    out = *std::min_element(cand.begin(), cand.end(),
-                            [](const QuadShape &a, const QuadShape &b) { return a.ms < b.ms; });
+    out = best;
     return HUB_OK;
 }
 
-// Tuned shapes are kept per device, dtype and sector structure (dimensions and
-// nonzeros; the values of t, U and eps do not change the timing), so sectors
-// of the same lattice share one tuning.
+// Tuned schedules are kept per device, dtype and sector structure (dimensions,
+// nonzeros and LDS size; the values of t, U and eps do not change the timing),
+// so sectors of the same lattice share one tuning.
 struct ShapeKey {
     int device, dtype;
     int64_t cu, cd, nnz_up, nnz_dn;
@@ -1275,60 +1484,97 @@ struct ShapeKey {
     }
 };
 std::mutex g_shape_mu;
-std::map<ShapeKey, QuadShape> g_shapes;
+std::map<ShapeKey, Sched> g_shapes;
 
-// Shape of the four-rows-per-lane product: forced by HUB_MATVEC_TB / _BS / _XC,
-// else the sector's tuned shape (tuning on first use, shared by sectors of
-// the same structure).  epi: the shape of the product fused with the Lanczos
-// update, tuned separately (apart: its partials buffer, used while tuning).
+// The schedule of the product (epi = false) or of the product fused with the
+// Lanczos update (epi = true) for aligned vectors: forced, cached, shared by a
+// sector of the same structure, or tuned now.  Tuning runs outside the lock;
+// two threads that tune at once both store a valid schedule.
 template <typename T>
-hub_status quad_shape(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, QuadShape &out, bool epi = false,
-                      double *apart = nullptr)
+hub_status schedule_for(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, bool epi, double *apart, Sched &out)
 {
-    const int di = (sizeof(T) == 8) ? 0 : 1;
-    const int tb_env = env_int("HUB_MATVEC_TB", 0);
-    const int bs_env = env_int("HUB_MATVEC_BS", 0);
-    if (tb_env > 0 || bs_env > 0) {
-        out.tb = std::min(std::max(tb_env > 0 ? tb_env : 1, 1), 3);
-        out.bs = bs_env == 512 ? 512 : 1024;
-        out.xc = env_int("HUB_MATVEC_XC", 1) != 0 ? 1 : 0;
-        return HUB_OK;
-    }
-    // the sector's cached shape and the shared table are read and written under
-    // one mutex (a sector may serve products on several threads); tuning runs
-    // outside it, and two threads that tune at once both store a valid shape
-    QuadShape &q = epi ? s->quad_lz[di] : s->quad[di];
+    const int di = dix<T>();
     const ShapeKey key{s->device, di, (int64_t)A.cu, (int64_t)A.cd, s->spin[0].nnz, s->spin[1].nnz, epi ? 1 : 0};
     {
-        std::lock_guard<std::mutex> lk(g_shape_mu);
-        if (q.tb == 0) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->forced[di]) {
+            out = s->sched[di];
+            return HUB_OK;
+        }
+        Sched &q = epi ? s->sched_lz[di] : s->sched[di];
+        if (q.fam == 0) {
+            std::lock_guard<std::mutex> lk2(g_shape_mu);
             auto it = g_shapes.find(key);
             if (it != g_shapes.end()) q = it->second;
         }
-        if (q.tb != 0) {
+        if (q.fam != 0) {
             out = q;
             return HUB_OK;
         }
     }
-    QuadShape t;
-    HUB_TRY(tune_quad<T>(s, A, st, t, epi, apart));
-    std::lock_guard<std::mutex> lk(g_shape_mu);
-    g_shapes[key] = t;
-    q = t;
-    out = t;
+    if (!quad_ok(s)) {
+        out = Sched{};
+        out.fam = (s->spin[0].ell_c32 && column_fits<T>(s, 1, false)) ? HUB_SCHED_ROWS : HUB_SCHED_CSR;
+        if (epi) {
+            set_error("no fused Lanczos update for this sector");
+            return HUB_ERR_UNSUPPORTED;
+        }
+    } else {
+        Sched t;
+        // building chunk tables and timing use the sector's stream and caches under its lock
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            HUB_TRY(tune<T>(s, A, st, epi, apart, t));
+        }
+        out = t;
+        std::lock_guard<std::mutex> lk2(g_shape_mu);
+        g_shapes[key] = t;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    (epi ? s->sched_lz[di] : s->sched[di]) = out;
     return HUB_OK;
 }
 
-// Whether the fused product + first Lanczos update is available for the sector.
+template <typename T>
+hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
+{
+    MvArgs<T> A = make_args<T>(s, x, y);
+    // the 16-byte-access kernels need 16-byte aligned vectors
+    const bool aligned16 = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0;
+    if (!aligned16 || !quad_ok(s)) {
+        std::unique_lock<std::mutex> lk(s->mu);
+        const bool csr = s->forced[dix<T>()] && s->sched[dix<T>()].fam == HUB_SCHED_CSR;
+        lk.unlock();
+        Sched q;
+        q.fam = csr ? HUB_SCHED_CSR : HUB_SCHED_ROWS;
+        return launch_sched<T>(s, A, st, q, nullptr);
+    }
+    Sched q;
+    HUB_TRY(schedule_for<T>(s, A, st, false, nullptr, q));
+    std::lock_guard<std::mutex> lk(s->mu);  // chunk tables may be built on first use
+    return launch_sched<T>(s, A, st, q, nullptr);
+}
+
+// Whether the product fused with the first Lanczos update is available.
 template <typename T>
 bool lz_fusable(const hub_sector *s)
 {
-    const SpinTables &U = s->spin[0];
-    const size_t col_bytes = (size_t)U.count * sizeof(T);
-    return !s->k0 && env_int("HUB_MATVEC_IMPL", 2) == 2 && env_int("HUB_MATVEC_QUAD", 1) != 0 &&
-           env_int("HUB_ELL_FMT", 1) != 0 && env_int("HUB_LZ_FUSE", 1) != 0 && U.ell_c32 && !s->force_chunked &&
-           (U.count % 4) == 0 &&
-           col_bytes + 256 * sizeof(T) + (size_t)((U.count / 4 + 63) / 64) * sizeof(double) <= s->lds_max;
+    if (!quad_ok(s)) return false;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int di = dix<T>();
+    if (s->forced[di]) {
+        const Sched &q = s->sched[di];
+        if (q.nofuse) return false;
+        if (q.br > 0) {
+            // the partials buffer holds at most 65536 band items (matvec_lz_partials)
+            BandGeom g;
+            return band_geom<T>(s, q.br, q.bbs, q.bch, g) && (int64_t)g.nbands * g.ngroups <= 65536 &&
+                   (q.fam == HUB_SCHED_COLUMNS || q.fam == HUB_SCHED_CHUNKED);
+        }
+        return q.fam == HUB_SCHED_COLUMNS && column_fits<T>(s, q.tb, true);
+    }
+    return !column_candidates<T>(s, true, true).empty() ||
+           (!column_candidates<T>(s, false, false).empty() && !band_candidates<T>(s, true).empty());
 }
 
 template <typename T>
@@ -1337,151 +1583,18 @@ hub_status run_kron_lz(const hub_sector *s, const void *x, void *w, const void *
 {
     if (!lz_fusable<T>(s)) return HUB_ERR_UNSUPPORTED;
     MvArgs<T> A = make_args<T>(s, x, w);
-    QuadShape q;
-    HUB_TRY(quad_shape<T>(s, A, st, q, true, apart));
-    const int G = (int)(((A.cu >> 2) + 63) / 64);
-    const LzEpi<T> E{(const T *)vprev, beta, apart, G, beta_prev, unnorm};
-    *npart = (int64_t)A.cd;
-    // the group partials need TB * G doubles of LDS beside the columns: fall back to fewer columns
-    for (int tb = q.tb; tb >= 1; --tb) {
-        if ((size_t)(A.cu * tb + 256) * sizeof(T) + (size_t)tb * G * sizeof(double) <= s->lds_max)
-            return launch_quad<T>(s, A, st, tb, q.bs, q.xc, &E);
+    Sched q;
+    HUB_TRY(schedule_for<T>(s, A, st, true, apart, q));
+    const LzEpi<T> E{(const T *)vprev, beta, apart, (int)(((A.cu >> 2) + 63) / 64), beta_prev, unnorm};
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (q.br > 0) {
+        BandGeom g;
+        if (!band_geom<T>(s, q.br, q.bbs, q.bch, g)) return HUB_ERR_UNSUPPORTED;
+        *npart = (int64_t)g.nbands * g.ngroups;
+    } else {
+        *npart = (int64_t)A.cd;
     }
-    return HUB_ERR_UNSUPPORTED;
-}
-
-// Row-chunked product with register-held output rows: TB columns per work
-// item (the chunk tables were sized for TB), 4 x 1024 lane-quads per row part.
-template <typename T, int TB>
-hub_status launch_chunked_parts_t(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const T *cv)
-{
-    constexpr int BSC = 1024, QPL = 4;
-    const int di = (sizeof(T) == 8) ? 0 : 1;
-    const SpinTables &U = s->spin[0];
-    const size_t lds = ((size_t)U.chunk_rows[di] * TB + 256) * sizeof(T);
-    if (lds > s->lds_max) {
-        set_error("row-chunked product: chunk does not fit in LDS");
-        return HUB_ERR_UNSUPPORTED;
-    }
-    const int nq = (int)(A.cu >> 2);
-    const int P = (nq + BSC * QPL - 1) / (BSC * QPL);
-    const int ntiles = (A.cd + TB - 1) / TB;
-    static std::atomic<bool> attr{false};
-    if (!attr) {
-        HUB_TRY(allow_lds(k_kron_chunked_parts<T, BSC, QPL, TB>, s->lds_max));
-        attr = true;
-    }
-    const unsigned grid = 8u * (unsigned)P * (unsigned)((ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_kron_chunked_parts<T, BSC, QPL, TB>), dim3(grid), dim3(BSC), lds, st, A, U.ch_off[di],
-                       U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di], (int)U.nslices, P);
-    HUB_HIP(hipGetLastError());
-    return HUB_OK;
-}
-
-template <typename T>
-hub_status launch_chunked_parts(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, const T *cv)
-{
-    // FP64 with four columns would need more registers than a 1024-lane workgroup has
-    if constexpr (sizeof(T) == 4)
-        if (tb >= 4) return launch_chunked_parts_t<T, 4>(s, A, st, cv);
-    if (tb >= 2) return launch_chunked_parts_t<T, 2>(s, A, st, cv);
-    return launch_chunked_parts_t<T, 1>(s, A, st, cv);
-}
-
-// Schedule selection.  Environment overrides for measurement: HUB_MATVEC_IMPL
-// (1 csr, 2 fused, 3 two-pass), HUB_MATVEC_TB, HUB_MATVEC_BS (512 / 1024),
-// HUB_MATVEC_XC (tile order), HUB_MATVEC_QUAD (0: one row per lane),
-// HUB_FUSED_R, HUB_ELL_FMT (0 packed, 1 compact), HUB_DN_OCC, HUB_DN_NT.
-// Default: the four-rows-per-lane fused kernel when count_up % 4 == 0 (shape
-// tuned on the first product of each dtype), else the one-row fused kernel
-// with two columns per workgroup when they fit in half of the LDS; the
-// row-chunked kernel when a column does not fit in the LDS.
-template <typename T>
-hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
-{
-    MvArgs<T> A = make_args<T>(s, x, y);
-    const size_t col_bytes = (size_t)A.cu * sizeof(T);
-    // read on every call so a variant or shape can be forced for measurement or tests
-    const int impl = env_int("HUB_MATVEC_IMPL", 2);
-    const int tb_env = env_int("HUB_MATVEC_TB", 0);
-    const int bs_env = env_int("HUB_MATVEC_BS", 0);
-    const int occ = env_int("HUB_DN_OCC", 4);
-    const int nt = env_int("HUB_DN_NT", 1);
-    const int rows = env_int("HUB_FUSED_R", 4);
-    const bool cf = env_int("HUB_ELL_FMT", 1) != 0;
-    // four-rows-per-lane kernels use 16-byte accesses: caller vectors that are
-    // not 16-byte aligned take the one-row-per-lane kernels
-    const bool aligned16 = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0;
-    const bool quad = env_int("HUB_MATVEC_QUAD", 1) != 0 && aligned16;
-    const size_t extra = 256 * sizeof(T);
-    const size_t half = s->lds_max / 2;
-    int tb = tb_env;
-    if (tb <= 0) tb = (2 * col_bytes + extra <= half) ? 2 : 1;
-    while (tb > 1 && tb * col_bytes + extra > s->lds_max) tb >>= 1;
-    const bool fits = col_bytes + extra <= s->lds_max;
-    const bool big = bs_env != 512;
-    if (impl == 3 && fits) {
-        if (tb >= 2)
-            return big ? launch_two_pass<T, 2, 1024>(s, A, st, occ, nt) : launch_two_pass<T, 2, 512>(s, A, st, occ, nt);
-        return big ? launch_two_pass<T, 1, 1024>(s, A, st, occ, nt) : launch_two_pass<T, 1, 512>(s, A, st, occ, nt);
-    }
-    const int di = (sizeof(T) == 8) ? 0 : 1;
-    const SpinTables &U = s->spin[0];
-    if (impl != 1 && (!fits || s->force_chunked) && U.ch_ell[di]) {
-        constexpr int BSC = 1024;
-        const size_t lds = (size_t)(U.chunk_rows[di] + 256) * sizeof(T);
-        static std::atomic<bool> attr{false};
-        if (!attr) {
-            HUB_TRY(allow_lds(k_kron_chunked<T, BSC, 4>, s->lds_max));
-            attr = true;
-        }
-        const T *cv;
-        if constexpr (sizeof(T) == 8) cv = (const T *)U.code_v64;
-        else cv = (const T *)U.code_v32;
-        const unsigned grid = 8u * (unsigned)((A.cd + 7) / 8);
-        const int ctb = U.chunk_tb[di];
-        if (quad && (A.cu % 4) == 0 && (U.chunk_rows[di] % 4) == 0 && env_int("HUB_CHUNK_PARTS", 1) != 0) {
-            HUB_TRY(launch_chunked_parts<T>(s, A, st, ctb, cv));
-        } else if (quad && (A.cu % 4) == 0 && (U.chunk_rows[di] % 4) == 0) {
-            // tile order: launch order (all XCDs on nearby columns, so recently read
-            // neighbour columns are more often still in the MALL: 2x9 ladder FP32 39.3 -> 37.6 ms)
-            // or XCD-contiguous ranges (HUB_CHUNK_XC=1)
-            const bool xc = env_int("HUB_CHUNK_XC", 0) != 0;
-            static std::atomic<bool> attrq{false};
-            if (!attrq) {
-                HUB_TRY(allow_lds(k_kron_chunked_quad<T, BSC, true>, s->lds_max));
-                HUB_TRY(allow_lds(k_kron_chunked_quad<T, BSC, false>, s->lds_max));
-                attrq = true;
-            }
-            if (xc)
-                hipLaunchKernelGGL((k_kron_chunked_quad<T, BSC, true>), dim3(grid), dim3(BSC), lds, st, A,
-                                   U.ch_off[di], U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di],
-                                   (int)U.nslices);
-            else
-                hipLaunchKernelGGL((k_kron_chunked_quad<T, BSC, false>), dim3(grid), dim3(BSC), lds, st, A,
-                                   U.ch_off[di], U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di],
-                                   (int)U.nslices);
-        } else {
-            hipLaunchKernelGGL((k_kron_chunked<T, BSC, 4>), dim3(grid), dim3(BSC), lds, st, A, U.ch_off[di],
-                               U.ch_base[di], U.ch_ell[di], cv, U.nchunks[di], U.chunk_rows[di], (int)U.nslices);
-        }
-        HUB_HIP(hipGetLastError());
-        return HUB_OK;
-    }
-    if (impl == 2 && fits && cf && U.ell_c32 && (A.cu % 4) == 0 && quad) {
-        QuadShape q;
-        HUB_TRY(quad_shape<T>(s, A, st, q));
-        return launch_quad<T>(s, A, st, q.tb, q.bs, q.xc);
-    }
-    if (impl == 2 && fits) {
-        if (tb >= 4) return big ? launch_fused<T, 4, 1024, 1>(s, A, st, cf) : launch_fused<T, 4, 512, 1>(s, A, st, cf);
-        if (tb >= 2) return big ? launch_fused<T, 2, 1024, 2>(s, A, st, cf) : launch_fused<T, 2, 512, 2>(s, A, st, cf);
-        if (rows >= 4) return big ? launch_fused<T, 1, 1024, 4>(s, A, st, cf) : launch_fused<T, 1, 512, 4>(s, A, st, cf);
-        return big ? launch_fused<T, 1, 1024, 1>(s, A, st, cf) : launch_fused<T, 1, 512, 1>(s, A, st, cf);
-    }
-    hipLaunchKernelGGL((k_kron_csr<T, 512>), dim3((unsigned)A.cd), dim3(512), 0, st, A);
-    HUB_HIP(hipGetLastError());
-    return HUB_OK;
+    return launch_sched<T>(s, A, st, q, &E);
 }
 
 }  // namespace
@@ -1497,9 +1610,21 @@ bool matvec_lz_available(const hub_sector *s, int dtype)
     return dtype == HUB_F64 ? lz_fusable<double>(s) : lz_fusable<float>(s);
 }
 
+// Upper bound of the fused product's partials (per column, or per row-band
+// work item of a candidate whose count is at most 65536).
 int64_t matvec_lz_partials(const hub_sector *s)
 {
-    return s->spin[1].count;
+    int64_t np = s->spin[1].count;
+    for (int bs : {512, 1024}) {
+        BandGeom g;
+        for (int R : {4, 8})
+            if (band_geom<float>(s, R, bs, 0, g) && (int64_t)g.nbands * g.ngroups <= 65536)
+                np = std::max(np, (int64_t)g.nbands * g.ngroups);
+        for (int R : {2, 4})
+            if (band_geom<double>(s, R, bs, 0, g) && (int64_t)g.nbands * g.ngroups <= 65536)
+                np = std::max(np, (int64_t)g.nbands * g.ngroups);
+    }
+    return np;
 }
 
 hub_status launch_matvec_lz(const hub_sector *s, int dtype, const void *x, void *w, const void *vprev,
@@ -1535,6 +1660,111 @@ int64_t matvec_bytes(const hub_sector *s, int dtype)
         bytes += 4 * (T.count + 1) + T.nnz * (4 + es) + 4 * T.count + es * T.count;
     }
     return bytes;
+}
+
+// ---- forced schedules (tests and measurement) --------------------------------
+
+namespace {
+
+template <typename T>
+hub_status check_forced(const hub_sector *s, const hub_schedule &h, Sched &q)
+{
+    q = Sched{};
+    q.fam = h.family;
+    q.tb = h.tile_cols;
+    q.bs = h.block;
+    q.xc = h.order;
+    q.qpl = h.quads_per_lane;
+    q.crows = h.chunk_rows;
+    q.br = h.band_rows;
+    q.bbs = h.band_block;
+    q.bch = h.band_chunk;
+    q.nofuse = h.no_fused_update;
+    auto bad = [](const char *m) {
+        set_error(m);
+        return HUB_ERR_INVALID_ARG;
+    };
+    switch (q.fam) {
+    case HUB_SCHED_COLUMNS:
+        if (!quad_ok(s)) return bad("columns schedule needs count_up % 4 == 0 and compact entries");
+        if (q.tb < 1 || q.tb > 3 || (q.bs != 512 && q.bs != 1024) || (q.xc != 0 && q.xc != 1))
+            return bad("columns schedule: tile_cols 1..3, block 512 or 1024, order 0 or 1");
+        if (!column_fits<T>(s, q.tb, false)) return bad("columns schedule: the tile does not fit in LDS");
+        break;
+    case HUB_SCHED_CHUNKED:
+        if (!quad_ok(s)) return bad("chunked schedule needs count_up % 4 == 0 and compact entries");
+        if (!chunked_shape_ok<T>(q.tb, q.qpl) || (q.xc != 0 && q.xc != 1))
+            return bad("chunked schedule: unsupported tile_cols / quads_per_lane / order");
+        if (q.crows <= 0) q.crows = chunked_rows<T>(s, q.tb);
+        if (q.crows <= 0 || q.crows % 4 != 0 || ((size_t)q.crows * q.tb + 256) * sizeof(T) > s->lds_max)
+            return bad("chunked schedule: chunk_rows must be a positive multiple of 4 that fits in LDS");
+        q.bs = 1024;
+        break;
+    case HUB_SCHED_ROWS:
+        if (!column_fits<T>(s, 1, false)) return bad("rows schedule: a column does not fit in LDS");
+        q.br = 0;
+        break;
+    case HUB_SCHED_CSR:
+        q.br = 0;
+        break;
+    default:
+        return bad("unknown schedule family");
+    }
+    if (q.br > 0) {
+        BandGeom g;
+        if (!band_geom<T>(s, q.br, q.bbs, q.bch, g))
+            return bad("row-band pass: band_rows must give 16- or 32-byte slots, band_block 512 or 1024, "
+                       "band_chunk fit in LDS");
+        q.bch = g.chunk;
+    } else {
+        q.br = 0;
+    }
+    return HUB_OK;
+}
+
+void to_public(const Sched &q, hub_schedule *h)
+{
+    *h = hub_schedule{};
+    h->family = q.fam;
+    h->tile_cols = q.tb;
+    h->block = q.bs;
+    h->order = q.xc;
+    h->quads_per_lane = q.qpl;
+    h->chunk_rows = q.crows;
+    h->band_rows = q.br;
+    h->band_block = q.bbs;
+    h->band_chunk = q.bch;
+    h->no_fused_update = q.nofuse;
+    h->ms = q.ms;
+}
+
+}  // namespace
+
+hub_status set_schedule(const hub_sector *s, int dtype, const hub_schedule *h)
+{
+    const int di = dtype == HUB_F64 ? kF64 : kF32;
+    if (!h) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->forced[di] = false;
+        s->sched[di] = Sched{};
+        s->sched_lz[di] = Sched{};
+        return HUB_OK;
+    }
+    Sched q;
+    HUB_TRY(dtype == HUB_F64 ? check_forced<double>(s, *h, q) : check_forced<float>(s, *h, q));
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->forced[di] = true;
+    s->sched[di] = q;
+    s->sched_lz[di] = q;
+    return HUB_OK;
+}
+
+hub_status get_schedule(const hub_sector *s, int dtype, int fused, hub_schedule *h)
+{
+    const int di = dtype == HUB_F64 ? kF64 : kF32;
+    std::lock_guard<std::mutex> lk(s->mu);
+    to_public(fused && !s->forced[di] ? s->sched_lz[di] : s->sched[di], h);
+    return HUB_OK;
 }
 
 }  // namespace hub

@@ -438,26 +438,43 @@ hub_status build_spin_tables(hub_sector *s, int spin, int N, hipStream_t st)
     return HUB_OK;
 }
 
-hub_status build_chunked_tables(hub_sector *s, int spin, int dtype, int chunk_rows, hipStream_t st)
+// Chunk tables of H_spin (see ChunkSet), built on first request and kept for
+// the life of the sector.  Called under the sector's cache mutex.
+static hub_status build_chunk_set(hub_sector *s, int spin, int chunk_rows, ChunkSet &cs, hipStream_t st)
 {
-    SpinTables &T = s->spin[spin];
-    const int di = (dtype == HUB_F64) ? 0 : 1;
-    if (T.ch_ell[di]) return HUB_OK;
+    const SpinTables &T = s->spin[spin];
     if (!T.ell_c32) {
-        set_error("row-chunked product needs the compact entry format (count < 2^24, <= 127 bonds)");
+        set_error("chunked products need the compact entry format (count < 2^24, <= 127 bonds)");
         return HUB_ERR_UNSUPPORTED;
+    }
+    if (chunk_rows < 1) {
+        set_error("chunk of fewer than one column");
+        return HUB_ERR_INVALID_ARG;
     }
     const int64_t count = T.count, ns = T.nslices;
     const int P = (int)((count + chunk_rows - 1) / chunk_rows);
+    // temporaries freed on every path; the tables themselves are owned by the sector
+    struct Tmp {
+        std::vector<void *> p;
+        ~Tmp()
+        {
+            for (void *q : p) (void)hipFree(q);
+        }
+    } tmp;
+    auto talloc = [&](void **q, size_t bytes) -> hub_status {
+        HUB_HIP(hipMalloc(q, bytes == 0 ? 1 : bytes));
+        tmp.p.push_back(*q);
+        return HUB_OK;
+    };
     int32_t *rstart = nullptr, *rlen = nullptr, *slen = nullptr, *offs = nullptr;
     int64_t *stmp = nullptr, *ssum = nullptr;
     const int64_t snblk = (ns + kScanBlock - 1) / kScanBlock;
-    HUB_TRY(dalloc(s, &rstart, count));
-    HUB_TRY(dalloc(s, &rlen, count));
-    HUB_TRY(dalloc(s, &slen, ns));
+    HUB_TRY(talloc((void **)&rstart, sizeof(int32_t) * (size_t)count));
+    HUB_TRY(talloc((void **)&rlen, sizeof(int32_t) * (size_t)count));
+    HUB_TRY(talloc((void **)&slen, sizeof(int32_t) * (size_t)ns));
+    HUB_TRY(talloc((void **)&stmp, sizeof(int64_t) * (size_t)ns));
+    HUB_TRY(talloc((void **)&ssum, sizeof(int64_t) * (size_t)snblk));
     HUB_TRY(dalloc(s, &offs, (size_t)P * (ns + 1)));
-    HUB_TRY(dalloc(s, &stmp, ns));
-    HUB_TRY(dalloc(s, &ssum, snblk));
     std::vector<int64_t> base(P + 1, 0);
     const int B = 256;
     for (int p = 0; p < P; ++p) {
@@ -477,14 +494,14 @@ hub_status build_chunked_tables(hub_sector *s, int spin, int dtype, int chunk_ro
         base[p + 1] = base[p] + 64 * (int64_t)slots;
     }
     if (base[P] >= ((int64_t)1 << 31)) {
-        set_error("row-chunked hopping matrix would exceed 2^31 entries");
+        set_error("chunked hopping matrix would exceed 2^31 entries");
         return HUB_ERR_RANGE;
     }
     uint32_t *ell = nullptr;
     int64_t *dbase = nullptr;
     HUB_TRY(dalloc(s, &ell, (size_t)base[P]));
     HUB_TRY(dalloc(s, &dbase, P));
-    HUB_HIP(hipMemcpy(dbase, base.data(), sizeof(int64_t) * P, hipMemcpyHostToDevice));
+    HUB_HIP(hipMemcpyAsync(dbase, base.data(), sizeof(int64_t) * P, hipMemcpyHostToDevice, st));
     for (int p = 0; p < P; ++p) {
         const int c_lo = p * chunk_rows;
         const int c_hi = (int)std::min<int64_t>(count, (int64_t)(p + 1) * chunk_rows);
@@ -495,19 +512,28 @@ hub_status build_chunked_tables(hub_sector *s, int spin, int dtype, int chunk_ro
     }
     HUB_HIP(hipGetLastError());
     HUB_HIP(hipStreamSynchronize(st));
-    T.nchunks[di] = P;
-    T.chunk_rows[di] = chunk_rows;
-    T.ch_off[di] = offs;
-    T.ch_base[di] = dbase;
-    T.ch_ell[di] = ell;
-    if (s->shared_spin && spin == 0) {
-        SpinTables &D = s->spin[1];
-        D.nchunks[di] = P;
-        D.chunk_rows[di] = chunk_rows;
-        D.ch_off[di] = offs;
-        D.ch_base[di] = dbase;
-        D.ch_ell[di] = ell;
-    }
+    cs.spin = spin;
+    cs.rows = chunk_rows;
+    cs.n = P;
+    cs.off = offs;
+    cs.base = dbase;
+    cs.ell = ell;
+    return HUB_OK;
+}
+
+hub_status chunk_set(const hub_sector *cs, int spin, int rows, const ChunkSet **out, hipStream_t st)
+{
+    hub_sector *s = const_cast<hub_sector *>(cs);  // the chunk cache is not part of the sector's value
+    if (s->shared_spin) spin = 0;
+    for (const ChunkSet &c : s->chunks)
+        if (c.spin == spin && c.rows == rows) {
+            *out = &c;
+            return HUB_OK;
+        }
+    ChunkSet c;
+    HUB_TRY(build_chunk_set(s, spin, rows, c, st));
+    s->chunks.push_back(c);
+    *out = &s->chunks.back();
     return HUB_OK;
 }
 
