@@ -206,15 +206,12 @@ def k0_timing(hub, torch, model):
 
 
 def kernel_name(sched, es):
-    """Name of the product kernel a tuned schedule launches (the dominant one)."""
+    """Name of the product kernel a tuned schedule launches."""
     T = "double" if es == 8 else "float"
     if sched["family"] == 1:
-        return (f"k_kron_quad<{T}, {sched['tile_cols']}, {sched['block']}, {bool(sched['order'])}, false, "
-                f"{'false' if sched['band_rows'] else 'true'}>")
+        return f"k_kron_quad<{T}, {sched['tile_cols']}, {sched['block']}, {bool(sched['order'])}, false>"
     if sched["family"] == 2:
-        dn = "false" if sched["band_rows"] else "true"
-        tm = "true" if (sched["band_rows"] and sched["order"]) else "false"
-        return f"k_kron_chunked_parts<{T}, 1024, {sched['quads_per_lane']}, {sched['tile_cols']}, {dn}, {tm}>"
+        return f"k_kron_chunked_parts<{T}, 1024, {sched['quads_per_lane']}, {sched['tile_cols']}>"
     return {3: "k_kron_fused", 4: "k_kron_csr"}.get(sched["family"], "?")
 
 

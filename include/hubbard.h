@@ -160,28 +160,27 @@ hub_status hub_start_vector(const hub_sector *sec, int32_t dtype, uint64_t seed,
 hub_status hub_matvec(const hub_sector *sec, int32_t dtype, const void *dev_x, void *dev_y, void *stream);
 
 /*
- * Product schedule: which kernels apply the Kronecker sum of Sec. IV A and with
- * what tile shape.  Every schedule computes each element of y with the same
- * operations in the same order (diagonal, H_up entries in column order, H_dn
- * entries in column order), so the choice never changes a result.
+ * Product schedule: which kernel applies the Kronecker sum of Sec. IV A and
+ * with what tile shape.  Every schedule computes each element of y with the
+ * same operations in the same order (diagonal, H_up entries in column order,
+ * H_dn entries in column order, one fused multiply-add each), so the choice
+ * never changes a result.
  *
- *   HUB_SCHED_COLUMNS  whole columns of V staged in LDS (count_up % 4 == 0);
- *   HUB_SCHED_CHUNKED  columns staged in chunks of chunk_rows rows (columns
- *                      larger than the LDS);
+ *   HUB_SCHED_COLUMNS  whole columns of V staged in LDS, four rows per lane
+ *                      (count_up % 4 == 0);
+ *   HUB_SCHED_CHUNKED  columns staged in LDS in chunks of chunk_rows rows, the
+ *                      output rows held in registers (columns larger than the
+ *                      LDS);
  *   HUB_SCHED_ROWS     one row per lane (count_up % 4 != 0, unaligned vectors);
  *   HUB_SCHED_CSR      CSR rows from global memory (no compact entries).
- * With band_rows > 0 a COLUMNS or CHUNKED schedule runs in two passes: the
- * column pass writes y = D o x + H_up x, then a row-band pass adds x H_dn^T
- * from bands of band_rows rows of x staged in LDS (band_rows * element size =
- * 16 or 32 bytes).
  *
  * By default the first product of each dtype on a sector structure times the
- * candidates and keeps the fastest (hub_matvec); hub_get_schedule reports it.
- * hub_set_schedule forces one for tests and measurement (NULL: back to the
- * tuned one); it returns INVALID_ARG for a shape the sector cannot run.
- * A forced schedule also applies to the products inside hub_ground_state,
- * whose Lanczos update is fused into the product unless no_fused_update is set
- * or the schedule has no fused form (one-pass CHUNKED, ROWS, CSR).
+ * candidate shapes and keeps the fastest (hub_matvec); hub_get_schedule
+ * reports it.  hub_set_schedule forces one, for tests and measurement (NULL:
+ * back to the tuned one); it returns INVALID_ARG for a shape the sector cannot
+ * run.  A forced schedule also applies to the products inside
+ * hub_ground_state, whose Lanczos update is fused into the COLUMNS product
+ * unless no_fused_update is set.
  */
 #define HUB_SCHED_AUTO 0
 #define HUB_SCHED_COLUMNS 1
@@ -192,13 +191,11 @@ hub_status hub_matvec(const hub_sector *sec, int32_t dtype, const void *dev_x, v
 typedef struct hub_schedule {
     int32_t family;          /* HUB_SCHED_* (AUTO in hub_get_schedule: not chosen yet) */
     int32_t tile_cols;       /* COLUMNS: 1..3; CHUNKED: 1, 2 or 4 columns per workgroup */
-    int32_t block;           /* COLUMNS: 512 or 1024 lanes per workgroup */
-    int32_t order;           /* COLUMNS: 1 = XCD-contiguous tiles; CHUNKED: 1 = a tile's row parts together */
-    int32_t quads_per_lane;  /* CHUNKED: 4 or 8 (a work item covers 4096 * quads_per_lane rows) */
+    int32_t block;           /* COLUMNS: 512 or 1024 lanes per workgroup (CHUNKED: 1024) */
+    int32_t order;           /* COLUMNS: 1 = XCD-contiguous tiles, 0 = launch order */
+    int32_t quads_per_lane;  /* CHUNKED: 4 or 8 (a work item covers 4096 * quads_per_lane rows);
+                                tile_cols * quads_per_lane <= 16 (FP32) or 8 (FP64) */
     int32_t chunk_rows;      /* CHUNKED: rows per staged chunk (0 = as many as fit; multiple of 4) */
-    int32_t band_rows;       /* > 0: two passes, rows per band of the row-band pass */
-    int32_t band_block;      /* row-band pass: 512 or 1024 lanes per workgroup */
-    int32_t band_chunk;      /* row-band pass: columns per staged chunk (0 = as many as fit) */
     int32_t no_fused_update; /* 1: hub_ground_state keeps its Lanczos update out of the product */
     float ms;                /* tuned: time of one product in milliseconds; 0 when forced */
 } hub_schedule;

@@ -50,11 +50,10 @@ class _Model(ctypes.Structure):
 
 
 class Schedule(ctypes.Structure):
-    """hub_schedule: product schedule (family, tile shape, optional row-band pass)."""
+    """hub_schedule: product schedule (family and tile shape)."""
     _fields_ = [
         ("family", ctypes.c_int32), ("tile_cols", ctypes.c_int32), ("block", ctypes.c_int32),
         ("order", ctypes.c_int32), ("quads_per_lane", ctypes.c_int32), ("chunk_rows", ctypes.c_int32),
-        ("band_rows", ctypes.c_int32), ("band_block", ctypes.c_int32), ("band_chunk", ctypes.c_int32),
         ("no_fused_update", ctypes.c_int32), ("ms", ctypes.c_float),
     ]
 
@@ -264,14 +263,14 @@ class Sector:
         return rp, col[:nnz], val[:nnz], bond[:nnz]
 
     def set_schedule(self, dtype: int, family: Optional[int] = None, *, tile_cols: int = 1, block: int = 1024,
-                     order: int = 1, quads_per_lane: int = 4, chunk_rows: int = 0, band_rows: int = 0,
-                     band_block: int = 1024, band_chunk: int = 0, no_fused_update: bool = False):
+                     order: int = 1, quads_per_lane: int = 4, chunk_rows: int = 0, no_fused_update: bool = False):
         """Force the product schedule of `dtype` (family None: back to the tuned one)."""
         if family is None:
             _check(lib().hub_set_schedule(self._h, dtype, None), "hub_set_schedule")
             return
-        sc = Schedule(family, tile_cols, block, order, quads_per_lane, chunk_rows, band_rows, band_block,
-                      band_chunk, int(no_fused_update), 0.0)
+        if family == SCHED_CHUNKED:
+            order, block = 0, 1024
+        sc = Schedule(family, tile_cols, block, order, quads_per_lane, chunk_rows, int(no_fused_update), 0.0)
         _check(lib().hub_set_schedule(self._h, dtype, ctypes.byref(sc)), "hub_set_schedule")
 
     def schedule(self, dtype: int = F64, fused: bool = False) -> dict:

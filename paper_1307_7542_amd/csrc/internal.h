@@ -97,10 +97,9 @@ struct ChunkSet {
 // Product schedule (see hub_schedule in hubbard.h): fam 0 = not chosen yet.
 struct Sched {
     int fam = 0;
-    int tb = 0, bs = 0, xc = 0;  // column pass: columns per workgroup, lanes, tile order
-    int qpl = 0;                 // row-chunked column pass: lane-quads per lane
-    int crows = 0;               // row-chunked column pass: rows per staged chunk
-    int br = 0, bbs = 0, bch = 0;  // row-band pass: rows per band, lanes, columns per staged chunk
+    int tb = 0, bs = 0, xc = 0;  // columns per workgroup, lanes, tile order
+    int qpl = 0;                 // row-chunked: lane-quads per lane
+    int crows = 0;               // row-chunked: rows per staged chunk
     int nofuse = 0;              // forced: keep the Lanczos update out of the product
     float ms = 0.f;
 };

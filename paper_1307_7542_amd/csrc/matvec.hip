@@ -16,20 +16,13 @@
 //             reads its neighbour columns through L2 / MALL.
 //   chunked   columns larger than the LDS (k_kron_chunked_parts): the columns
 //             are staged chunk by chunk while the output rows stay in registers.
-//   two-pass  either of the above without the H_dn term (writes Y = D o V +
-//             H_up V), then the row-band pass k_kron_dn_band: bands of R rows
-//             of V are staged in LDS chunk by chunk, slot of R elements per
-//             column, and each lane adds the H_dn entries of its output columns
-//             from LDS into Y, accumulators in registers.  Every element of V is
-//             then read from HBM twice instead of once plus deg_dn times
-//             through the caches.
 //   rows      one row per lane (k_kron_fused), for count_up % 4 != 0 or
 //             vectors that are not 16-byte aligned.
 //   csr       rows of the CSR gathered from global memory (no compact entries).
 //
 // Every schedule computes each element as: diagonal, then the H_up entries in
-// column order, then the H_dn entries in column order, one rounding per term, so
-// all give bit-identical products (tested).
+// column order, then the H_dn entries in column order, one fused multiply-add
+// per term, so all give bit-identical products (tested).
 //
 // H_up is read from its sliced-ELL copy: lane r of a wavefront owns row
 // 64*s + r of slice s and loads entry k from a coalesced address; the default
@@ -274,30 +267,6 @@ __device__ __forceinline__ void st_q4(T *p, const T (&v)[4])
     }
 }
 
-// one 16-byte piece: 4 FP32 or 2 FP64 elements
-template <typename T>
-struct P16 {
-    static constexpr int N = 16 / (int)sizeof(T);
-    T v[N];
-};
-
-template <typename T>
-__device__ __forceinline__ P16<T> ld16(const T *p)
-{
-    P16<T> r;
-    const uint4 q = *reinterpret_cast<const uint4 *>(p);
-    __builtin_memcpy(r.v, &q, 16);
-    return r;
-}
-
-template <typename T>
-__device__ __forceinline__ void st16(T *p, const P16<T> &v)
-{
-    uint4 q;
-    __builtin_memcpy(&q, v.v, 16);
-    *reinterpret_cast<uint4 *>(p) = q;
-}
-
 // First Lanczos update fused into the product's epilogue: w = (H x) - beta v_prev
 // (rounded as the separate update kernel does) and partial sums of w * x.
 //
@@ -311,7 +280,7 @@ template <typename T>
 struct LzEpi {
     const T *vprev;           // NULL at the first step
     const double *beta;       // beta_k (device)
-    double *apart;            // partials (per column or per band item)
+    double *apart;            // [cd] per-column partials
     int G;                    // lane-quad groups per column: ceil(count_up / 256)
     const double *beta_prev;  // unnorm: beta_{k-1} (device), NULL for beta_0
     int unnorm;
@@ -367,18 +336,15 @@ __device__ __forceinline__ T epi_w(const LzEpi<T> &E, const EpiCoef<T> &c, T o, 
 // 16-byte (FP32) or 2 x 16-byte (FP64) accesses, and the four rows' sliced-ELL
 // entries k are four consecutive lanes of the slice, read with one 16-byte
 // load.  XC: XCD-contiguous tile order (workgroup i on XCD i mod 8 takes the
-// i-th tile of that XCD's range) or plain launch order.  DN: add the H_dn term
-// (one pass); without it the kernel is the column pass of the two-pass
-// schedule.  EPI (with DN): the first Lanczos update, each group of 64
-// lane-quads (256 rows) summed by one wavefront in a fixed order, then the
-// groups of a column in increasing order, so the per-column partials do not
-// depend on the tile shape.
-template <typename T, int TB, int BS, bool XC, bool EPI, bool DN>
+// i-th tile of that XCD's range) or plain launch order.  EPI: the first
+// Lanczos update, each group of 64 lane-quads (256 rows) summed by one
+// wavefront in a fixed order, then the groups of a column in increasing order,
+// so the per-column partials do not depend on the tile shape.
+template <typename T, int TB, int BS, bool XC, bool EPI>
 __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__restrict__ sl_off,
                                                   const uint32_t *__restrict__ ellc, const T *__restrict__ code_v,
                                                   int ntiles, LzEpi<T> E)
 {
-    static_assert(DN || !EPI, "the fused update needs the whole product");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tab = reinterpret_cast<T *>(smem_raw);  // 256 code values
     T *xs = tab + 256;                         // TB staged columns, interleaved
@@ -468,28 +434,26 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
                 for (int t = 0; t < TB; ++t) acc[i][t] += v * xr[t];
             }
         }
-        if constexpr (DN) {
-            // H_dn term: whole neighbour columns, four rows per load
+        // H_dn term: whole neighbour columns, four rows per load
 #pragma unroll
-            for (int t = 0; t < TB; ++t) {
-                int kk = ds[t];
-                for (; kk + 4 <= de[t]; kk += 4) {
-                    Q4<T> v[4];
+        for (int t = 0; t < TB; ++t) {
+            int kk = ds[t];
+            for (; kk + 4 <= de[t]; kk += 4) {
+                Q4<T> v[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
+                for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const T w = A.dn_val[kk + u];
+                for (int u = 0; u < 4; ++u) {
+                    const T w = A.dn_val[kk + u];
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[r][t] += w * v[u].v[r];
-                    }
+                    for (int r = 0; r < 4; ++r) acc[r][t] += w * v[u].v[r];
                 }
-                for (; kk < de[t]; ++kk) {
-                    const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
-                    const T w = A.dn_val[kk];
+            }
+            for (; kk < de[t]; ++kk) {
+                const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
+                const T w = A.dn_val[kk];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc[r][t] += w * v.v[r];
-                }
+                for (int r = 0; r < 4; ++r) acc[r][t] += w * v.v[r];
             }
         }
 #pragma unroll
@@ -528,14 +492,14 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
 // Work item (tile of TB columns, row part j) owns quads [j BS QPL, (j+1) BS
 // QPL) of its columns, QPL per lane.  It stages every row chunk of its columns
 // in turn (interleaved, element (a, t) at a TB + t) and accumulates the chunk's
-// H_up entries of its rows, each entry serving the TB columns; then (DN) the
-// H_dn term and one store.  No partial results go through memory.  Tiles are
-// interleaved over the XCDs (tile = 8 k + xcd); TM = 0: row parts dispatched in
-// turn (every tile's first part, then every tile's second, ...: the neighbour
-// rows read at a time by the one-pass H_dn term are one part's), TM = 1: the
-// parts of a tile consecutively on one XCD (its staged columns are then read
-// from that XCD's L2 by the later parts).
-template <typename T, int BS, int QPL, int TB, bool DN, bool TM>
+// H_up entries of its rows, each entry serving the TB columns; then the H_dn
+// term and one store.  No partial results go through memory.  Tiles are
+// interleaved over the XCDs (tile = 8 k + xcd) and row parts dispatched in
+// turn (every tile's first part, then every tile's second, ...), so the
+// neighbour rows the H_dn term reads at a time are one part's (2x9 ladder:
+// FP32 30.6 -> 30.0 ms, FP64 57.8 -> 56.1 ms against the parts of a tile
+// dispatched together).
+template <typename T, int BS, int QPL, int TB>
 __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const int32_t *__restrict__ ch_off,
                                                            const int64_t *__restrict__ ch_base,
                                                            const uint32_t *__restrict__ ch_ell,
@@ -549,8 +513,7 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const in
     const int cd = A.cd;
     const int ntiles = (cd + TB - 1) / TB;
     const int n8 = (ntiles + 7) / 8;
-    const int tile = TM ? 8 * (r / P) + xcd : 8 * (r % n8) + xcd;
-    const int part = TM ? r % P : r / n8;
+    const int tile = 8 * (r % n8) + xcd, part = r / n8;
     if (tile >= ntiles) return;
     const int b0 = tile * TB;
     const int cu = A.cu, nq = cu >> 2;
@@ -642,189 +605,28 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const in
         const int a0 = 4 * q;
 #pragma unroll
         for (int t = 0; t < TB; ++t) {
-            if constexpr (DN) {
-                int kk = ds[t];
-                for (; kk + 4 <= de[t]; kk += 4) {
-                    Q4<T> v[4];
+            int kk = ds[t];
+            for (; kk + 4 <= de[t]; kk += 4) {
+                Q4<T> v[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
+                for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const T w = A.dn_val[kk + u];
+                for (int u = 0; u < 4; ++u) {
+                    const T w = A.dn_val[kk + u];
 #pragma unroll
-                        for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v[u].v[rr];
-                    }
+                    for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v[u].v[rr];
                 }
-                for (; kk < de[t]; ++kk) {
-                    const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
-                    const T w = A.dn_val[kk];
+            }
+            for (; kk < de[t]; ++kk) {
+                const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
+                const T w = A.dn_val[kk];
 #pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v.v[rr];
-                }
+                for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v.v[rr];
             }
             if (b0 + t < cd) {
                 const T o[4] = {acc[i][0][t], acc[i][1][t], acc[i][2][t], acc[i][3][t]};
                 st_q4(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
             }
-        }
-    }
-}
-
-// ---- row-band pass of the two-pass schedule: y += V H_dn^T ---------------
-// Work item (band j, column group g): rows [R j, R j + R) of the output
-// columns b = g BS NC + lane + BS i (i < NC), accumulated in registers from
-// their value in y (the column pass's diagonal + H_up term), so each element
-// sees the operations of the one-pass kernels in the same order.  The band of
-// V is staged chunk by chunk in LDS, a slot of R elements (one 16- or 32-byte
-// segment of a column) per column, and the H_dn entries of every output column
-// whose column lies in the chunk are added from LDS (the chunk tables of H_dn:
-// entry k of row b at off[b >> 6] 64 + 64 k + (b & 63)).  The 128 / (R s)
-// bands that share a 128-byte line of every column run back to back on one
-// XCD, so its L2 merges their segments of V, y and v_prev.  EPI: the first
-// Lanczos update as in k_kron_quad, with one partial per work item (its lanes
-// in a fixed order) at apart[j ngroups + g].
-template <typename T>
-struct BandArgs {
-    const int32_t *__restrict__ off;
-    const int64_t *__restrict__ base;
-    const uint32_t *__restrict__ ell;
-    const T *__restrict__ code_v;
-    int nchunks, chunk, nslices;
-    int nbands, ngroups;
-};
-
-template <typename T, int R, int NC, int BS, bool EPI>
-__global__ __launch_bounds__(BS) void k_kron_dn_band(MvArgs<T> A, BandArgs<T> B, LzEpi<T> E)
-{
-    constexpr int PN = P16<T>::N;                     // elements per 16-byte piece
-    constexpr int PPS = R / PN;                       // pieces per slot
-    constexpr int LB = 128 / (R * (int)sizeof(T));    // bands per 128-byte line
-    static_assert(PPS >= 1 && PPS * PN == R, "a slot is whole 16-byte pieces");
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *tab = reinterpret_cast<T *>(smem_raw);
-    T *xs = tab + 256;
-    double *wpart = reinterpret_cast<double *>(xs + (size_t)B.chunk * R);  // EPI: one partial per wavefront
-    const int xcd = (int)(blockIdx.x & 7), r = (int)(blockIdx.x >> 3);
-    const int per = LB * B.ngroups;
-    const int band = ((r / per) * 8 + xcd) * LB + (r % per) / B.ngroups;
-    const int group = (r % per) % B.ngroups;
-    if (band >= B.nbands) return;
-    const int cu = A.cu, cd = A.cd;
-    const int64_t cu64 = cu;
-    const int a0 = band * R;
-    const int npv = min(PPS, (cu - a0) / PN);  // whole pieces in the band (count_up % 4 == 0)
-    const int gb0 = group * (BS * NC);
-    for (int i = threadIdx.x; i < 256; i += BS) tab[i] = B.code_v[i];
-    T acc[NC][R];
-#pragma unroll
-    for (int i = 0; i < NC; ++i) {
-        const int b = gb0 + (int)threadIdx.x + i * BS;
-#pragma unroll
-        for (int j = 0; j < PPS; ++j) {
-            P16<T> v = {};
-            if (b < cd && j < npv) v = ld16(A.y + (int64_t)b * cu64 + a0 + j * PN);
-#pragma unroll
-            for (int e = 0; e < PN; ++e) acc[i][j * PN + e] = v.v[e];
-        }
-    }
-    for (int p = 0; p < B.nchunks; ++p) {
-        const int c0 = p * B.chunk;
-        const int nc = min(B.chunk, cd - c0);
-        __syncthreads();  // the previous chunk's gathers are done
-        // four 16-byte loads in flight per lane before their LDS stores
-        for (int i0 = threadIdx.x; i0 < nc * PPS; i0 += 4 * BS) {
-            P16<T> v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int idx = i0 + u * BS;
-                const int c = idx / PPS, j = idx - c * PPS;
-                v[u] = P16<T>{};
-                if (idx < nc * PPS && j < npv) v[u] = ld16(A.x + (int64_t)(c0 + c) * cu64 + a0 + j * PN);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int idx = i0 + u * BS;
-                const int c = idx / PPS, j = idx - c * PPS;
-                if (idx < nc * PPS) st16(xs + c * R + j * PN, v[u]);
-            }
-        }
-        __syncthreads();
-        const int32_t *__restrict__ off = B.off + (int64_t)p * (B.nslices + 1);
-        const uint32_t *__restrict__ ell = B.ell + B.base[p];
-#pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            const int b = gb0 + (int)threadIdx.x + i * BS;
-            if (b >= cd) continue;
-            const int sl = b >> 6;
-            const uint32_t *__restrict__ e = ell + (int64_t)off[sl] * 64 + (b & 63);
-            const int len = off[sl + 1] - off[sl];
-            int k = 0;
-            for (; k + 2 <= len; k += 2) {
-                const uint32_t e0 = e[64 * k], e1 = e[64 * (k + 1)];
-                const T h0 = tab[e0 >> 24], h1 = tab[e1 >> 24];
-                const T *x0 = xs + (e0 & 0xFFFFFFu) * R, *x1 = xs + (e1 & 0xFFFFFFu) * R;
-                P16<T> v0[PPS], v1[PPS];
-#pragma unroll
-                for (int j = 0; j < PPS; ++j) {
-                    v0[j] = ld16(x0 + j * PN);
-                    v1[j] = ld16(x1 + j * PN);
-                }
-#pragma unroll
-                for (int j = 0; j < PPS; ++j)
-#pragma unroll
-                    for (int u = 0; u < PN; ++u) acc[i][j * PN + u] += h0 * v0[j].v[u];
-#pragma unroll
-                for (int j = 0; j < PPS; ++j)
-#pragma unroll
-                    for (int u = 0; u < PN; ++u) acc[i][j * PN + u] += h1 * v1[j].v[u];
-            }
-            if (k < len) {
-                const uint32_t e0 = e[64 * k];
-                const T h0 = tab[e0 >> 24];
-                const T *x0 = xs + (e0 & 0xFFFFFFu) * R;
-#pragma unroll
-                for (int j = 0; j < PPS; ++j) {
-                    const P16<T> v0 = ld16(x0 + j * PN);
-#pragma unroll
-                    for (int u = 0; u < PN; ++u) acc[i][j * PN + u] += h0 * v0.v[u];
-                }
-            }
-        }
-    }
-    double part = 0.0;
-    EpiCoef<T> ec;
-    if (EPI) ec = epi_coef(E);
-#pragma unroll
-    for (int i = 0; i < NC; ++i) {
-        const int b = gb0 + (int)threadIdx.x + i * BS;
-        if (b >= cd) continue;
-        const int64_t o0 = (int64_t)b * cu64 + a0;
-#pragma unroll
-        for (int j = 0; j < npv && j < PPS; ++j) {
-            P16<T> o;
-#pragma unroll
-            for (int u = 0; u < PN; ++u) o.v[u] = acc[i][j * PN + u];
-            if (EPI) {
-                P16<T> vp = {};
-                if (E.vprev) vp = ld16(E.vprev + o0 + j * PN);
-                const P16<T> xv = ld16(A.x + o0 + j * PN);
-#pragma unroll
-                for (int u = 0; u < PN; ++u) {
-                    o.v[u] = epi_w(E, ec, o.v[u], vp.v[u]);
-                    part += (double)o.v[u] * (double)xv.v[u];
-                }
-            }
-            st16(A.y + o0 + j * PN, o);
-        }
-    }
-    if (EPI) {
-        part = quad_wave_sum(part);
-        if ((threadIdx.x & 63) == 0) wpart[threadIdx.x >> 6] = part;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double sum = 0.0;
-            for (int w = 0; w < BS / 64; ++w) sum += wpart[w];
-            E.apart[(int64_t)band * B.ngroups + group] = sum;
         }
     }
 }
@@ -1034,7 +836,7 @@ bool column_fits(const hub_sector *s, int tb, bool epi)
     return (size_t)(cu * tb + 256) * sizeof(T) + (epi ? (size_t)tb * g * sizeof(double) : 0) <= s->lds_max;
 }
 
-// balanced chunks of at most `maxc` (a multiple of 64) for `n` columns
+// balanced chunks of at most `maxc` (a multiple of 64) for `n` rows
 int balanced_chunk(int64_t n, int64_t maxc)
 {
     if (maxc < 64) return 0;
@@ -1043,7 +845,7 @@ int balanced_chunk(int64_t n, int64_t maxc)
     return (int)std::min<int64_t>(maxc, (c + 63) / 64 * 64);
 }
 
-// rows per staged chunk of the row-chunked column pass for TB columns
+// rows per staged chunk of the row-chunked product for TB columns
 template <typename T>
 int chunked_rows(const hub_sector *s, int tb)
 {
@@ -1051,43 +853,18 @@ int chunked_rows(const hub_sector *s, int tb)
     return balanced_chunk(s->spin[0].count, maxr);
 }
 
-// Row-band pass geometry: R rows (slots of 16 or 32 bytes), BS lanes, at most
-// kBandRegs accumulator registers per lane (NC R s / 4 <= 48), so that 16
-// wavefronts per CU fit in the register file without spills.
-constexpr int kBandRegs = 48;
-
-struct BandGeom {
-    int nc = 0, nbands = 0, ngroups = 0, chunk = 0;
-};
-
+// the row-chunked shapes: (TB, QPL) with at most 64 FP32 / 32 FP64 accumulators per lane
 template <typename T>
-bool band_geom(const hub_sector *s, int R, int bs, int chunk_force, BandGeom &g)
+bool chunked_shape_ok(int tb, int qpl)
 {
-    const int64_t cu = s->spin[0].count, cd = s->spin[1].count;
-    if (R * (int)sizeof(T) != 16 && R * (int)sizeof(T) != 32) return false;
-    if (bs != 512 && bs != 1024) return false;
-    const int ncmax = kBandRegs * 4 / (R * (int)sizeof(T));  // 6 for 32-byte slots, 12 for 16-byte
-    const int64_t ng = (cd + (int64_t)bs * ncmax - 1) / ((int64_t)bs * ncmax);
-    const int64_t need = (cd + (int64_t)bs * ng - 1) / ((int64_t)bs * ng);
-    // instantiated column counts per lane: 4 or ncmax
-    g.nc = need <= 4 ? 4 : ncmax;
-    g.ngroups = (int)((cd + (int64_t)bs * g.nc - 1) / ((int64_t)bs * g.nc));
-    g.nbands = (int)((cu + R - 1) / R);
-    // LDS: code table, slots, one partial per wavefront; two workgroups per CU at 512 lanes
-    const int64_t avail = (int64_t)(s->lds_max * bs / 1024) - 256 * (int64_t)sizeof(T) - 16 * 8;
-    const int64_t maxc = avail / (R * (int64_t)sizeof(T)) / 64 * 64;
-    if (chunk_force > 0) {
-        if (chunk_force > maxc && chunk_force > 64) return false;
-        g.chunk = chunk_force;
-    } else {
-        g.chunk = balanced_chunk(cd, maxc);
-    }
-    return g.chunk > 0 && (int64_t)g.nbands * g.ngroups < ((int64_t)1 << 31);
+    if (tb != 1 && tb != 2 && tb != 4) return false;
+    if (qpl != 4 && qpl != 8) return false;
+    return tb * qpl <= (sizeof(T) == 8 ? 8 : 16);
 }
 
 // ---- launchers --------------------------------------------------------------
 
-template <typename T, int TB, int BS, bool XC, bool EPI, bool DN>
+template <typename T, int TB, int BS, bool XC, bool EPI>
 hub_status launch_quad_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const LzEpi<T> &E)
 {
     const SpinTables &U = s->spin[0];
@@ -1098,25 +875,23 @@ hub_status launch_quad_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t st
         set_error("column product: tile does not fit in LDS");
         return HUB_ERR_UNSUPPORTED;
     }
-    HUB_TRY(allow_lds(k_kron_quad<T, TB, BS, XC, EPI, DN>, s->lds_max));
-    hipLaunchKernelGGL((k_kron_quad<T, TB, BS, XC, EPI, DN>), dim3(grid), dim3(BS), lds, st, A, U.sl_off, U.ell_c32,
+    HUB_TRY(allow_lds(k_kron_quad<T, TB, BS, XC, EPI>, s->lds_max));
+    hipLaunchKernelGGL((k_kron_quad<T, TB, BS, XC, EPI>), dim3(grid), dim3(BS), lds, st, A, U.sl_off, U.ell_c32,
                        code_table<T>(U), ntiles, E);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
 
-// column product of shape (tb in 1..3, bs in {512, 1024}, xc); E: fused
-// Lanczos update (one pass only) or NULL; dn: include the H_dn term
+// column product of shape (tb in 1..3, bs in {512, 1024}, xc); E: fused Lanczos update or NULL
 template <typename T>
 hub_status launch_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, int bs, int xc,
-                       const LzEpi<T> *E, bool dn)
+                       const LzEpi<T> *E)
 {
     const LzEpi<T> ne = no_epi<T>();
-#define HUB_QUAD(TBV, BSV, XCV)                                                                        \
-    if (tb == TBV && bs == BSV && xc == XCV) {                                                         \
-        if (!dn) return launch_quad_k<T, TBV, BSV, XCV, false, false>(s, A, st, ne);                  \
-        if (E) return launch_quad_k<T, TBV, BSV, XCV, true, true>(s, A, st, *E);                      \
-        return launch_quad_k<T, TBV, BSV, XCV, false, true>(s, A, st, ne);                            \
+#define HUB_QUAD(TBV, BSV, XCV)                                                              \
+    if (tb == TBV && bs == BSV && xc == XCV) {                                               \
+        if (E) return launch_quad_k<T, TBV, BSV, XCV, true>(s, A, st, *E);                  \
+        return launch_quad_k<T, TBV, BSV, XCV, false>(s, A, st, ne);                        \
     }
     HUB_QUAD(1, 512, 0) HUB_QUAD(1, 512, 1) HUB_QUAD(1, 1024, 0) HUB_QUAD(1, 1024, 1)
     HUB_QUAD(2, 512, 0) HUB_QUAD(2, 512, 1) HUB_QUAD(2, 1024, 0) HUB_QUAD(2, 1024, 1)
@@ -1126,7 +901,7 @@ hub_status launch_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, 
     return HUB_ERR_UNSUPPORTED;
 }
 
-template <typename T, int QPL, int TB, bool DN, bool TM>
+template <typename T, int QPL, int TB>
 hub_status launch_chunked_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const ChunkSet &C)
 {
     constexpr int BSC = 1024;
@@ -1139,88 +914,26 @@ hub_status launch_chunked_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t
     const int nq = (int)(A.cu >> 2);
     const int P = (nq + BSC * QPL - 1) / (BSC * QPL);
     const int ntiles = (A.cd + TB - 1) / TB;
-    HUB_TRY(allow_lds(k_kron_chunked_parts<T, BSC, QPL, TB, DN, TM>, s->lds_max));
+    HUB_TRY(allow_lds(k_kron_chunked_parts<T, BSC, QPL, TB>, s->lds_max));
     const unsigned grid = 8u * (unsigned)P * (unsigned)((ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_kron_chunked_parts<T, BSC, QPL, TB, DN, TM>), dim3(grid), dim3(BSC), lds, st, A, C.off,
-                       C.base, C.ell, code_table<T>(U), C.n, C.rows, (int)U.nslices, P);
+    hipLaunchKernelGGL((k_kron_chunked_parts<T, BSC, QPL, TB>), dim3(grid), dim3(BSC), lds, st, A, C.off, C.base,
+                       C.ell, code_table<T>(U), C.n, C.rows, (int)U.nslices, P);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
 
-// the row-chunked shapes: (TB, QPL) with at most 64 FP32 / 32 FP64 accumulators
 template <typename T>
-bool chunked_shape_ok(int tb, int qpl)
+hub_status launch_chunked(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, int qpl,
+                          const ChunkSet &C)
 {
-    if (tb != 1 && tb != 2 && tb != 4) return false;
-    if (qpl != 4 && qpl != 8) return false;
-    return tb * qpl <= (sizeof(T) == 8 ? 8 : 16);
-}
-
-template <typename T>
-hub_status launch_chunked(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, int qpl, int tm,
-                          bool dn, const ChunkSet &C)
-{
-#define HUB_CH(TBV, QV)                                                                                    \
-    if (tb == TBV && qpl == QV) {                                                                          \
-        if (dn) return launch_chunked_k<T, QV, TBV, true, false>(s, A, st, C);                             \
-        if (tm) return launch_chunked_k<T, QV, TBV, false, true>(s, A, st, C);                             \
-        return launch_chunked_k<T, QV, TBV, false, false>(s, A, st, C);                                    \
-    }
+#define HUB_CH(TBV, QV) \
+    if (tb == TBV && qpl == QV) return launch_chunked_k<T, QV, TBV>(s, A, st, C);
     HUB_CH(1, 4) HUB_CH(1, 8) HUB_CH(2, 4)
     if constexpr (sizeof(T) == 4) {
         HUB_CH(2, 8) HUB_CH(4, 4)
     }
 #undef HUB_CH
     set_error("unsupported row-chunked product shape");
-    return HUB_ERR_UNSUPPORTED;
-}
-
-template <typename T, int R, int NC, int BS, bool EPI>
-hub_status launch_band_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const BandGeom &g,
-                         const ChunkSet &C, const LzEpi<T> &E)
-{
-    const SpinTables &D = s->spin[1];
-    const size_t lds = ((size_t)g.chunk * R + 256) * sizeof(T) + 16 * sizeof(double);
-    if (lds > s->lds_max) {
-        set_error("row-band pass: chunk does not fit in LDS");
-        return HUB_ERR_UNSUPPORTED;
-    }
-    constexpr int LB = 128 / (R * (int)sizeof(T));
-    const int64_t lines = (g.nbands + LB - 1) / LB;
-    const int64_t grid = 8 * ((lines + 7) / 8) * LB * (int64_t)g.ngroups;
-    if (grid >= ((int64_t)1 << 31)) {
-        set_error("row-band pass: too many work items");
-        return HUB_ERR_RANGE;
-    }
-    BandArgs<T> B{C.off, C.base, C.ell, code_table<T>(D), C.n, C.rows, (int)D.nslices, g.nbands, g.ngroups};
-    HUB_TRY(allow_lds(k_kron_dn_band<T, R, NC, BS, EPI>, s->lds_max));
-    hipLaunchKernelGGL((k_kron_dn_band<T, R, NC, BS, EPI>), dim3((unsigned)grid), dim3(BS), lds, st, A, B, E);
-    HUB_HIP(hipGetLastError());
-    return HUB_OK;
-}
-
-template <typename T>
-hub_status launch_band(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int R, int bs, int chunk_force,
-                       const LzEpi<T> *E)
-{
-    BandGeom g;
-    if (!band_geom<T>(s, R, bs, chunk_force, g)) {
-        set_error("unsupported row-band pass shape");
-        return HUB_ERR_UNSUPPORTED;
-    }
-    const ChunkSet *C = nullptr;
-    HUB_TRY(chunk_set(s, HUB_SPIN_DN, g.chunk, &C, st));
-    const LzEpi<T> ne = no_epi<T>();
-    constexpr int R32 = 32 / (int)sizeof(T), R16 = 16 / (int)sizeof(T);
-#define HUB_BAND(RV, NCV, BSV)                                                                             \
-    if (R == RV && g.nc == NCV && bs == BSV) {                                                            \
-        if (E) return launch_band_k<T, RV, NCV, BSV, true>(s, A, st, g, *C, *E);                           \
-        return launch_band_k<T, RV, NCV, BSV, false>(s, A, st, g, *C, ne);                                 \
-    }
-    HUB_BAND(R32, 4, 512) HUB_BAND(R32, 6, 512) HUB_BAND(R32, 4, 1024) HUB_BAND(R32, 6, 1024)
-    HUB_BAND(R16, 4, 512) HUB_BAND(R16, 12, 512) HUB_BAND(R16, 4, 1024) HUB_BAND(R16, 12, 1024)
-#undef HUB_BAND
-    set_error("unsupported row-band pass shape");
     return HUB_ERR_UNSUPPORTED;
 }
 
@@ -1246,7 +959,8 @@ hub_status launch_rows(const hub_sector *s, const MvArgs<T> &A, hipStream_t st)
     return HUB_OK;
 }
 
-// one row per lane: two columns per workgroup when they fit in half of the LDS
+// one row per lane: two columns per workgroup when they fit in half of the LDS;
+// CSR rows when a column does not fit
 template <typename T>
 hub_status launch_rows_auto(const hub_sector *s, const MvArgs<T> &A, hipStream_t st)
 {
@@ -1258,44 +972,32 @@ hub_status launch_rows_auto(const hub_sector *s, const MvArgs<T> &A, hipStream_t
     return HUB_OK;
 }
 
-// Run schedule q (fam, shapes); E: the fused Lanczos update (q must support it)
+// Run schedule q; E: the fused Lanczos update (COLUMNS schedules only)
 template <typename T>
 hub_status launch_sched(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const Sched &q, const LzEpi<T> *E)
 {
+    if (E && q.fam != HUB_SCHED_COLUMNS) {
+        set_error("only the columns schedule has a fused Lanczos update");
+        return HUB_ERR_UNSUPPORTED;
+    }
     switch (q.fam) {
     case HUB_SCHED_COLUMNS:
-        if (q.br > 0) {
-            HUB_TRY(launch_quad<T>(s, A, st, q.tb, q.bs, q.xc, nullptr, false));
-            return launch_band<T>(s, A, st, q.br, q.bbs, q.bch, E);
-        }
-        return launch_quad<T>(s, A, st, q.tb, q.bs, q.xc, E, true);
+        return launch_quad<T>(s, A, st, q.tb, q.bs, q.xc, E);
     case HUB_SCHED_CHUNKED: {
-        if (E && q.br <= 0) {
-            set_error("the one-pass row-chunked product has no fused Lanczos update");
-            return HUB_ERR_UNSUPPORTED;
-        }
         const ChunkSet *C = nullptr;
         HUB_TRY(chunk_set(s, HUB_SPIN_UP, q.crows > 0 ? q.crows : chunked_rows<T>(s, q.tb), &C, st));
-        if (q.br > 0) {
-            HUB_TRY(launch_chunked<T>(s, A, st, q.tb, q.qpl, q.xc, false, *C));
-            return launch_band<T>(s, A, st, q.br, q.bbs, q.bch, E);
-        }
-        return launch_chunked<T>(s, A, st, q.tb, q.qpl, 0, true, *C);
+        return launch_chunked<T>(s, A, st, q.tb, q.qpl, *C);
     }
     case HUB_SCHED_ROWS:
-        if (!E) return launch_rows_auto<T>(s, A, st);
-        break;
+        return launch_rows_auto<T>(s, A, st);
     case HUB_SCHED_CSR:
-        if (!E) {
-            hipLaunchKernelGGL((k_kron_csr<T, 512>), dim3((unsigned)A.cd), dim3(512), 0, st, A);
-            HUB_HIP(hipGetLastError());
-            return HUB_OK;
-        }
-        break;
+        hipLaunchKernelGGL((k_kron_csr<T, 512>), dim3((unsigned)A.cd), dim3(512), 0, st, A);
+        HUB_HIP(hipGetLastError());
+        return HUB_OK;
     default:
         break;
     }
-    set_error("product schedule cannot run here");
+    set_error("product schedule not chosen");
     return HUB_ERR_UNSUPPORTED;
 }
 
@@ -1340,14 +1042,17 @@ hub_status time_candidates(hipStream_t st, int n, F launch, int &best, float &be
     return HUB_OK;
 }
 
-// Candidate column passes of a sector (the part before the H_dn term).
+// Candidate schedules of a sector: whole columns in LDS when one fits (1-3
+// columns per workgroup, 512 or 1024 lanes, XCD or launch tile order; with the
+// fused update, the shapes whose partials also fit), else the row-chunked
+// shapes (1, 2 or 4 columns per work item, 4 or 8 lane-quads per lane).
 template <typename T>
-std::vector<Sched> column_candidates(const hub_sector *s, bool dn, bool epi)
+std::vector<Sched> candidates(const hub_sector *s, bool epi)
 {
     std::vector<Sched> v;
-    if (column_fits<T>(s, 1, epi && dn)) {
+    if (column_fits<T>(s, 1, false)) {
         for (int tb = 1; tb <= 3; ++tb) {
-            if (!column_fits<T>(s, tb, epi && dn)) break;
+            if (!column_fits<T>(s, tb, epi)) break;
             for (int bs : {512, 1024})
                 for (int xc : {0, 1}) {
                     Sched c;
@@ -1360,49 +1065,24 @@ std::vector<Sched> column_candidates(const hub_sector *s, bool dn, bool epi)
         }
         return v;
     }
-    if (epi && dn) return v;  // the one-pass row-chunked product has no epilogue
+    if (epi) return v;
     for (int tb : {1, 2, 4})
-        for (int qpl : {4, 8})
-            for (int tm : {0, 1}) {
-                if (!chunked_shape_ok<T>(tb, qpl)) continue;
-                if (dn && (qpl != 4 || tm != 0)) continue;  // one pass: the measured part-major layout
-                if (chunked_rows<T>(s, tb) <= 0) continue;
-                Sched c;
-                c.fam = HUB_SCHED_CHUNKED;
-                c.tb = tb;
-                c.qpl = qpl;
-                c.xc = tm;
-                c.bs = 1024;
-                c.crows = chunked_rows<T>(s, tb);
-                v.push_back(c);
-            }
-    return v;
-}
-
-template <typename T>
-std::vector<Sched> band_candidates(const hub_sector *s, bool epi)
-{
-    std::vector<Sched> v;
-    for (int R : {32 / (int)sizeof(T), 16 / (int)sizeof(T)})
-        for (int bs : {512, 1024}) {
-            BandGeom g;
-            if (!band_geom<T>(s, R, bs, 0, g)) continue;
-            // the fused update's partials are summed inside the update kernel: at most 65536
-            if (epi && (int64_t)g.nbands * g.ngroups > 65536) continue;
+        for (int qpl : {4, 8}) {
+            if (!chunked_shape_ok<T>(tb, qpl) || chunked_rows<T>(s, tb) <= 0) continue;
             Sched c;
-            c.br = R;
-            c.bbs = bs;
-            c.bch = g.chunk;
+            c.fam = HUB_SCHED_CHUNKED;
+            c.tb = tb;
+            c.qpl = qpl;
+            c.bs = 1024;
+            c.crows = chunked_rows<T>(s, tb);
             v.push_back(c);
         }
     return v;
 }
 
 // Tune the product (epi = false) or the product fused with the Lanczos update
-// (epi = true, apart: its partials buffer) on the caller's x and y: the
-// one-pass schedules and the two-pass ones (best column pass + best row-band
-// pass, each timed on its own).  The epilogue's timing launches read x as
-// v_prev with beta = 0.
+// (epi = true, apart: its partials buffer) on the caller's x and y.  The
+// epilogue's timing launches read x as v_prev with beta = 0.
 template <typename T>
 hub_status tune(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, bool epi, double *apart, Sched &out)
 {
@@ -1418,61 +1098,24 @@ hub_status tune(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, bool ep
         HUB_HIP(hipMemsetAsync(zero, 0, sizeof(double), st));
         E = LzEpi<T>{A.x, zero, apart, (int)(((A.cu >> 2) + 63) / 64), nullptr, 0};
     }
-    Sched best;
-    best.ms = 1e30f;
-    // one pass
-    std::vector<Sched> one = column_candidates<T>(s, true, epi);
-    if (!one.empty()) {
-        int bi = 0;
-        float ms = 0.f;
-        HUB_TRY(time_candidates(st, (int)one.size(),
-                                [&](int c) { return launch_sched<T>(s, A, st, one[(size_t)c], epi ? &E : nullptr); },
-                                bi, ms));
-        best = one[(size_t)bi];
-        best.ms = ms;
-    }
-    // two passes
-    std::vector<Sched> p1 = column_candidates<T>(s, false, false);
-    std::vector<Sched> p2 = band_candidates<T>(s, epi);
-    if (!p1.empty() && !p2.empty()) {
-        int b1 = 0, b2 = 0;
-        float ms1 = 0.f, ms2 = 0.f;
-        HUB_TRY(time_candidates(
-            st, (int)p1.size(),
-            [&](int c) {
-                const Sched &q = p1[(size_t)c];
-                if (q.fam == HUB_SCHED_COLUMNS) return launch_quad<T>(s, A, st, q.tb, q.bs, q.xc, nullptr, false);
-                const ChunkSet *C = nullptr;
-                HUB_TRY(chunk_set(s, HUB_SPIN_UP, q.crows, &C, st));
-                return launch_chunked<T>(s, A, st, q.tb, q.qpl, q.xc, false, *C);
-            },
-            b1, ms1));
-        HUB_TRY(time_candidates(
-            st, (int)p2.size(),
-            [&](int c) {
-                const Sched &q = p2[(size_t)c];
-                return launch_band<T>(s, A, st, q.br, q.bbs, q.bch, epi ? &E : nullptr);
-            },
-            b2, ms2));
-        if (ms1 + ms2 < best.ms) {
-            best = p1[(size_t)b1];
-            best.br = p2[(size_t)b2].br;
-            best.bbs = p2[(size_t)b2].bbs;
-            best.bch = p2[(size_t)b2].bch;
-            best.ms = ms1 + ms2;
-        }
-    }
-    if (best.fam == 0) {
+    std::vector<Sched> c = candidates<T>(s, epi);
+    if (c.empty()) {
         set_error("no product schedule fits this sector");
         return HUB_ERR_UNSUPPORTED;
     }
-    out = best;
+    int bi = 0;
+    float ms = 0.f;
+    HUB_TRY(time_candidates(st, (int)c.size(),
+                            [&](int k) { return launch_sched<T>(s, A, st, c[(size_t)k], epi ? &E : nullptr); }, bi,
+                            ms));
+    out = c[(size_t)bi];
+    out.ms = ms;
     return HUB_OK;
 }
 
 // Tuned schedules are kept per device, dtype and sector structure (dimensions,
-// nonzeros and LDS size; the values of t, U and eps do not change the timing),
-// so sectors of the same lattice share one tuning.
+// nonzeros; the values of t, U and eps do not change the timing), so sectors of
+// the same lattice share one tuning.
 struct ShapeKey {
     int device, dtype;
     int64_t cu, cd, nnz_up, nnz_dn;
@@ -1488,50 +1131,32 @@ std::map<ShapeKey, Sched> g_shapes;
 
 // The schedule of the product (epi = false) or of the product fused with the
 // Lanczos update (epi = true) for aligned vectors: forced, cached, shared by a
-// sector of the same structure, or tuned now.  Tuning runs outside the lock;
-// two threads that tune at once both store a valid schedule.
+// sector of the same structure, or tuned now (under the sector's lock: tuning
+// launches on the caller's stream and may build chunk tables).
 template <typename T>
 hub_status schedule_for(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, bool epi, double *apart, Sched &out)
 {
     const int di = dix<T>();
     const ShapeKey key{s->device, di, (int64_t)A.cu, (int64_t)A.cd, s->spin[0].nnz, s->spin[1].nnz, epi ? 1 : 0};
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->forced[di]) {
-            out = s->sched[di];
-            return HUB_OK;
-        }
-        Sched &q = epi ? s->sched_lz[di] : s->sched[di];
-        if (q.fam == 0) {
-            std::lock_guard<std::mutex> lk2(g_shape_mu);
-            auto it = g_shapes.find(key);
-            if (it != g_shapes.end()) q = it->second;
-        }
-        if (q.fam != 0) {
-            out = q;
-            return HUB_OK;
-        }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->forced[di]) {
+        out = s->sched[di];
+        return HUB_OK;
     }
-    if (!quad_ok(s)) {
-        out = Sched{};
-        out.fam = (s->spin[0].ell_c32 && column_fits<T>(s, 1, false)) ? HUB_SCHED_ROWS : HUB_SCHED_CSR;
-        if (epi) {
-            set_error("no fused Lanczos update for this sector");
-            return HUB_ERR_UNSUPPORTED;
-        }
-    } else {
+    Sched &q = epi ? s->sched_lz[di] : s->sched[di];
+    if (q.fam == 0) {
+        std::lock_guard<std::mutex> lk2(g_shape_mu);
+        auto it = g_shapes.find(key);
+        if (it != g_shapes.end()) q = it->second;
+    }
+    if (q.fam == 0) {
         Sched t;
-        // building chunk tables and timing use the sector's stream and caches under its lock
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            HUB_TRY(tune<T>(s, A, st, epi, apart, t));
-        }
-        out = t;
+        HUB_TRY(tune<T>(s, A, st, epi, apart, t));
         std::lock_guard<std::mutex> lk2(g_shape_mu);
         g_shapes[key] = t;
+        q = t;
     }
-    std::lock_guard<std::mutex> lk(s->mu);
-    (epi ? s->sched_lz[di] : s->sched[di]) = out;
+    out = q;
     return HUB_OK;
 }
 
@@ -1542,9 +1167,11 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
     // the 16-byte-access kernels need 16-byte aligned vectors
     const bool aligned16 = (((uintptr_t)x | (uintptr_t)y) & 15u) == 0;
     if (!aligned16 || !quad_ok(s)) {
-        std::unique_lock<std::mutex> lk(s->mu);
-        const bool csr = s->forced[dix<T>()] && s->sched[dix<T>()].fam == HUB_SCHED_CSR;
-        lk.unlock();
+        bool csr;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            csr = s->forced[dix<T>()] && s->sched[dix<T>()].fam == HUB_SCHED_CSR;
+        }
         Sched q;
         q.fam = csr ? HUB_SCHED_CSR : HUB_SCHED_ROWS;
         return launch_sched<T>(s, A, st, q, nullptr);
@@ -1555,7 +1182,8 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
     return launch_sched<T>(s, A, st, q, nullptr);
 }
 
-// Whether the product fused with the first Lanczos update is available.
+// Whether the product fused with the first Lanczos update is available: the
+// columns schedule with its partials in LDS (forced or tuned).
 template <typename T>
 bool lz_fusable(const hub_sector *s)
 {
@@ -1564,17 +1192,9 @@ bool lz_fusable(const hub_sector *s)
     const int di = dix<T>();
     if (s->forced[di]) {
         const Sched &q = s->sched[di];
-        if (q.nofuse) return false;
-        if (q.br > 0) {
-            // the partials buffer holds at most 65536 band items (matvec_lz_partials)
-            BandGeom g;
-            return band_geom<T>(s, q.br, q.bbs, q.bch, g) && (int64_t)g.nbands * g.ngroups <= 65536 &&
-                   (q.fam == HUB_SCHED_COLUMNS || q.fam == HUB_SCHED_CHUNKED);
-        }
-        return q.fam == HUB_SCHED_COLUMNS && column_fits<T>(s, q.tb, true);
+        return !q.nofuse && q.fam == HUB_SCHED_COLUMNS && column_fits<T>(s, q.tb, true);
     }
-    return !column_candidates<T>(s, true, true).empty() ||
-           (!column_candidates<T>(s, false, false).empty() && !band_candidates<T>(s, true).empty());
+    return column_fits<T>(s, 1, true);
 }
 
 template <typename T>
@@ -1586,14 +1206,8 @@ hub_status run_kron_lz(const hub_sector *s, const void *x, void *w, const void *
     Sched q;
     HUB_TRY(schedule_for<T>(s, A, st, true, apart, q));
     const LzEpi<T> E{(const T *)vprev, beta, apart, (int)(((A.cu >> 2) + 63) / 64), beta_prev, unnorm};
+    *npart = (int64_t)A.cd;
     std::lock_guard<std::mutex> lk(s->mu);
-    if (q.br > 0) {
-        BandGeom g;
-        if (!band_geom<T>(s, q.br, q.bbs, q.bch, g)) return HUB_ERR_UNSUPPORTED;
-        *npart = (int64_t)g.nbands * g.ngroups;
-    } else {
-        *npart = (int64_t)A.cd;
-    }
     return launch_sched<T>(s, A, st, q, &E);
 }
 
@@ -1610,21 +1224,10 @@ bool matvec_lz_available(const hub_sector *s, int dtype)
     return dtype == HUB_F64 ? lz_fusable<double>(s) : lz_fusable<float>(s);
 }
 
-// Upper bound of the fused product's partials (per column, or per row-band
-// work item of a candidate whose count is at most 65536).
+// Partials of the fused product: one per column.
 int64_t matvec_lz_partials(const hub_sector *s)
 {
-    int64_t np = s->spin[1].count;
-    for (int bs : {512, 1024}) {
-        BandGeom g;
-        for (int R : {4, 8})
-            if (band_geom<float>(s, R, bs, 0, g) && (int64_t)g.nbands * g.ngroups <= 65536)
-                np = std::max(np, (int64_t)g.nbands * g.ngroups);
-        for (int R : {2, 4})
-            if (band_geom<double>(s, R, bs, 0, g) && (int64_t)g.nbands * g.ngroups <= 65536)
-                np = std::max(np, (int64_t)g.nbands * g.ngroups);
-    }
-    return np;
+    return s->spin[1].count;
 }
 
 hub_status launch_matvec_lz(const hub_sector *s, int dtype, const void *x, void *w, const void *vprev,
@@ -1656,7 +1259,7 @@ int64_t matvec_bytes(const hub_sector *s, int dtype)
     const int nsp = s->shared_spin ? 1 : 2;
     for (int sp = 0; sp < nsp; ++sp) {
         const SpinTables &T = s->spin[sp];
-        // row pointers, columns, values, basis integers, site energies
+        // row pointers, columns, values, basis integers, site sums
         bytes += 4 * (T.count + 1) + T.nnz * (4 + es) + 4 * T.count + es * T.count;
     }
     return bytes;
@@ -1676,9 +1279,6 @@ hub_status check_forced(const hub_sector *s, const hub_schedule &h, Sched &q)
     q.xc = h.order;
     q.qpl = h.quads_per_lane;
     q.crows = h.chunk_rows;
-    q.br = h.band_rows;
-    q.bbs = h.band_block;
-    q.bch = h.band_chunk;
     q.nofuse = h.no_fused_update;
     auto bad = [](const char *m) {
         set_error(m);
@@ -1690,34 +1290,27 @@ hub_status check_forced(const hub_sector *s, const hub_schedule &h, Sched &q)
         if (q.tb < 1 || q.tb > 3 || (q.bs != 512 && q.bs != 1024) || (q.xc != 0 && q.xc != 1))
             return bad("columns schedule: tile_cols 1..3, block 512 or 1024, order 0 or 1");
         if (!column_fits<T>(s, q.tb, false)) return bad("columns schedule: the tile does not fit in LDS");
+        q.qpl = 0;
+        q.crows = 0;
         break;
     case HUB_SCHED_CHUNKED:
         if (!quad_ok(s)) return bad("chunked schedule needs count_up % 4 == 0 and compact entries");
-        if (!chunked_shape_ok<T>(q.tb, q.qpl) || (q.xc != 0 && q.xc != 1))
-            return bad("chunked schedule: unsupported tile_cols / quads_per_lane / order");
+        if (!chunked_shape_ok<T>(q.tb, q.qpl))
+            return bad("chunked schedule: tile_cols 1, 2 or 4 and quads_per_lane 4 or 8 "
+                       "(tile_cols * quads_per_lane <= 16 in FP32, 8 in FP64)");
         if (q.crows <= 0) q.crows = chunked_rows<T>(s, q.tb);
         if (q.crows <= 0 || q.crows % 4 != 0 || ((size_t)q.crows * q.tb + 256) * sizeof(T) > s->lds_max)
             return bad("chunked schedule: chunk_rows must be a positive multiple of 4 that fits in LDS");
         q.bs = 1024;
+        q.xc = 0;
         break;
     case HUB_SCHED_ROWS:
         if (!column_fits<T>(s, 1, false)) return bad("rows schedule: a column does not fit in LDS");
-        q.br = 0;
         break;
     case HUB_SCHED_CSR:
-        q.br = 0;
         break;
     default:
         return bad("unknown schedule family");
-    }
-    if (q.br > 0) {
-        BandGeom g;
-        if (!band_geom<T>(s, q.br, q.bbs, q.bch, g))
-            return bad("row-band pass: band_rows must give 16- or 32-byte slots, band_block 512 or 1024, "
-                       "band_chunk fit in LDS");
-        q.bch = g.chunk;
-    } else {
-        q.br = 0;
     }
     return HUB_OK;
 }
@@ -1731,9 +1324,6 @@ void to_public(const Sched &q, hub_schedule *h)
     h->order = q.xc;
     h->quads_per_lane = q.qpl;
     h->chunk_rows = q.crows;
-    h->band_rows = q.br;
-    h->band_block = q.bbs;
-    h->band_chunk = q.bch;
     h->no_fused_update = q.nofuse;
     h->ms = q.ms;
 }

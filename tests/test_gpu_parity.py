@@ -445,18 +445,11 @@ def test_param_bilinear_vs_oracle(hub, which):
     del torch
 
 
-def _force(hub, s, dt, fam, band=0, **kw):
-    """Force a product schedule; band = slot bytes (16 or 32) of a row-band pass."""
-    es = 8 if dt == hub.F64 else 4
-    s.set_schedule(dt, fam, band_rows=(band // es if band else 0), **kw)
-
-
-# (family, keyword shape) of the row-chunked column pass, one and two passes
+# shapes of the row-chunked product (columns per work item, lane-quads per lane)
 _CHUNKED_VARIANTS = {
-    "one_pass": dict(tile_cols=1, quads_per_lane=4, order=0),
-    "one_pass_tb2": dict(tile_cols=2, quads_per_lane=4, order=0),
-    "two_pass_r16": dict(tile_cols=2, quads_per_lane=4, order=1, band=16, band_block=1024, band_chunk=64),
-    "two_pass_r32": dict(tile_cols=1, quads_per_lane=8, order=0, band=32, band_block=512, band_chunk=100),
+    "tb1_q4": dict(tile_cols=1, quads_per_lane=4),
+    "tb2_q4": dict(tile_cols=2, quads_per_lane=4),
+    "tb1_q8": dict(tile_cols=1, quads_per_lane=8),
 }
 
 
@@ -464,18 +457,15 @@ _CHUNKED_VARIANTS = {
 @pytest.mark.parametrize("variant", sorted(_CHUNKED_VARIANTS))
 def test_matvec_row_chunked_parity(hub, chunk, variant):
     """The row-chunked product (used when a column exceeds the LDS) forced on
-    small sectors with several chunks and a ragged last chunk, in one pass and
-    with the row-band pass (several band chunks, a ragged last one); products
-    against the oracle, and a solve through the same schedule (the two-pass ones
-    with the Lanczos update fused into the row-band pass)."""
+    small sectors with several chunks and a ragged last chunk, in each shape;
+    products against the oracle, and a solve through the same schedule."""
     import torch
     kw = dict(_CHUNKED_VARIANTS[variant])
-    band = kw.pop("band", 0)
     for m in (W.square_periodic(3, 4, n_up=5, n_dn=4), W.random_graph(10, 17, seed=303, site_U=True, n_up=3)):
         s = hub.Sector(m)
         assert s.count_up % 4 == 0
         for dt in (hub.F64, hub.F32):
-            _force(hub, s, dt, hub.SCHED_CHUNKED, band=band, chunk_rows=chunk, **kw)
+            s.set_schedule(dt, hub.SCHED_CHUNKED, chunk_rows=chunk, **kw)
         osec = oracle.Sector(m)
         xr = oracle.start_vector(5, osec.dim)
         yr = oracle.spmv(osec.csr(), xr)
@@ -496,21 +486,15 @@ def test_matvec_row_chunked_parity(hub, chunk, variant):
 
 def _all_schedules(hub, s, dt):
     """Every schedule family and shape the sector can run in dtype dt."""
-    es = 8 if dt == hub.F64 else 4
     out = []
     for tb in (1, 2, 3):
         for bs in (512, 1024):
             for xc in (0, 1):
                 out.append(dict(family=hub.SCHED_COLUMNS, tile_cols=tb, block=bs, order=xc))
-    for band in (16, 32):
-        for bb in (512, 1024):
-            for bch in (0, 64):
-                out.append(dict(family=hub.SCHED_COLUMNS, tile_cols=2, block=512, order=1, band_rows=band // es,
-                                band_block=bb, band_chunk=bch))
-    for tb, qpl in ((1, 4), (2, 4), (1, 8)):
-        out.append(dict(family=hub.SCHED_CHUNKED, tile_cols=tb, quads_per_lane=qpl, order=0, chunk_rows=128))
-        out.append(dict(family=hub.SCHED_CHUNKED, tile_cols=tb, quads_per_lane=qpl, order=1, chunk_rows=200,
-                        band_rows=16 // es, band_block=512, band_chunk=128))
+    shapes = [(1, 4), (2, 4), (1, 8)] + ([(2, 8), (4, 4)] if dt == hub.F32 else [])
+    for tb, qpl in shapes:
+        for chunk in (128, 200, 0):
+            out.append(dict(family=hub.SCHED_CHUNKED, tile_cols=tb, quads_per_lane=qpl, chunk_rows=chunk))
     out.append(dict(family=hub.SCHED_ROWS))
     out.append(dict(family=hub.SCHED_CSR))
     return out
@@ -519,10 +503,10 @@ def _all_schedules(hub, s, dt):
 @pytest.mark.parametrize("which", ["ring10", "square3x4_n5", "ring12_u3"])
 def test_product_schedules_bitwise(hub, which):
     """Every schedule the tuner may pick or a caller may force (whole columns in
-    LDS with 1-3 columns per workgroup, row-chunked columns, each in one pass or
-    with the row-band pass of 16- or 32-byte slots, one row per lane, CSR rows)
-    computes each element with the same operations in the same order: the
-    products are bit-identical to the tuned one and match the oracle."""
+    LDS with 1-3 columns per workgroup, row-chunked columns in every shape and
+    chunk size, one row per lane, CSR rows) computes each element with the same
+    operations in the same order: the products are bit-identical to the tuned
+    one and match the oracle."""
     import torch
     if which == "ring10":
         m = W.ring(10, U=3.0, n_up=5, n_dn=4).with_params(eps=[0.1 * i for i in range(10)])
@@ -646,11 +630,8 @@ def test_fused_solve_same_for_every_tile_shape(hub):
     tile order) is tuned in each process, so a solve must not depend on it.  On
     a sector whose 91 down-spin columns leave a partial tile of two and of three
     columns, and whose 3432 rows leave a partial group of 64 lane-quads, every
-    forced one-pass shape gives the same energy and step count bit for bit, on
-    both precisions, and that energy is the oracle's.  The two-pass schedules
-    (Lanczos update fused into the row-band pass, whose partials of alpha are
-    per band) agree among themselves bit for bit for every column-pass shape,
-    and with the oracle."""
+    forced shape gives the same energy and step count bit for bit, on both
+    precisions, and that energy is the oracle's."""
     m = W.ring(14, U=4.0, n_up=7, n_dn=2)
     s = hub.Sector(m)
     assert s.count_up % 4 == 0 and s.count_dn % 2 == 1 and s.count_dn % 3 != 0
@@ -658,15 +639,13 @@ def test_fused_solve_same_for_every_tile_shape(hub):
     _, e_ref, _ = oracle.ground_state(m, want_vector=False)
     shapes = [(tb, bs, xc) for tb in (1, 2, 3) for bs in (512, 1024) for xc in (0, 1)]
     for dt, tol, rel in ((hub.F64, 1e-12, 1e-10), (hub.F32, 1e-7, 1e-5)):
-        for band in (0, 16, 32):
-            got = []
-            for tb, bs, xc in shapes:
-                _force(hub, s, dt, hub.SCHED_COLUMNS, band=band, tile_cols=tb, block=bs, order=xc,
-                       band_block=1024)
-                g = s.ground_state(dtype=dt, tol=tol, want_vector=False)
-                got.append((g.e0, g.info["iters"]))
-            assert all(r == got[0] for r in got), (dt, band, list(zip(shapes, got)))
-            assert abs(got[0][0] - e_ref) <= rel * abs(e_ref), (dt, band, got[0], e_ref)
+        got = []
+        for tb, bs, xc in shapes:
+            s.set_schedule(dt, hub.SCHED_COLUMNS, tile_cols=tb, block=bs, order=xc)
+            g = s.ground_state(dtype=dt, tol=tol, want_vector=False)
+            got.append((g.e0, g.info["iters"]))
+        assert all(r == got[0] for r in got), (dt, list(zip(shapes, got)))
+        assert abs(got[0][0] - e_ref) <= rel * abs(e_ref), (dt, got[0], e_ref)
         s.set_schedule(dt, None)
     s.close()
 
@@ -818,8 +797,7 @@ def _variant_model(which):
     return W.square_periodic(3, 4, n_up=5, n_dn=5)
 
 
-@pytest.mark.parametrize("variant", ["csr", "rows", "columns", "columns_two_pass", "chunked",
-                                     "chunked_two_pass"])
+@pytest.mark.parametrize("variant", ["csr", "rows", "columns", "chunked"])
 @pytest.mark.parametrize("which", ["ring10_eps", "ring9", "square3x4_n5"])
 def test_product_variants_match_oracle(hub, variant, which):
     """Every product schedule against the oracle, on a sector with count_up % 4
@@ -833,19 +811,17 @@ def test_product_variants_match_oracle(hub, variant, which):
     bound = _row_abs(osec, xr)
     yr = oracle.spmv(osec.csr(), xr)
     fam = {"csr": hub.SCHED_CSR, "rows": hub.SCHED_ROWS, "columns": hub.SCHED_COLUMNS,
-           "columns_two_pass": hub.SCHED_COLUMNS, "chunked": hub.SCHED_CHUNKED,
-           "chunked_two_pass": hub.SCHED_CHUNKED}[variant]
+           "chunked": hub.SCHED_CHUNKED}[variant]
     kw = dict(tile_cols=2, block=1024, order=1)
-    if variant.startswith("chunked"):
-        kw = dict(tile_cols=2, quads_per_lane=4, order=1, chunk_rows=96)
+    if variant == "chunked":
+        kw = dict(tile_cols=2, quads_per_lane=4, chunk_rows=96)
     for dt, tol in ((hub.F64, 1e-13), (hub.F32, 1e-5)):
-        band = 32 if variant.endswith("two_pass") else 0
         if s.count_up % 4 != 0 and fam in (hub.SCHED_COLUMNS, hub.SCHED_CHUNKED):
             with pytest.raises(hub.HubError) as ei:
-                _force(hub, s, dt, fam, band=band, **kw)
+                s.set_schedule(dt, fam, **kw)
             assert ei.value.status == 1
             continue
-        _force(hub, s, dt, fam, band=band, **kw)
+        s.set_schedule(dt, fam, **kw)
         x = torch.from_numpy(xr).cuda()
         if dt == hub.F32:
             x = x.float()
@@ -874,24 +850,19 @@ def test_many_bonds_use_packed_entries(hub):
     s.close()
 
 
-@pytest.mark.parametrize("variant", ["one_pass_tb1", "one_pass_tb2", "two_pass_tb1_q8", "two_pass_tb2_tile"])
+@pytest.mark.parametrize("variant", ["tb1_q4", "tb2_q4", "tb1_q8"])
 def test_matvec_row_chunked_several_row_parts(hub, variant):
     """count_up = 18564 (ring M=18, N_up=6) is more than one row part of the
-    register-held output (4 x 1024 quads per lane-quad set): parts, chunks of
-    5000 rows, 1 or 2 columns per work item (18 columns: a ragged last tile),
-    parts dispatched in turn or a tile's parts together, one pass or with the
-    row-band pass, and the ragged ends all at once, against the oracle."""
+    register-held output (4096 or 8192 rows per work item): parts, chunks of
+    5000 rows, 1 or 2 columns per work item (18 columns: a ragged last tile) and
+    the ragged ends all at once, against the oracle."""
     import torch
-    kw = {"one_pass_tb1": dict(tile_cols=1, quads_per_lane=4, order=0),
-          "one_pass_tb2": dict(tile_cols=2, quads_per_lane=4, order=0),
-          "two_pass_tb1_q8": dict(tile_cols=1, quads_per_lane=8, order=0, band=16, band_block=1024),
-          "two_pass_tb2_tile": dict(tile_cols=2, quads_per_lane=4, order=1, band=32, band_block=512)}[variant]
-    band = kw.pop("band", 0)
+    kw = _CHUNKED_VARIANTS[variant]
     m = W.ring(18, U=3.0, n_up=6, n_dn=1).with_params(eps=[0.03 * i for i in range(18)])
     s = hub.Sector(m)
     assert s.count_up == 18564
     for dt in (hub.F64, hub.F32):
-        _force(hub, s, dt, hub.SCHED_CHUNKED, band=band, chunk_rows=5000, **kw)
+        s.set_schedule(dt, hub.SCHED_CHUNKED, chunk_rows=5000, **kw)
     osec = oracle.Sector(m)
     xr = oracle.start_vector(41, osec.dim)
     bound = _row_abs(osec, xr)
@@ -910,15 +881,14 @@ def test_matvec_row_chunked_several_row_parts(hub, variant):
 def test_matvec_unaligned_views(hub, which):
     """Vectors that start at an element but not a 16-byte boundary (views into a
     larger buffer) take the one-row-per-lane kernels and give the oracle's product;
-    also with the row-chunked two-pass schedule forced."""
+    also with the row-chunked schedule forced."""
     import torch
     m = _variant_model(which)
     for chunk in (None, 200):
         s = hub.Sector(m)
         if chunk:
             for dt in (hub.F64, hub.F32):
-                _force(hub, s, dt, hub.SCHED_CHUNKED, band=16, tile_cols=1, quads_per_lane=4, order=0,
-                       chunk_rows=chunk)
+                s.set_schedule(dt, hub.SCHED_CHUNKED, tile_cols=1, quads_per_lane=4, chunk_rows=chunk)
         osec = oracle.Sector(m)
         xr = oracle.start_vector(13, osec.dim)
         bound = _row_abs(osec, xr)
