@@ -148,6 +148,21 @@ hub_status hub_start_vector(const hub_sector *sec, int32_t dtype, uint64_t seed,
                             void *dev_out, void *stream);
 
 /*
+ * hub_start_vector for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same bits as hub_start_vector, with the norm's partial
+ * sums kept in a static device array of 1028 doubles (8 KB per device, held
+ * until the process ends) instead of a buffer allocated per call, and no
+ * synchronisation (asynchronous on `stream`).  The array's size does not depend
+ * on the dimension (the norm is summed over a fixed grid of at most 1024
+ * blocks); RANGE if that ever failed to hold.  Every call on a device shares
+ * the array, so calls that overlap on one device (other streams or threads)
+ * race: serialise them.
+ */
+hub_status hub_start_vector_noalloc(const hub_sector *sec, int32_t dtype, uint64_t seed, int32_t normalize,
+                                    void *dev_out, void *stream);
+
+/*
  * y = H x as the Kronecker sum Y = H_up X + X H_dn^T + D o X (Sec. IV A), in
  * `dtype` arithmetic (FP32 accumulates in FP32).  dev_x and dev_y are dim-long
  * device vectors; they must not overlap (INVALID_ARG).  Asynchronous on

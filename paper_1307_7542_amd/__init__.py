@@ -29,7 +29,7 @@ EXPORTED = [
     "hub_last_error", "hub_version", "hub_batch_create", "hub_batch_destroy", "hub_batch_offsets",
     "hub_batch_matvec", "hub_batch_ground_state", "hub_apply_fermion", "hub_lanczos_coefficients",
     "hub_continued_fraction", "hub_greens_function", "hub_sector_create_k0", "hub_k0_layout",
-    "hub_set_schedule", "hub_get_schedule",
+    "hub_set_schedule", "hub_get_schedule", "hub_start_vector_noalloc",
 ]
 
 SCHED_AUTO, SCHED_COLUMNS, SCHED_CHUNKED, SCHED_ROWS, SCHED_CSR = 0, 1, 2, 3, 4
@@ -107,6 +107,7 @@ def lib():
             "hub_hopping_csr": (i32, [P, i32, P, P, P, P]),
             "hub_diagonal": (i32, [P, i32, P, P]),
             "hub_start_vector": (i32, [P, i32, u64, i32, P, P]),
+            "hub_start_vector_noalloc": (i32, [P, i32, u64, i32, P, P]),
             "hub_matvec": (i32, [P, i32, P, P, P]),
             "hub_ground_state": (i32, [P, P, P, P, P, P]),
             "hub_param_bilinear": (i32, [P, P, P, P, P, P, P]),
@@ -295,10 +296,13 @@ class Sector:
                "hub_diagonal")
         return out
 
-    def start_vector(self, seed: int, dtype: int = F64, normalize: bool = True, out=None, stream=None):
+    def start_vector(self, seed: int, dtype: int = F64, normalize: bool = True, out=None, stream=None,
+                     noalloc: bool = False):
+        """noalloc: hub_start_vector_noalloc (static scratch, no allocation, no synchronisation)."""
         out = self.empty(dtype) if out is None else out
-        _check(lib().hub_start_vector(self._h, dtype, ctypes.c_uint64(seed), int(normalize),
-                                      _dev_ptr(out, dtype, self.dim, "out"), _stream(stream)), "hub_start_vector")
+        fn = lib().hub_start_vector_noalloc if noalloc else lib().hub_start_vector
+        _check(fn(self._h, dtype, ctypes.c_uint64(seed), int(normalize), _dev_ptr(out, dtype, self.dim, "out"),
+                  _stream(stream)), "hub_start_vector_noalloc" if noalloc else "hub_start_vector")
         return out
 
     def matvec(self, x, y=None, stream=None):

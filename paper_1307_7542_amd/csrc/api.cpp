@@ -315,6 +315,15 @@ hub_status hub_start_vector(const hub_sector *sec, int32_t dtype, uint64_t seed,
     return HUB_OK;
 }
 
+hub_status hub_start_vector_noalloc(const hub_sector *sec, int32_t dtype, uint64_t seed, int32_t normalize,
+                                    void *dev_out, void *stream)
+{
+    HUB_TRY(check_sector(sec));
+    HUB_TRY(check_dtype(dtype));
+    if (!dev_out) return fail(HUB_ERR_INVALID_ARG, "dev_out is NULL");
+    return start_vector_noalloc(sec, dtype, seed, normalize, dev_out, (hipStream_t)stream);
+}
+
 hub_status hub_matvec(const hub_sector *sec, int32_t dtype, const void *dev_x, void *dev_y, void *stream)
 {
     HUB_TRY(check_sector(sec));

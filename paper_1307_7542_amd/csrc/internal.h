@@ -178,6 +178,9 @@ constexpr int kRedBlock = 256;
 constexpr int kRedGrid = 1024;
 int red_grid(int64_t n);
 hub_status launch_start_vector(int dtype, uint64_t seed, void *out, int64_t n, hipStream_t st);
+// hub_start_vector without allocation: the norm's partials in a static device array
+hub_status start_vector_noalloc(const hub_sector *s, int dtype, uint64_t seed, int normalize, void *out,
+                                hipStream_t st);
 // partial FP64 reductions + final: result written to device double *out
 hub_status launch_dot(int dtype, const void *x, const void *y, int64_t n, double *partial, double *out,
                       int sqrt_result, hipStream_t st);

@@ -12,6 +12,9 @@
 // Vectors of FP32 ("mixed") or FP64 storage; every scalar (alpha, beta, Gram
 // coefficients, norms) is FP64 and every update is evaluated in FP64 and
 // rounded once to the storage type.
+#include <mutex>
+#include <vector>
+
 #include "internal.h"
 
 namespace hub {
@@ -774,6 +777,64 @@ hub_status launch_residual(const double *hpsi, const double *psi, const double *
     hipLaunchKernelGGL(k_resid, dim3(G), dim3(RB), 0, st, hpsi, psi, e, n, partial);
     hipLaunchKernelGGL(k_final, dim3(1), dim3(RB), 0, st, partial, G, out, 1);
     HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+// ---- allocation-free start vector ---------------------------------------------
+//
+// hub_start_vector_noalloc keeps the partial sums of the norm and the norm
+// itself in `scratch` instead of a buffer allocated per call.  Each device
+// holds its own copy of the array until the process ends; its address there
+// comes from hipGetSymbolAddress (host code never passes the array's name to a
+// kernel).  Calls that overlap on one device race on it.
+
+constexpr int kScratchDoubles = kRedGrid + 4;  // the norm, three spare, then the partials
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_addr;  // per device, looked up on first use
+
+hub_status scratch_on_current_device(double **out)
+{
+    int dev = 0;
+    HUB_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_addr[(size_t)dev]) {
+        void *p = nullptr;
+        HUB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_addr[(size_t)dev] = (double *)p;
+    }
+    *out = g_scratch_addr[(size_t)dev];
+    return HUB_OK;
+}
+
+}  // namespace
+
+hub_status start_vector_noalloc(const hub_sector *s, int dtype, uint64_t seed, int normalize, void *out,
+                                hipStream_t st)
+{
+    const int64_t n = s->dim;
+    double *sc = nullptr;
+    if (normalize) {
+        // the partials come from a fixed grid of at most kRedGrid blocks, so any
+        // dimension fits; checked anyway so a change of the grid cannot overrun it
+        if (red_grid(n) + 4 > kScratchDoubles) {
+            set_error("start vector: " + std::to_string(red_grid(n)) + " partial sums exceed the " +
+                      std::to_string(kScratchDoubles - 4) + " of the static scratch");
+            return HUB_ERR_RANGE;
+        }
+        HUB_TRY(scratch_on_current_device(&sc));
+    }
+    HUB_TRY(launch_start_vector(dtype, seed, out, n, st));
+    HUB_TRY(k0_project(s, dtype, out, st));
+    if (normalize) {
+        // every partial and the norm are written before they are read: nothing to clear
+        HUB_TRY(launch_dot(dtype, out, out, n, sc + 4, sc, 1, st));
+        HUB_TRY(launch_convert(dtype, out, dtype, out, n, sc, 1, st));
+    }
     return HUB_OK;
 }
 
