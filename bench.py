@@ -294,8 +294,9 @@ def ladder_time_to_e0(hub, torch, model):
 
 
 def ring14_solves(hub, torch, oracle_e0):
-    """Table IV's chain, U = 2, 4, 8: plain FP64, mixed with full
-    reorthogonalisation and plain mixed Lanczos, time-to-E0 against the oracle."""
+    """Table IV's chain, U = 2, 4, 8: plain FP64, mixed with full and with
+    partial reorthogonalisation (with the orthogonality of the stored basis from
+    the matrix-core Gram), and plain mixed Lanczos; time-to-E0 against the oracle."""
     import workloads as W
     out = {}
     for U in (2, 4, 8):
@@ -308,7 +309,9 @@ def ring14_solves(hub, torch, oracle_e0):
             "fp64_plain": sec.ground_state(dtype=hub.F64, want_vector=False, tol=1e-12, time_kernels=TIME_EVERY,
                                            **tgt),
             "mixed_reorth": sec.ground_state(dtype=hub.F32, reorth=True, refine=True, tol=1e-7,
-                                             time_kernels=TIME_EVERY, **tgt),
+                                             time_kernels=TIME_EVERY, orth_check=True, **tgt),
+            "mixed_partial_reorth": sec.ground_state(dtype=hub.F32, reorth="partial", refine=True, tol=1e-7,
+                                                     time_kernels=TIME_EVERY, orth_check=True, **tgt),
             "mixed_plain": sec.ground_state(dtype=hub.F32, reorth=False, refine=True, tol=1e-7,
                                             time_kernels=TIME_EVERY, **tgt),
         }
@@ -321,9 +324,14 @@ def ring14_solves(hub, torch, oracle_e0):
              "solve_s": {k: v.info["seconds"] for k, v in runs.items()},
              "iters": {k: v.info["iters"] for k, v in runs.items()},
              "rel_err_vs_fp64": {k: abs(v.e0 - e64) / abs(e64) for k, v in runs.items()},
-             "product_ms": {k: v.info["matvec_ms"] / max(1, v.info["matvec_timed"]) for k, v in runs.items()}}
+             "product_ms": {k: v.info["matvec_ms"] / max(1, v.info["matvec_timed"]) for k, v in runs.items()},
+             "reorth_steps": {k: v.info["reorth_steps"] for k, v in runs.items()},
+             "orth_loss_max_abs_QtQ_minus_I": {k: v.info["orth_loss"] for k, v in runs.items()}}
         if r["time_to_e0_s"]["fp64_plain"] > 0:
             r["mixed_plain_over_fp64"] = r["time_to_e0_s"]["mixed_plain"] / r["time_to_e0_s"]["fp64_plain"]
+        if r["time_to_e0_s"]["mixed_plain"] > 0:
+            r["reorth_over_mixed_plain"] = {k: r["time_to_e0_s"][k] / r["time_to_e0_s"]["mixed_plain"]
+                                            for k in ("mixed_reorth", "mixed_partial_reorth")}
         out[f"U={U}"] = r
         sec.close()
     return out

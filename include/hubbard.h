@@ -233,6 +233,11 @@ hub_status hub_get_schedule(const hub_sector *sec, int32_t dtype, int32_t fused,
  *               vectors, repeated in the same step when the first pass kept
  *               less than 1/sqrt(2) of the norm (needs max_iter vectors of
  *               memory); psi from the stored vectors.
+ *   reorth = 2: partial reorthogonalisation (Simon 1984): the same passes, run
+ *               only at the steps where the omega recurrence estimates that
+ *               some |<v_j, v_{k+1}>| reached sqrt(eps) of the stored precision
+ *               (and at the step after), which keeps the basis semi-orthogonal;
+ *               vectors stored as for reorth = 1.
  *   refine = 1: with psi promoted to FP64, an FP64 product gives the Rayleigh
  *               quotient (info.e0_refined, returned as *e0) and the true
  *               residual ||H psi - E psi|| (info.true_residual).
@@ -260,6 +265,7 @@ typedef struct hub_lanczos_opts {
     int32_t time_kernels;  /* > 0: HIP events around every time_kernels-th product launch */
     double e0_target;      /* reference energy for seconds_to_target (used when e0_target_rel > 0) */
     double e0_target_rel;  /* record the first check with |theta - e0_target| <= rel |e0_target| */
+    int32_t orth_check;    /* reorth > 0: measure max |Q^T Q - I| of the stored basis (info.orth_loss) */
 } hub_lanczos_opts;
 
 typedef struct hub_lanczos_info {
@@ -278,6 +284,8 @@ typedef struct hub_lanczos_info {
     int32_t iters_to_target; /* steps when the lowest Ritz value first met the e0 target (-1: never / unused) */
     double seconds_to_target; /* wall time from entry until then (-1: never / unused) */
     int32_t matvec_timed;   /* products whose time is in matvec_ms */
+    int32_t reorth_steps;   /* steps that ran the Gram-Schmidt passes (reorth > 0) */
+    double orth_loss;       /* orth_check: max |Q^T Q - I| over the stored basis (hub_gram), else -1 */
 } hub_lanczos_info;
 
 hub_status hub_ground_state(const hub_sector *sec, const hub_lanczos_opts *opts, double *e0, void *dev_psi,
@@ -422,6 +430,16 @@ typedef struct hub_gf_info {
 hub_status hub_greens_function(const hub_sector *sec, double e0, const void *dev_psi, int32_t site, int32_t spin,
                                int32_t max_steps, int32_t nz, const double *z_re, const double *z_im, double *g_re,
                                double *g_im, double *coef, hub_gf_info *info, void *stream);
+
+/*
+ * G = Q^T Q in FP64 for m n-long device vectors of `dtype` (their device
+ * pointers listed in the host array dev_q): the dense Gram product of the
+ * reorthogonalisation check, on the FP64 matrix cores (FP32 vectors are widened
+ * exactly, so the products are exact and the sums FP64).  host_g receives the
+ * m x m matrix row-major.  Synchronous on `stream`.  UNSUPPORTED for more than
+ * 304 (FP64) or 624 (FP32) vectors.
+ */
+hub_status hub_gram(int32_t dtype, const void *const *dev_q, int32_t m, int64_t n, double *host_g, void *stream);
 
 /* Algorithmic bytes of one product in `dtype`: read x, write y, plus the tables. */
 hub_status hub_matvec_bytes(const hub_sector *sec, int32_t dtype, int64_t *bytes);

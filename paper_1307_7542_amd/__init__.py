@@ -29,7 +29,7 @@ EXPORTED = [
     "hub_last_error", "hub_version", "hub_batch_create", "hub_batch_destroy", "hub_batch_offsets",
     "hub_batch_matvec", "hub_batch_ground_state", "hub_apply_fermion", "hub_lanczos_coefficients",
     "hub_continued_fraction", "hub_greens_function", "hub_sector_create_k0", "hub_k0_layout",
-    "hub_set_schedule", "hub_get_schedule", "hub_start_vector_noalloc",
+    "hub_set_schedule", "hub_get_schedule", "hub_start_vector_noalloc", "hub_gram",
 ]
 
 SCHED_AUTO, SCHED_COLUMNS, SCHED_CHUNKED, SCHED_ROWS, SCHED_CSR = 0, 1, 2, 3, 4
@@ -67,6 +67,7 @@ class LanczosOpts(ctypes.Structure):
         ("dev_start", ctypes.c_void_p), ("vec_dtype", ctypes.c_int32), ("reorth", ctypes.c_int32),
         ("want_vector", ctypes.c_int32), ("refine", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("time_kernels", ctypes.c_int32), ("e0_target", ctypes.c_double), ("e0_target_rel", ctypes.c_double),
+        ("orth_check", ctypes.c_int32),
     ]
 
 
@@ -77,7 +78,7 @@ class LanczosInfo(ctypes.Structure):
         ("residual", ctypes.c_double), ("true_residual", ctypes.c_double), ("seconds", ctypes.c_double),
         ("seconds_to_e0", ctypes.c_double), ("matvec_ms", ctypes.c_double), ("matvec_bytes", ctypes.c_int64),
         ("iters_to_target", ctypes.c_int32), ("seconds_to_target", ctypes.c_double),
-        ("matvec_timed", ctypes.c_int32),
+        ("matvec_timed", ctypes.c_int32), ("reorth_steps", ctypes.c_int32), ("orth_loss", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -108,6 +109,7 @@ def lib():
             "hub_diagonal": (i32, [P, i32, P, P]),
             "hub_start_vector": (i32, [P, i32, u64, i32, P, P]),
             "hub_start_vector_noalloc": (i32, [P, i32, u64, i32, P, P]),
+            "hub_gram": (i32, [i32, P, i32, i64, P, P]),
             "hub_matvec": (i32, [P, i32, P, P, P]),
             "hub_ground_state": (i32, [P, P, P, P, P, P]),
             "hub_param_bilinear": (i32, [P, P, P, P, P, P, P]),
@@ -313,18 +315,22 @@ class Sector:
                                 _dev_ptr(y, dtype, self.dim, "y"), _stream(stream)), "hub_matvec")
         return y
 
-    def ground_state(self, *, dtype: int = F64, reorth: bool = False, want_vector: bool = True,
+    def ground_state(self, *, dtype: int = F64, reorth=False, want_vector: bool = True,
                      refine: bool = False, max_iter: int = 400, tol: float = 0.0, seed: int = 7542,
                      start=None, check_every: int = 1, time_kernels: int = 0, psi=None,
                      stream=None, allow_not_converged: bool = False, e0_target: Optional[float] = None,
-                     e0_target_rel: float = 0.0) -> GroundState:
+                     e0_target_rel: float = 0.0, orth_check: bool = False) -> GroundState:
+        """reorth: False / 0 plain recurrence, True / 1 / "full" full, 2 / "partial" partial
+        reorthogonalisation (Simon's omega recurrence)."""
+        ro = {"full": 1, "partial": 2}.get(reorth, reorth) if isinstance(reorth, str) else int(reorth)
         want = want_vector or refine
         if want and psi is None:
             psi = self.empty(F64)
         o = LanczosOpts(max_iter, tol, seed,
                         _dev_ptr(start, F64, self.dim, "start") if start is not None else None,
-                        dtype, int(reorth), int(want_vector), int(refine), check_every, int(time_kernels),
-                        float(e0_target or 0.0), float(e0_target_rel if e0_target is not None else 0.0))
+                        dtype, ro, int(want_vector), int(refine), check_every, int(time_kernels),
+                        float(e0_target or 0.0), float(e0_target_rel if e0_target is not None else 0.0),
+                        int(orth_check))
         info = LanczosInfo()
         e0 = ctypes.c_double()
         allow = (HUB_OK, HUB_ERR_NOT_CONVERGED) if allow_not_converged else (HUB_OK,)
@@ -479,3 +485,17 @@ class Batch:
 
 def version() -> str:
     return lib().hub_version().decode()
+
+
+def gram(vectors, stream=None) -> np.ndarray:
+    """G = Q^T Q (FP64, on the FP64 matrix cores) of equal-length contiguous CUDA
+    vectors of one dtype (hub_gram)."""
+    torch = _torch()
+    if not vectors:
+        return np.zeros((0, 0))
+    dt = F64 if vectors[0].dtype == torch.float64 else F32
+    n = vectors[0].numel()
+    ptrs = (ctypes.c_void_p * len(vectors))(*[_dev_ptr(v, dt, n, "vector").value for v in vectors])
+    out = np.zeros((len(vectors), len(vectors)), dtype=np.float64)
+    _check(lib().hub_gram(dt, ptrs, len(vectors), n, _ptr(out), _stream(stream)), "hub_gram")
+    return out

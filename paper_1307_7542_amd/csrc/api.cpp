@@ -354,6 +354,39 @@ hub_status hub_get_schedule(const hub_sector *sec, int32_t dtype, int32_t fused,
     return get_schedule(sec, dtype, fused, out);
 }
 
+hub_status hub_gram(int32_t dtype, const void *const *dev_q, int32_t m, int64_t n, double *host_g, void *stream)
+{
+    HUB_TRY(check_dtype(dtype));
+    if (m < 0 || n < 0) return fail(HUB_ERR_INVALID_ARG, "negative size");
+    if (m == 0) return HUB_OK;
+    if (!dev_q || !host_g) return fail(HUB_ERR_INVALID_ARG, "NULL argument");
+    for (int i = 0; i < m; ++i)
+        if (!dev_q[i]) return fail(HUB_ERR_INVALID_ARG, "NULL vector pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const int ld = 16 * ((m + 15) / 16);
+    void **dq = nullptr;
+    double *dG = nullptr;
+    struct Free {
+        void *a = nullptr, *b = nullptr;
+        ~Free()
+        {
+            (void)hipFree(a);
+            (void)hipFree(b);
+        }
+    } fr;
+    HUB_HIP(hipMalloc((void **)&dq, sizeof(void *) * (size_t)m));
+    fr.a = dq;
+    HUB_HIP(hipMalloc((void **)&dG, sizeof(double) * (size_t)ld * ld));
+    fr.b = dG;
+    HUB_HIP(hipMemcpyAsync(dq, dev_q, sizeof(void *) * (size_t)m, hipMemcpyHostToDevice, st));
+    HUB_TRY(gram_mfma(dtype, (const void *const *)dq, m, n, dG, ld, st));
+    std::vector<double> G((size_t)ld * ld);
+    HUB_HIP(hipMemcpy(G.data(), dG, sizeof(double) * G.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) host_g[(size_t)i * m + j] = G[(size_t)i * ld + j];
+    return HUB_OK;
+}
+
 hub_status hub_matvec_bytes(const hub_sector *sec, int32_t dtype, int64_t *bytes)
 {
     if (!sec) return fail(HUB_ERR_INVALID_ARG, "sector is NULL");
@@ -369,7 +402,7 @@ hub_status hub_ground_state(const hub_sector *sec, const hub_lanczos_opts *opts,
     HUB_TRY(check_sector(sec));
     if (!opts) return fail(HUB_ERR_INVALID_ARG, "opts is NULL");
     HUB_TRY(check_dtype(opts->vec_dtype));
-    if (opts->reorth != 0 && opts->reorth != 1) return fail(HUB_ERR_INVALID_ARG, "reorth must be 0 or 1");
+    if (opts->reorth < 0 || opts->reorth > 2) return fail(HUB_ERR_INVALID_ARG, "reorth must be 0, 1 or 2");
     if (dev_psi && !(opts->want_vector || opts->refine))
         return fail(HUB_ERR_INVALID_ARG, "dev_psi given but want_vector is 0");
     return ground_state(sec, opts, e0, dev_psi, (hipStream_t)stream, info);

@@ -221,6 +221,14 @@ hub_status launch_gram(int dtype, const void *const *dQ, int k, void *w, int64_t
                        double *coef, hipStream_t st, const int *skip, double *npart = nullptr);
 int gram_norm_parts(int64_t n);
 hub_status launch_dgks_flag(const double *before, const double *after, int *flag, hipStream_t st);
+// partial reorthogonalisation: omega recurrence and pass flags (state: int[4], see vec.hip)
+hub_status launch_pro_omega(const double *alpha, const double *beta, const double *beta_t, const double *om_prev,
+                            const double *om_cur, double *om_next, int k, double eps, int *state, hipStream_t st);
+hub_status launch_pro_flag2(const double *before, const double *after, int *state, hipStream_t st);
+hub_status launch_pro_beta(const int *state, const double *beta_t, double *beta, hipStream_t st);
+// G = Q^T Q (FP64, ld x ld with ld >= 16 ceil(m / 16), both triangles) of m
+// device vectors (device pointer array dq) on the FP64 matrix cores; synchronous
+hub_status gram_mfma(int dtype, const void *const *dq, int m, int64_t n, double *dG, int ld, hipStream_t st);
 hub_status launch_psi_from_basis(int dtype, const void *const *dQ, int k, const double *ycoef, double *psi,
                                  int64_t n, hipStream_t st);
 hub_status launch_normalize_sign(double *psi, int64_t n, double *partial, double *scal, hipStream_t st);

@@ -203,7 +203,8 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     if ((int64_t)max_iter > n) max_iter = (int)n;
     const double tol = o->tol > 0 ? o->tol : (dt == HUB_F64 ? 1e-12 : 1e-7);
     const int check_every = o->check_every > 0 ? o->check_every : 1;
-    const bool reorth = o->reorth != 0;
+    const bool reorth = o->reorth != 0;          // the Lanczos vectors are stored
+    const bool partial_ro = o->reorth == 2;      // Gram-Schmidt only where the omega estimate asks for it
     const bool want_vec = o->want_vector != 0 || o->refine != 0;
     // k = 0 sectors with short-period rows: the vectors live in the consistent
     // subspace; rounding noise outside it is removed from every new vector (the
@@ -255,8 +256,22 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     HUB_TRY(mem.alloc((void **)&dQ, sizeof(void *) * (size_t)kmax));
     double *d_coef = nullptr;  // Gram coefficients against the stored vectors
     HUB_TRY(mem.alloc((void **)&d_coef, sizeof(double) * (size_t)kmax));
-    int *d_flag = nullptr;  // skip flag of the second Gram-Schmidt pass
-    HUB_TRY(mem.alloc((void **)&d_flag, sizeof(int) * 4));
+    int *d_flag = nullptr;  // skip flag of the second Gram-Schmidt pass; [4..8): partial reorthogonalisation state
+    HUB_TRY(mem.alloc((void **)&d_flag, sizeof(int) * 8));
+    HUB_HIP(hipMemsetAsync(d_flag, 0, sizeof(int) * 8, st));
+    int *d_pro = d_flag + 4;
+    double *om[3] = {nullptr, nullptr, nullptr};  // omega_{k-1}, omega_k, omega_{k+1}
+    if (partial_ro) {
+        double *omb = nullptr;
+        HUB_TRY(mem.alloc((void **)&omb, sizeof(double) * 3 * (size_t)(kmax + 2)));
+        HUB_HIP(hipMemsetAsync(omb, 0, sizeof(double) * 3 * (size_t)(kmax + 2), st));
+        const double one = 1.0;
+        for (int i = 0; i < 3; ++i) om[i] = omb + (size_t)i * (kmax + 2);
+        HUB_HIP(hipMemcpyAsync(om[1], &one, sizeof(double), hipMemcpyHostToDevice, st));  // omega_{0,0} = 1
+        HUB_HIP(hipStreamSynchronize(st));
+    }
+    // unit roundoff of the stored vectors
+    const double eps_store = (dt == HUB_F64) ? DBL_EPSILON / 2 : FLT_EPSILON / 2;
 
     void *W = nullptr, *Va = nullptr, *Vb = nullptr;
     HUB_TRY(mem.alloc(&W, es * (size_t)n));
@@ -482,20 +497,36 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
             // runs only when the first removed more than 1 - 1/sqrt(2) of the norm
             HUB_TRY(lz_b(v, d_alpha + k, d_misc + 8));
             HUB_HIP(hipMemcpyAsync(dQ, Q.data(), sizeof(void *) * Q.size(), hipMemcpyHostToDevice, st));
+            // partial: the omega estimate decides (on the device) whether this step
+            // runs the passes; full: the first pass always runs
+            const int *skip1 = nullptr, *skip2 = d_flag;
+            if (partial_ro) {
+                HUB_TRY(launch_pro_omega(d_alpha, d_beta, d_misc + 8, om[0], om[1], om[2], k, eps_store, d_pro, st));
+                skip1 = d_pro + 1;
+                skip2 = d_pro + 3;
+            }
             // the norms come from the update's partials: after the first pass, and
             // (second pass run or skipped) after the second
             const int nq = gram_norm_parts(n);
-            HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, nullptr,
+            HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, skip1,
                                 wpart));
             HUB_TRY(launch_sum(wpart, nq, d_misc + 9, st, 1));
-            HUB_TRY(launch_dgks_flag(d_misc + 8, d_misc + 9, d_flag, st));
-            HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, d_flag,
+            if (partial_ro) HUB_TRY(launch_pro_flag2(d_misc + 8, d_misc + 9, d_pro, st));
+            else HUB_TRY(launch_dgks_flag(d_misc + 8, d_misc + 9, d_flag, st));
+            HUB_TRY(launch_gram(dt, (const void *const *)dQ, (int)Q.size(), W, n, partial, d_coef, st, skip2,
                                 wpart));
             if (reproject) {
                 HUB_TRY(k0_project(s, dt, W, st));
                 HUB_TRY(launch_dot(dt, W, W, n, partial, d_beta + k + 1, 1, st));
             } else {
                 HUB_TRY(launch_sum(wpart, nq, d_beta + k + 1, st, 1));
+                if (partial_ro) HUB_TRY(launch_pro_beta(d_pro, d_misc + 8, d_beta + k + 1, st));
+            }
+            if (partial_ro) {
+                double *o0 = om[0];
+                om[0] = om[1];
+                om[1] = om[2];
+                om[2] = o0;
             }
         } else {
             // beta_{k+1} is formed from the partials by the normalisation below
@@ -541,6 +572,30 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         v = vn;
     }
     inf.iters = m_final;
+    inf.orth_loss = -1.0;
+    inf.reorth_steps = 0;
+    if (reorth) {
+        int ph[8] = {0};
+        HUB_HIP(hipMemcpyAsync(ph, d_flag, sizeof(ph), hipMemcpyDeviceToHost, st));
+        HUB_HIP(hipStreamSynchronize(st));
+        inf.reorth_steps = partial_ro ? ph[6] : m_final;
+        // max |Q^T Q - I| over the stored basis, from the FP64 matrix-core Gram
+        const int mq = std::min<int>((int)Q.size(), m_final);
+        if (o->orth_check && mq > 0 && mq <= 304) {
+            const int ld = 16 * ((mq + 15) / 16);
+            double *dG = nullptr;
+            HUB_TRY(mem.alloc((void **)&dG, sizeof(double) * (size_t)ld * ld));
+            HUB_HIP(hipMemcpyAsync(dQ, Q.data(), sizeof(void *) * mq, hipMemcpyHostToDevice, st));
+            HUB_TRY(gram_mfma(dt, (const void *const *)dQ, mq, n, dG, ld, st));
+            std::vector<double> G((size_t)ld * ld);
+            HUB_HIP(hipMemcpy(G.data(), dG, sizeof(double) * G.size(), hipMemcpyDeviceToHost));
+            double loss = 0.0;
+            for (int i = 0; i < mq; ++i)
+                for (int j = 0; j < mq; ++j)
+                    loss = std::max(loss, std::fabs(G[(size_t)i * ld + j] - (i == j ? 1.0 : 0.0)));
+            inf.orth_loss = loss;
+        }
+    }
     inf.converged = converged ? 1 : 0;
     inf.breakdown = breakdown ? 1 : 0;
     inf.e0_ritz = theta;

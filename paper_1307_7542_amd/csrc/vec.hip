@@ -441,6 +441,77 @@ __global__ void k_dgks_flag(const double *__restrict__ before, const double *__r
     if (threadIdx.x == 0 && blockIdx.x == 0) *flag = (*after > 0.70710678118654752 * *before) ? 1 : 0;
 }
 
+// ---- partial reorthogonalisation (Simon, Math. Comp. 42 (1984) 115) ------------
+// The rounding errors of the Lanczos step obey a recurrence that estimates
+// om_{k+1,j} ~ <v_j, v_{k+1}> from alpha and beta alone:
+//   beta_{k+1} om_{k+1,j} = beta_{j+1} om_{k,j+1} + (alpha_j - alpha_k) om_{k,j}
+//                         + beta_j om_{k,j-1} - beta_k om_{k-1,j} + theta_{k,j},
+// om_{k,k} = 1, with theta_{k,j} = eps (beta_{j+1} + beta_{k+1}) added in the
+// direction that increases |om| (an over-estimate of the rounding term).  A
+// Gram-Schmidt pass against the stored vectors runs when some |om_{k+1,j}|,
+// j < k, reaches sqrt(eps) -- the vectors then stay semi-orthogonal, which keeps
+// the Ritz values as accurate as full reorthogonalisation -- and once more at
+// the next step, since the recurrence couples two consecutive steps; om_{k+1,.}
+// is reset to eps after a pass.  beta_t is ||w|| before any pass.
+// state[0]: the pass is forced at this step; state[1]: skip flag of the first
+// pass (1 = skip); state[2]: passes run so far; state[3]: skip flag of the second
+// pass (set by k_pro_flag2).
+__global__ __launch_bounds__(256) void k_pro_omega(const double *__restrict__ alpha, const double *__restrict__ beta,
+                                                   const double *__restrict__ beta_t,
+                                                   const double *__restrict__ om_prev,
+                                                   const double *__restrict__ om_cur, double *__restrict__ om_next,
+                                                   int k, double eps, int *__restrict__ state)
+{
+    __shared__ double smax[256];
+    __shared__ int srun;
+    const double bk1 = *beta_t, bk = beta[k], ak = alpha[k];
+    double mx = 0.0;
+    for (int j = (int)threadIdx.x; j < k; j += 256) {
+        const double om_j1 = (j + 1 == k) ? 1.0 : om_cur[j + 1];
+        const double om_prev_j = (j + 1 == k) ? 1.0 : om_prev[j];
+        double t = beta[j + 1] * om_j1 + (alpha[j] - ak) * om_cur[j] - bk * om_prev_j;
+        if (j > 0) t += beta[j] * om_cur[j - 1];
+        const double th = eps * (beta[j + 1] + bk1);
+        t += (t >= 0.0) ? th : -th;
+        const double o = bk1 > 0.0 ? t / bk1 : 1.0;
+        om_next[j] = o;
+        mx = fmax(mx, fabs(o));
+    }
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int forced = state[0];
+        const int run = (forced || smax[0] >= sqrt(eps)) ? 1 : 0;
+        state[1] = run ? 0 : 1;
+        state[0] = (run && !forced) ? 1 : 0;
+        state[2] += run;
+        om_next[k] = eps;  // local orthogonality after the explicit alpha subtraction
+        om_next[k + 1] = 1.0;
+        srun = run;
+    }
+    __syncthreads();
+    if (srun)
+        for (int j = (int)threadIdx.x; j < k; j += 256) om_next[j] = eps;
+}
+
+// second pass of a partial reorthogonalisation step: run only when the first
+// ran and kept less than 1/sqrt(2) of the norm (the DGKS test)
+__global__ void k_pro_flag2(const double *__restrict__ before, const double *__restrict__ after, int *__restrict__ state)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        state[3] = (state[1] || *after > 0.70710678118654752 * *before) ? 1 : 0;
+}
+
+// beta_{k+1}: the norm after the passes, or ||w|| when none ran
+__global__ void k_pro_beta(const int *__restrict__ state, const double *__restrict__ beta_t, double *__restrict__ beta)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0 && state[1]) *beta = *beta_t;
+}
+
 template <typename T>
 __global__ void k_psi_basis(const T *const *__restrict__ Q, int k, const double *__restrict__ y,
                             double *__restrict__ psi, int64_t n)
@@ -739,6 +810,29 @@ hub_status launch_gram(int dtype, const void *const *dQ, int k, void *w, int64_t
 hub_status launch_dgks_flag(const double *before, const double *after, int *flag, hipStream_t st)
 {
     hipLaunchKernelGGL(k_dgks_flag, dim3(1), dim3(64), 0, st, before, after, flag);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_pro_omega(const double *alpha, const double *beta, const double *beta_t, const double *om_prev,
+                            const double *om_cur, double *om_next, int k, double eps, int *state, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pro_omega, dim3(1), dim3(256), 0, st, alpha, beta, beta_t, om_prev, om_cur, om_next, k, eps,
+                       state);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_pro_flag2(const double *before, const double *after, int *state, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pro_flag2, dim3(1), dim3(64), 0, st, before, after, state);
+    HUB_HIP(hipGetLastError());
+    return HUB_OK;
+}
+
+hub_status launch_pro_beta(const int *state, const double *beta_t, double *beta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pro_beta, dim3(1), dim3(64), 0, st, state, beta_t, beta);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
