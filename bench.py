@@ -47,6 +47,8 @@ def parse():
                     help="profiling aid: copy a buffer of this many MiB three times (counter calibration)")
     ap.add_argument("--lanczos-only", type=str, default="",
                     help="run one FP64 and one mixed solve of the named workload and exit (counter runs)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 64-sector impurity batch measurement and print it")
     ap.add_argument("--matvec-only", type=str, default="",
                     help="profiling aid: 'workload:count[:dtype]' runs count back-to-back products "
                          "(dtype f32 or f64; both by default) in the tuned schedule")
@@ -120,7 +122,11 @@ def square_mixed_gradients(hub, torch, model):
 def batch_timing(hub, torch, count=64):
     """The synthetic impurity-model batch (one DMFT step's exact-diagonalisation
     solves): one batched FP64 solve and one FP32 solve with FP64 refinement,
-    against the same sectors solved one after another; plus one batched product."""
+    against the same sectors solved one after another (and the batch with its
+    steps launched eagerly instead of replayed from the captured graphs); plus
+    the batched product in both precisions."""
+    import numpy as np
+
     import workloads as W
     models = W.aim_batch(count)
     secs = [hub.Sector(m) for m in models]
@@ -138,6 +144,10 @@ def batch_timing(hub, torch, count=64):
     torch.cuda.synchronize()
     t_m = time.perf_counter() - t0
     t0 = time.perf_counter()
+    e_e, _, _, info_e = batch.ground_state(dtype=hub.F64, graph=False, **kw)
+    torch.cuda.synchronize()
+    t_e = time.perf_counter() - t0
+    t0 = time.perf_counter()
     e_s = [s.ground_state(dtype=hub.F64, want_vector=False, **kw).e0 for s in secs]
     torch.cuda.synchronize()
     t_s = time.perf_counter() - t0
@@ -153,14 +163,29 @@ def batch_timing(hub, torch, count=64):
     torch.cuda.synchronize()
     mv_ms = ev0.elapsed_time(ev1) / 10
     mv_bytes = sum(s.matvec_bytes(hub.F64) for s in secs)
+    x32, y32 = batch.empty(hub.F32), batch.empty(hub.F32)
+    x32.fill_(1.0)
+    batch.matvec(x32, y32)
+    ev0.record()
+    for _ in range(10):
+        batch.matvec(x32, y32)
+    ev1.record()
+    torch.cuda.synchronize()
+    mv32_ms = ev0.elapsed_time(ev1) / 10
+    mv32_bytes = sum(s.matvec_bytes(hub.F32) for s in secs)
     out = {"sectors": count, "total_dim": batch.total, "max_dim": int(max(s.dim for s in secs)),
            "batch_fp64_s": t_b, "batch_f32_refined_s": t_m, "sequential_fp64_s": t_s,
            "batch_speedup_fp64": t_s / t_b, "steps": info["steps"], "graph_replays": info["graph_replays"],
-           "max_iters": int(it_b.max()), "tile_columns": info["tile_columns"], "block_size": info["block_size"],
+           "max_iters": int(it_b.max()), "rows_per_lane": info["rows_per_lane"], "cols_per_lane": info["cols_per_lane"],
+           "block_size": info["block_size"],
            "max_abs_diff_batch_vs_sequential": float(max(abs(a - b) for a, b in zip(e_b, e_s))),
            "max_abs_diff_refined_vs_fp64": float(max(abs(a - b) for a, b in zip(e_m, e_b))),
-           "product_f64_ms": mv_ms, "product_f64_GBps": mv_bytes / mv_ms / 1e6}
-    del x, y
+           "product_f64_ms": mv_ms, "product_f64_GBps": mv_bytes / mv_ms / 1e6,
+           "product_f64_frac": mv_bytes / mv_ms / 1e6 / HBM_PEAK_GBPS,
+           "product_f32_ms": mv32_ms, "product_f32_GBps": mv32_bytes / mv32_ms / 1e6,
+           "step_ms_graph_fp64": 1e3 * t_b / info["steps"], "step_ms_eager_fp64": 1e3 * t_e / info_e["steps"],
+           "eager_equals_graph": bool(np.array_equal(e_b, e_e))}
+    del x, y, x32, y32
     batch.close()
     for s in secs:
         s.close()
@@ -372,6 +397,10 @@ def main():
             torch.cuda.synchronize()
             print(f"{name} lanczos dtype={'f64' if dt == F64 else 'f32'} iters={g.info['iters']}", flush=True)
         sec.close()
+        return
+
+    if args.batch_only:
+        print(json.dumps({"aim_batch64": batch_timing(hub, torch)}), flush=True)
         return
 
     if args.matvec_only:

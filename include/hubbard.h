@@ -266,6 +266,9 @@ typedef struct hub_lanczos_opts {
     double e0_target;      /* reference energy for seconds_to_target (used when e0_target_rel > 0) */
     double e0_target_rel;  /* record the first check with |theta - e0_target| <= rel |e0_target| */
     int32_t orth_check;    /* reorth > 0: measure max |Q^T Q - I| of the stored basis (info.orth_loss) */
+    int32_t batch_no_graph; /* hub_batch_ground_state only: 1 launches every step's kernels eagerly
+                               instead of replaying the captured step graphs (same kernels, same order,
+                               same results); ignored by hub_ground_state */
 } hub_lanczos_opts;
 
 typedef struct hub_lanczos_info {
@@ -331,8 +334,9 @@ typedef struct hub_batch_info {
     int32_t steps;            /* lockstep Lanczos steps executed (max over sectors; includes the
                                  group run while the last convergence test was on the host) */
     int32_t graph_replays;    /* steps executed by replaying a captured step or group graph */
-    int32_t tile_columns;     /* tuned columns per workgroup of the product */
+    int32_t rows_per_lane;    /* tuned product: rows each lane has in flight at once */
     int32_t block_size;       /* tuned workgroup size of the product */
+    int32_t cols_per_lane;    /* tuned product: columns each lane forms from one H_up entry stream */
     double seconds;           /* wall time of the call */
     double tune_seconds;      /* part of it spent tuning (first call per dtype) */
 } hub_batch_info;

@@ -67,7 +67,7 @@ class LanczosOpts(ctypes.Structure):
         ("dev_start", ctypes.c_void_p), ("vec_dtype", ctypes.c_int32), ("reorth", ctypes.c_int32),
         ("want_vector", ctypes.c_int32), ("refine", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("time_kernels", ctypes.c_int32), ("e0_target", ctypes.c_double), ("e0_target_rel", ctypes.c_double),
-        ("orth_check", ctypes.c_int32),
+        ("orth_check", ctypes.c_int32), ("batch_no_graph", ctypes.c_int32),
     ]
 
 
@@ -420,8 +420,8 @@ def continued_fraction(alpha, beta, steps: int, norm2: float, w) -> np.ndarray:
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [
-        ("steps", ctypes.c_int32), ("graph_replays", ctypes.c_int32), ("tile_columns", ctypes.c_int32),
-        ("block_size", ctypes.c_int32), ("seconds", ctypes.c_double), ("tune_seconds", ctypes.c_double),
+        ("steps", ctypes.c_int32), ("graph_replays", ctypes.c_int32), ("rows_per_lane", ctypes.c_int32),
+        ("block_size", ctypes.c_int32), ("cols_per_lane", ctypes.c_int32), ("seconds", ctypes.c_double), ("tune_seconds", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -469,10 +469,11 @@ class Batch:
 
     def ground_state(self, *, dtype: int = F64, want_vector: bool = False, refine: bool = False,
                      max_iter: int = 400, tol: float = 0.0, seed: int = 7542, check_every: int = 5,
-                     stream=None, allow_not_converged: bool = False):
+                     stream=None, allow_not_converged: bool = False, graph: bool = True):
         want = want_vector or refine
         psi = self.empty(F64) if want else None
-        o = LanczosOpts(max_iter, tol, seed, None, dtype, 0, int(want_vector), int(refine), check_every, 0, 0.0, 0.0)
+        o = LanczosOpts(max_iter, tol, seed, None, dtype, 0, int(want_vector), int(refine), check_every, 0, 0.0, 0.0,
+                        0, int(not graph))
         e0 = np.zeros(len(self.sectors))
         it = np.zeros(len(self.sectors), dtype=np.int32)
         info = BatchInfo()

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <vector>
 
 #include "internal.h"
@@ -45,6 +46,7 @@ struct BDesc {
     T U;
     int32_t uniform;
     uint32_t umask;
+    uint64_t cu_magic;  // ceil(2^32 / cu): e / cu = (e * cu_magic) >> 32 for e * cu < 2^32
 };
 
 template <typename T>
@@ -60,6 +62,12 @@ __device__ __forceinline__ T bdiag(const BDesc<T> &D, uint32_t both)
     }
     return d;
 }
+
+// TB consecutive LDS values read as one access (aligned to their size, at most 16 bytes)
+template <typename T, int N>
+struct __attribute__((aligned(sizeof(T) * N < 16 ? sizeof(T) * N : 16))) BVec {
+    T v[N];
+};
 
 // Role of each vector slot at step k: v = V[k % 3], v_prev = V[(k + 2) % 3],
 // v_next = V[(k + 1) % 3]; slot 3 of the pointer table is w.
@@ -79,82 +87,168 @@ __device__ __forceinline__ Roles<T> roles(T *const *ptrs, int k)
     return r;
 }
 
-// Batched product.  SEL (the Lanczos step): x = v and y = w from the pointer
-// table at the device step counter, and the first update fused in: w = H v -
-// beta_k v_prev (rounded as a separate update would be) and this work item's
-// partial of <w, v> in ipart[item] (a fixed-order block sum); otherwise x, y
-// as given.
-template <typename T, int TB, int BS, bool SEL>
-__global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ desc, const int2 *__restrict__ items,
+// Batched product.  A work item is `ncol` consecutive columns of one sector,
+// taken in groups of TB columns (the last group padded).  The item's columns
+// are staged in LDS interleaved by group (element (a, column g TB + t) at
+// (g cu + a) TB + t), and its H_dn rows, e_dn and bit patterns beside them.  A
+// lane owns TB columns of one row of one group: position f = g cu + a, the
+// quotient by a multiply-high with ceil(2^32 / cu) (exact while f cu < 2^32),
+// so a sector smaller than the workgroup fills it with several groups; each
+// H_up entry is read once for the TB columns (one LDS access gathers them),
+// and each lane takes R positions BS apart at a time, so that their loads are
+// in flight together (loads unconditional: a position past the end, or an
+// entry past its row's length, re-reads a valid one and only the update is
+// selected).  Every element is formed as in the single-sector product
+// (diagonal, then the H_up entries in sliced-ELL order, then the H_dn entries
+// in CSR order, one fused multiply-add each): the two agree bit for bit.
+// SEL (the Lanczos step): x = v and y = w from the pointer table at the device
+// step counter, and the first update fused in: w = H v - beta_k v_prev (rounded
+// as a separate update would be) and this item's partial of <w, v> in
+// ipart[item] (a fixed-order block sum); otherwise x, y as given.
+template <typename T, int BS, int R, int TB, bool SEL>
+__global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ desc, const int4 *__restrict__ items,
                                                    const T *xg, T *yg, T *const *ptrs, const int *step,
                                                    const int *__restrict__ active, const double *__restrict__ beta,
-                                                   int kmax, double *__restrict__ ipart)
+                                                   int kmax, double *__restrict__ ipart, int nitems)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[SEL ? BS : 1];
     T *tab = reinterpret_cast<T *>(smem_raw);
     T *xs = tab + 256;
-    const int2 it = items[blockIdx.x];
+    // items in launch order: with converged sectors masked out, the remaining
+    // work stays spread over every XCD
+    const int item = (int)blockIdx.x;
+    if (item >= nitems) return;
+    const int4 it = items[item];
     if (active && !active[it.x]) return;
     const BDesc<T> D = desc[it.x];
     const T *x = xg;
     T *y = yg;
     const T *vp = nullptr;
-    int k = 0;
+    int ks = 0;
     double bt = 0.0;
     if (SEL) {
-        k = *step;
-        const Roles<T> r = roles(ptrs, k);
+        ks = *step;
+        const Roles<T> r = roles(ptrs, ks);
         x = r.v;
         y = r.w;
         vp = r.vp + D.off;
-        if (k > 0) bt = beta[(int64_t)it.x * kmax + k];
+        if (ks > 0) bt = beta[(int64_t)it.x * kmax + ks];
     }
-    double dacc = 0.0;
     x += D.off;
     y += D.off;
-    const int cu = D.cu, cd = D.cd;
-    const int b0 = it.y * TB;
+    const int cu = D.cu, b0 = it.y, ncol = it.z;
+    const int ng = (ncol + TB - 1) / TB, F = ng * cu;
+    const int64_t t0 = (int64_t)b0 * cu;
+    const int rp0 = D.dn_rp[b0], nnz = D.dn_rp[b0 + ncol] - rp0;
+    T *lval = xs + (int64_t)F * TB;
+    T *ledn = lval + nnz;
+    int *lcol = reinterpret_cast<int *>(ledn + ncol);
+    int *lrp = lcol + nnz;
+    uint32_t *ldnb = reinterpret_cast<uint32_t *>(lrp + ncol + 1);
     for (int i = threadIdx.x; i < 256; i += BS) tab[i] = D.code_v[i];
-#pragma unroll
-    for (int t = 0; t < TB; ++t) {
-        const int b = b0 + t;
-        const T *xb = x + (int64_t)min(b, cd - 1) * cu;
-        for (int a = threadIdx.x; a < cu; a += BS) xs[a * TB + t] = (b < cd) ? xb[a] : (T)0;
+    for (int e = threadIdx.x; e < ng * TB * cu; e += BS) {
+        const int c = (int)(((uint64_t)(uint32_t)e * D.cu_magic) >> 32);  // column in the item
+        const int a = e - c * cu;
+        xs[((c / TB) * cu + a) * TB + c % TB] = (c < ncol) ? x[t0 + e] : (T)0;
+    }
+    for (int q = threadIdx.x; q < nnz; q += BS) {
+        lval[q] = D.dn_val[rp0 + q];
+        lcol[q] = D.dn_col[rp0 + q];
+    }
+    for (int t = threadIdx.x; t <= ncol; t += BS) lrp[t] = D.dn_rp[b0 + t] - rp0;
+    for (int t = threadIdx.x; t < ncol; t += BS) {
+        ledn[t] = D.e_dn[b0 + t];
+        ldnb[t] = D.dn_basis[b0 + t];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    for (int a = threadIdx.x; a < cu; a += BS) {
-        const uint32_t ua = D.up_basis[a];
-        const T eua = D.e_up[a];
-        T acc[TB];
+    double dacc = 0.0;
+    for (int f0 = threadIdx.x; f0 < F; f0 += R * BS) {
+        int ra[R], rg[R];  // row, group
+        T acc[R][TB];
 #pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            const int b = min(b0 + t, cd - 1);
-            acc[t] = (bdiag(D, ua & D.dn_basis[b]) + eua + D.e_dn[b]) * xs[a * TB + t];
-        }
-        const int s = a >> 6;
-        const int o0 = D.sl_off[s] * 64 + lane;
-        const int len = D.sl_off[s + 1] - D.sl_off[s];
-        for (int k = 0; k < len; ++k) {
-            const uint32_t e = D.ell[o0 + 64 * k];
-            const T v = tab[e >> 24];
-            const T *xr = xs + (e & 0xFFFFFFu) * TB;
+        for (int j = 0; j < R; ++j) {
+            const int f = (f0 + j * BS < F) ? f0 + j * BS : f0;
+            rg[j] = (int)(((uint64_t)(uint32_t)f * D.cu_magic) >> 32);
+            ra[j] = f - rg[j] * cu;
+            const uint32_t ub = D.up_basis[ra[j]];
+            const T eu = D.e_up[ra[j]];
 #pragma unroll
-            for (int t = 0; t < TB; ++t) acc[t] += v * xr[t];
-        }
-#pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            const int b = b0 + t;
-            if (b >= cd) continue;
-            T s2 = (T)0;
-            for (int kk = D.dn_rp[b]; kk < D.dn_rp[b + 1]; ++kk) s2 += D.dn_val[kk] * x[(int64_t)D.dn_col[kk] * cu + a];
-            T o = acc[t] + s2;
-            if (SEL) {
-                if (k > 0) o = (T)((double)o - bt * (double)vp[(int64_t)b * cu + a]);
-                dacc += (double)o * (double)xs[a * TB + t];
+            for (int t = 0; t < TB; ++t) {
+                const int c = min(rg[j] * TB + t, ncol - 1);
+                acc[j][t] = (bdiag(D, ub & ldnb[c]) + eu + ledn[c]) * xs[f * TB + t];
             }
-            y[(int64_t)b * cu + a] = o;
+        }
+        // H_up: entry k of row a at ell[64 sl_off[a / 64] + a % 64 + 64 k]
+        int eo[R], el_n[R], lmax = 0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int s = ra[j] >> 6;
+            eo[j] = D.sl_off[s] * 64 + (ra[j] & 63);
+            el_n[j] = D.sl_off[s + 1] - D.sl_off[s];
+            lmax = max(lmax, el_n[j]);
+        }
+        for (int k = 0; k < lmax; ++k) {
+            uint32_t c[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) c[j] = D.ell[el_n[j] > 0 ? eo[j] + 64 * min(k, el_n[j] - 1) : 0];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const T v = tab[c[j] >> 24];
+                const BVec<T, TB> xv =
+                    *reinterpret_cast<const BVec<T, TB> *>(xs + (rg[j] * cu + (int)(c[j] & 0xFFFFFFu)) * TB);
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    const T f = fma(v, xv.v[t], acc[j][t]);
+                    acc[j][t] = (k < el_n[j]) ? f : acc[j][t];
+                }
+            }
+        }
+        // H_dn: the row of each column's CSR (from LDS), neighbour columns read
+        // from the vector
+        int ds[R][TB], dn[R][TB], nmax = 0;
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                const int cc = rg[j] * TB + t;
+                ds[j][t] = lrp[min(cc, ncol)];
+                dn[j][t] = (cc < ncol) ? lrp[cc + 1] - ds[j][t] : 0;
+                nmax = max(nmax, dn[j][t]);
+            }
+        for (int u = 0; u < nmax; ++u) {
+            T w[R][TB], xv[R][TB];
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    const int kk = dn[j][t] > 0 ? ds[j][t] + min(u, dn[j][t] - 1) : 0;
+                    w[j][t] = lval[kk];
+                    xv[j][t] = x[(int64_t)lcol[kk] * cu + ra[j]];
+                }
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+#pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    const T f = fma(w[j][t], xv[j][t], acc[j][t]);
+                    acc[j][t] = (u < dn[j][t]) ? f : acc[j][t];
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (f0 + j * BS >= F) continue;
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                const int cc = rg[j] * TB + t;
+                if (cc >= ncol) continue;
+                const int64_t o = t0 + (int64_t)cc * cu + ra[j];
+                T r = acc[j][t];
+                if (SEL) {
+                    if (ks > 0) r = (T)((double)r - bt * (double)vp[o]);
+                    dacc += (double)r * (double)xs[(rg[j] * cu + ra[j]) * TB + t];
+                }
+                y[o] = r;
+            }
         }
     }
     if (SEL) {
@@ -164,27 +258,8 @@ __global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ 
             if (threadIdx.x < (unsigned)o2) red[threadIdx.x] += red[threadIdx.x + o2];
             __syncthreads();
         }
-        if (threadIdx.x == 0) ipart[blockIdx.x] = red[0];
+        if (threadIdx.x == 0) ipart[item] = red[0];
     }
-}
-
-// alpha[p * kmax + step] = the sum of sector p's work-item partials, in item order
-__global__ __launch_bounds__(BRB) void k_b_ifinal(const int *__restrict__ istart, const int *__restrict__ icount,
-                                                  const double *__restrict__ ipart, double *alpha, int kmax,
-                                                  const int *step, const int *__restrict__ active)
-{
-    __shared__ double sh[BRB];
-    const int p = blockIdx.x;
-    if (active && !active[p]) return;
-    double acc = 0.0;
-    for (int j = threadIdx.x; j < icount[p]; j += BRB) acc += ipart[istart[p] + j];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = BRB / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < (unsigned)o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) alpha[(int64_t)p * kmax + *step] = sh[0];
 }
 
 struct Seg {
@@ -246,17 +321,31 @@ __global__ __launch_bounds__(BRB) void k_b_final(Seg S, const double *partial, d
     }
 }
 
-// w -= alpha_k v; partial beta^2 = <w, w>.
+// The sum of v[0 .. n) in a fixed order (lane j adds j, j + BRB, ..., then the
+// tree of bblock_sum), the same in every block that forms it.
+__device__ __forceinline__ double bsum_strided(const double *v, int n, double *sh)
+{
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < n; j += BRB) acc += v[j];
+    return bblock_sum(acc, sh);
+}
+
+// Lanczos step after the fused product: alpha_k from the sector's work-item
+// partials (every block of the sector forms it alike; the first stores it),
+// then w -= alpha_k v and the block's partial of beta^2 = <w, w>.
 template <typename T>
-__global__ __launch_bounds__(BRB) void k_b_lz_b(Seg S, T *const *ptrs, const int *step, const double *alpha,
-                                                int kmax, double *partial, const int *__restrict__ active)
+__global__ __launch_bounds__(BRB) void k_b_lz_ab(Seg S, T *const *ptrs, const int *step,
+                                                 const int *__restrict__ istart, const int *__restrict__ icount,
+                                                 const double *__restrict__ ipart, double *alpha, int kmax,
+                                                 double *partial, const int *__restrict__ active)
 {
     __shared__ double sh[BRB];
     const int pp = S.prob[blockIdx.x];
     if (active && !active[pp]) return;
     const int k = *step;
+    const double al = bsum_strided(ipart + istart[pp], icount[pp], sh);
+    if (S.local[blockIdx.x] == 0 && threadIdx.x == 0) alpha[(int64_t)pp * kmax + k] = al;
     const Roles<T> r = roles(ptrs, k);
-    const double al = alpha[(int64_t)pp * kmax + k];
     double acc = 0.0;
     SEG_LOOP(S, p, i)
     {
@@ -264,26 +353,45 @@ __global__ __launch_bounds__(BRB) void k_b_lz_b(Seg S, T *const *ptrs, const int
         r.w[o_p + i] = wi;
         acc += (double)wi * (double)wi;
     }
-    const double s = bblock_sum(acc, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    const double s2 = bblock_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s2;
 }
 
-// v_next = w / beta_{k+1} (zero after a breakdown).
+// One block per sector: beta_{k+1} = sqrt of the sector's <w, w> partials.
+// The last block to arrive advances the step counter (every block has read it
+// before the barrier that precedes its arrival) and re-arms the arrival
+// counter `done`; the next kernel on the stream sees the new value at the
+// kernel boundary.  No fence: a device-scope fence per block would write back
+// the L2 each time.
+__global__ __launch_bounds__(BRB) void k_b_beta(Seg S, int *step, const double *partial, double *beta, int kmax,
+                                                const int *__restrict__ active, unsigned int *done)
+{
+    __shared__ double sh[BRB];
+    const int p = blockIdx.x;
+    const int k = *step;
+    if (!active || active[p]) {
+        const double bt = sqrt(bsum_strided(partial + S.start[p], S.nseg[p], sh));
+        if (threadIdx.x == 0) beta[(int64_t)p * kmax + k + 1] = bt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && atomicAdd(done, 1u) == gridDim.x - 1u) {
+        atomicExch(done, 0u);
+        *step = k + 1;
+    }
+}
+
+// v_next = w / beta_{k+1} (zero after a breakdown), run after k_b_beta has
+// advanced the step counter to k + 1.
 template <typename T>
-__global__ __launch_bounds__(BRB) void k_b_lz_next(Seg S, T *const *ptrs, const int *step, const double *beta,
-                                                   int kmax, const int *__restrict__ active)
+__global__ __launch_bounds__(BRB) void k_b_lz_nx(Seg S, T *const *ptrs, const int *step, const double *beta,
+                                                 int kmax, const int *__restrict__ active)
 {
     const int pp = S.prob[blockIdx.x];
     if (active && !active[pp]) return;
-    const int k = *step;
-    const Roles<T> r = roles(ptrs, k);
+    const int k = *step - 1;
     const double bt = beta[(int64_t)pp * kmax + k + 1];
+    const Roles<T> r = roles(ptrs, k);
     SEG_LOOP(S, p, i) r.vn[o_p + i] = (bt > 0.0) ? (T)((double)r.w[o_p + i] / bt) : (T)0;
-}
-
-__global__ void k_b_step(int *step, int add, int set)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *step = (set >= 0) ? set : (*step + add);
 }
 
 // Start vectors: sector-local SplitMix64 entries (same as a single-sector solve).
@@ -443,9 +551,10 @@ struct hub_batch {
     int64_t *d_off = nullptr;
     // tuned product per dtype
     bool tuned[2] = {false, false};
-    int tb[2] = {1, 1}, bs[2] = {256, 256};
-    int2 *items[2] = {nullptr, nullptr};
+    int rr[2] = {1, 1}, bs[2] = {256, 256}, tb[2] = {1, 1};  // rows / columns per lane, workgroup size
+    int4 *items[2] = {nullptr, nullptr};      // {sector, first column, columns, 0}
     int nitems[2] = {0, 0};
+    size_t lds_bytes[2] = {0, 0};             // dynamic LDS of the largest item
     int *istart[2] = {nullptr, nullptr}, *icount[2] = {nullptr, nullptr};  // items of each sector
     double tune_seconds = 0.0;
 };
@@ -501,6 +610,7 @@ BDesc<T> make_desc(const hub_sector *s, int64_t off)
     d.uniform = s->uniformU;
     d.umask = s->umask;
     d.U = (T)s->U0;
+    d.cu_magic = ((1ull << 32) + (uint64_t)d.cu - 1) / (uint64_t)d.cu;
     if constexpr (sizeof(T) == 8) {
         d.e_up = U.e64;
         d.e_dn = D.e64;
@@ -517,22 +627,26 @@ BDesc<T> make_desc(const hub_sector *s, int64_t off)
     return d;
 }
 
-template <typename T, int TB, int BS, bool SEL>
+template <typename T, int BS, int R, int TB, bool SEL>
 hub_status launch_bk(hub_batch *b, int di, const T *x, T *y, T *const *ptrs, const int *step, const int *active,
                      hipStream_t st, const double *beta, int kmax, double *ipart)
 {
-    const size_t lds = (size_t)(256 + (size_t)b->max_cu * TB) * sizeof(T);
     static std::atomic<bool> attr{false};
     if (!attr) {
-        HUB_HIP(hipFuncSetAttribute((const void *)k_batch_kron<T, TB, BS, SEL>,
+        HUB_HIP(hipFuncSetAttribute((const void *)k_batch_kron<T, BS, R, TB, SEL>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_max));
         attr = true;
     }
-    hipLaunchKernelGGL((k_batch_kron<T, TB, BS, SEL>), dim3(b->nitems[di]), dim3(BS), lds, st,
-                       (const BDesc<T> *)b->desc[di], b->items[di], x, y, ptrs, step, active, beta, kmax, ipart);
+    const int n = b->nitems[di];
+    hipLaunchKernelGGL((k_batch_kron<T, BS, R, TB, SEL>), dim3(n), dim3(BS), b->lds_bytes[di], st,
+                       (const BDesc<T> *)b->desc[di], b->items[di], x, y, ptrs, step, active, beta, kmax, ipart, n);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
+
+// The product shapes the tuner tries: {workgroup size, rows per lane, columns per lane}
+constexpr int kBatchShapes[][3] = {{256, 4, 1}, {256, 2, 2}, {256, 1, 4}, {256, 2, 4}, {256, 4, 2},
+                                   {512, 4, 1}, {512, 2, 2}, {512, 1, 4}, {512, 2, 4}};
 
 // SEL: the Lanczos step (vectors from the pointer table, first update fused,
 // item partials of alpha in ipart; beta and kmax as in the solver's arrays)
@@ -541,22 +655,42 @@ hub_status launch_batch_product(hub_batch *b, const T *x, T *y, T *const *ptrs, 
                                 hipStream_t st, const double *beta = nullptr, int kmax = 0, double *ipart = nullptr)
 {
     const int di = (sizeof(T) == 8) ? 0 : 1;
-    const int tb = b->tb[di], bs = b->bs[di];
-#define HUB_BK(TBV, BSV)                                                                 \
-    if (tb == TBV && bs == BSV)                                                          \
-        return launch_bk<T, TBV, BSV, SEL>(b, di, x, y, ptrs, step, active, st, beta, kmax, ipart);
-    HUB_BK(1, 256) HUB_BK(2, 256) HUB_BK(4, 256) HUB_BK(8, 256)
-    HUB_BK(1, 512) HUB_BK(2, 512) HUB_BK(4, 512) HUB_BK(8, 512)
+    const int rr = b->rr[di], bs = b->bs[di], tb = b->tb[di];
+#define HUB_BK(BSV, RV, TBV)                                                             \
+    if (bs == BSV && rr == RV && tb == TBV)                                              \
+        return launch_bk<T, BSV, RV, TBV, SEL>(b, di, x, y, ptrs, step, active, st, beta, kmax, ipart);
+    HUB_BK(256, 4, 1) HUB_BK(256, 2, 2) HUB_BK(256, 1, 4) HUB_BK(256, 2, 4) HUB_BK(256, 4, 2)
+    HUB_BK(512, 4, 1) HUB_BK(512, 2, 2) HUB_BK(512, 1, 4) HUB_BK(512, 2, 4)
 #undef HUB_BK
     return bfail(HUB_ERR_UNSUPPORTED, "untuned product shape");
 }
 
-hub_status build_items(hub_batch *b, int di, int tb)
+// Work items: each sector's columns in runs of tb x max(1, target / count_up)
+// (the last run shorter), at most kItemDnEntries / (the longest H_dn row)
+// columns, so that their H_dn rows fit the LDS beside them.
+constexpr int kItemDnEntries = 4096;
+
+hub_status build_items(hub_batch *b, int di, int target, int tb)
 {
-    std::vector<int2> it;
+    const size_t es = di == 0 ? sizeof(double) : sizeof(float);
+    std::vector<int4> it;
+    size_t lds = 0;
     for (int p = 0; p < b->P; ++p) {
-        const int cd = (int)b->secs[p]->spin[1].count;
-        for (int t = 0; t * tb < cd; ++t) it.push_back(make_int2(p, t));
+        const SpinTables &DN = b->secs[p]->spin[1];
+        const int cu = (int)b->secs[p]->spin[0].count, cd = (int)DN.count;
+        const int deg = std::max(1, (int)DN.max_row);
+        const int per = std::max(1, std::min({cd, tb * std::max(1, target / cu), kItemDnEntries / deg}));
+        // the in-kernel quotients by cu are exact while (padded columns of an item) * cu * cu < 2^32
+        const uint64_t padded = (uint64_t)((per + tb - 1) / tb * tb);
+        if (padded * (uint64_t)cu * (uint64_t)cu >= (1ull << 32))
+            return bfail(HUB_ERR_UNSUPPORTED, "sector too large for the batched product");
+        for (int b0 = 0; b0 < cd; b0 += per) {
+            const int n = std::min(per, cd - b0);
+            it.push_back(make_int4(p, b0, n, 0));
+            const size_t nnz = (size_t)n * (size_t)deg;
+            const size_t ncp = (size_t)((n + tb - 1) / tb * tb);
+            lds = std::max(lds, (256 + ncp * cu + nnz + n) * es + (nnz + 2 * (size_t)n + 1) * 4);
+        }
     }
     if (b->items[di]) {
         HUB_HIP(hipFree(b->items[di]));
@@ -565,8 +699,9 @@ hub_status build_items(hub_batch *b, int di, int tb)
         b->items[di] = nullptr;
     }
     HUB_TRY(balloc(b, &b->items[di], it.size()));
-    HUB_HIP(hipMemcpy(b->items[di], it.data(), sizeof(int2) * it.size(), hipMemcpyHostToDevice));
+    HUB_HIP(hipMemcpy(b->items[di], it.data(), sizeof(int4) * it.size(), hipMemcpyHostToDevice));
     b->nitems[di] = (int)it.size();
+    b->lds_bytes[di] = lds;
     // the items of sector p are [istart[p], istart[p] + icount[p]) (sector-major order)
     std::vector<int> hs(b->P, 0), hc(b->P, 0);
     for (int i = 0; i < (int)it.size(); ++i) {
@@ -577,11 +712,12 @@ hub_status build_items(hub_batch *b, int di, int tb)
     if (!b->icount[di]) HUB_TRY(balloc(b, &b->icount[di], (size_t)b->P));
     HUB_HIP(hipMemcpy(b->istart[di], hs.data(), sizeof(int) * b->P, hipMemcpyHostToDevice));
     HUB_HIP(hipMemcpy(b->icount[di], hc.data(), sizeof(int) * b->P, hipMemcpyHostToDevice));
-    b->tb[di] = tb;
     return HUB_OK;
 }
 
-// Autotuner: time every (TB, BS) whose panel fits the LDS on the batch itself.
+// Autotuner: time every (workgroup size, elements per lane) whose items fit
+// the LDS on the batch itself; items hold about size x elements-per-lane
+// elements.
 template <typename T>
 hub_status tune(hub_batch *b, hipStream_t st)
 {
@@ -603,31 +739,37 @@ hub_status tune(hub_batch *b, hipStream_t st)
     hipEvent_t e0, e1;
     HUB_HIP(hipEventCreate(&e0));
     HUB_HIP(hipEventCreate(&e1));
+    struct EvFree {
+        hipEvent_t a, c;
+        ~EvFree() { (void)hipEventDestroy(a); (void)hipEventDestroy(c); }
+    } ef{e0, e1};
     float best = 1e30f;
-    int btb = 1, bbs = 256;
-    for (int tb : {1, 2, 4, 8}) {
-        if ((size_t)(256 + (size_t)b->max_cu * tb) * sizeof(T) > b->lds_max) continue;
-        HUB_TRY(build_items(b, di, tb));
-        for (int bs : {256, 512}) {
-            b->bs[di] = bs;
-            HUB_TRY((launch_batch_product<T, false>(b, x, y, nullptr, nullptr, nullptr, st)));
-            HUB_HIP(hipEventRecord(e0, st));
-            for (int r = 0; r < 3; ++r) HUB_TRY((launch_batch_product<T, false>(b, x, y, nullptr, nullptr, nullptr, st)));
-            HUB_HIP(hipEventRecord(e1, st));
-            HUB_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HUB_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                btb = tb;
-                bbs = bs;
-            }
+    int bsel = -1;
+    const int nshape = (int)(sizeof(kBatchShapes) / sizeof(kBatchShapes[0]));
+    for (int i = 0; i < nshape; ++i) {
+        const int bs = kBatchShapes[i][0], r = kBatchShapes[i][1], tbv = kBatchShapes[i][2];
+        HUB_TRY(build_items(b, di, bs * r, tbv));
+        if (b->lds_bytes[di] > b->lds_max) continue;
+        b->bs[di] = bs;
+        b->rr[di] = r;
+        b->tb[di] = tbv;
+        HUB_TRY((launch_batch_product<T, false>(b, x, y, nullptr, nullptr, nullptr, st)));
+        HUB_HIP(hipEventRecord(e0, st));
+        for (int q = 0; q < 3; ++q) HUB_TRY((launch_batch_product<T, false>(b, x, y, nullptr, nullptr, nullptr, st)));
+        HUB_HIP(hipEventRecord(e1, st));
+        HUB_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HUB_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            bsel = i;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    HUB_TRY(build_items(b, di, btb));
-    b->bs[di] = bbs;
+    if (bsel < 0) return bfail(HUB_ERR_UNSUPPORTED, "a sector's columns do not fit in LDS for the batched product");
+    b->bs[di] = kBatchShapes[bsel][0];
+    b->rr[di] = kBatchShapes[bsel][1];
+    b->tb[di] = kBatchShapes[bsel][2];
+    HUB_TRY(build_items(b, di, b->bs[di] * b->rr[di], b->tb[di]));
     b->tuned[di] = true;
     b->tune_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return HUB_OK;
@@ -686,6 +828,7 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
     double *alpha = nullptr, *beta = nullptr, *partial = nullptr, *nrm = nullptr, *ycoef = nullptr;
     HUB_TRY(alloc((void **)&ptrs, sizeof(T *) * 4));
     HUB_TRY(alloc((void **)&step, sizeof(int) * 4));
+    unsigned int *done = reinterpret_cast<unsigned int *>(step + 1);  // arrival counter of k_b_beta
     HUB_TRY(alloc((void **)&active, sizeof(int) * P));
     HUB_TRY(alloc((void **)&mlen, sizeof(int) * P));
     HUB_TRY(alloc((void **)&alpha, sizeof(double) * (size_t)P * kmax));
@@ -698,6 +841,7 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
     HUB_HIP(hipMemcpyAsync(ptrs, V, sizeof(T *) * 4, hipMemcpyHostToDevice, st));
     std::vector<int> hact(P, 1);
     HUB_HIP(hipMemcpyAsync(active, hact.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
+    HUB_HIP(hipMemsetAsync(step, 0, sizeof(int) * 4, st));
     HUB_HIP(hipMemsetAsync(beta, 0, sizeof(double) * (size_t)P * kmax, st));
     HUB_HIP(hipMemsetAsync(alpha, 0, sizeof(double) * (size_t)P * kmax, st));
 
@@ -713,21 +857,18 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
         return HUB_OK;
     };
     HUB_TRY(make_start(V[0]));
-    hipLaunchKernelGGL(k_b_step, dim3(1), dim3(64), 0, st, step, 0, 0);
 
-    // one Lanczos step, captured as a graph
+    // one Lanczos step, captured as a graph: the fused product; alpha and
+    // w -= alpha v; beta and the step counter; v_next
     auto one_step = [&]() -> hub_status {
         HUB_TRY((launch_batch_product<T, true>(b, nullptr, nullptr, ptrs, step, active, st, beta, kmax, ipart)));
-        hipLaunchKernelGGL(k_b_ifinal, dim3(P), dim3(BRB), 0, st, (const int *)b->istart[di],
-                           (const int *)b->icount[di], (const double *)ipart, alpha, kmax, (const int *)step,
-                           (const int *)active);
-        hipLaunchKernelGGL(k_b_lz_b<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, ptrs, (const int *)step,
-                           (const double *)alpha, kmax, partial, (const int *)active);
-        hipLaunchKernelGGL(k_b_final, dim3(P), dim3(BRB), 0, st, S, (const double *)partial, beta, kmax, 0,
-                           (const int *)step, 1, 1, (const int *)active);
-        hipLaunchKernelGGL(k_b_lz_next<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, ptrs, (const int *)step,
+        hipLaunchKernelGGL(k_b_lz_ab<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, ptrs, (const int *)step,
+                           (const int *)b->istart[di], (const int *)b->icount[di], (const double *)ipart, alpha,
+                           kmax, partial, (const int *)active);
+        hipLaunchKernelGGL(k_b_beta, dim3(P), dim3(BRB), 0, st, S, step, (const double *)partial, beta, kmax,
+                           (const int *)active, done);
+        hipLaunchKernelGGL(k_b_lz_nx<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, ptrs, (const int *)step,
                            (const double *)beta, kmax, (const int *)active);
-        hipLaunchKernelGGL(k_b_step, dim3(1), dim3(64), 0, st, step, 1, -1);
         HUB_HIP(hipGetLastError());
         return HUB_OK;
     };
@@ -737,9 +878,8 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
     int k = 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    // HUB_BATCH_GRAPH=0 replays the step eagerly (same kernels, same order)
-    const char *genv = std::getenv("HUB_BATCH_GRAPH");
-    bool use_graph = !(genv && genv[0] == '0');
+    // opts->batch_no_graph: every step launched eagerly (same kernels, same order)
+    bool use_graph = !o->batch_no_graph;
     if (use_graph && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
         hub_status cs = one_step();
         hipError_t ec = hipStreamEndCapture(st, &graph);
@@ -777,15 +917,18 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
     int replays = 0, nactive = P;
 
     // Convergence checks overlap the GPU: after every group of check_every steps
-    // the coefficients are copied into one of two pinned buffers, the next group
-    // is enqueued before the host examines the previous copy, and the new active
-    // mask (through pinned memory as well) reaches the device one group later.
-    // A sector found converged may so run one more group; those steps are never
-    // used (its T and psi stop at the step of the test).
+    // the coefficients are copied into a ring of pinned buffers, and kAhead
+    // further groups are enqueued before the host examines a copy; the new
+    // active mask (through pinned memory as well) reaches the device after the
+    // groups already queued.  A sector found converged may so run kAhead more
+    // groups; those steps are never used (its T and psi stop at the step of the
+    // test).  (Two groups ahead left the inter-kernel gaps of the 64-sector
+    // batch unchanged: the host test is not what the GPU waits for.)
+    constexpr int kAhead = 1, NS = kAhead + 1;
     const size_t nab = (size_t)P * kmax;
     double *hab = nullptr;  // [2 slots][alpha | beta]
     int *hmask = nullptr;   // [2][P]
-    HUB_HIP(hipHostMalloc((void **)&hab, sizeof(double) * 4 * nab));
+    HUB_HIP(hipHostMalloc((void **)&hab, sizeof(double) * 2 * NS * nab));
     struct PinGuard {
         void *p;
         hipStream_t st;
@@ -796,20 +939,19 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
             (void)hipHostFree(p);
         }
     } pin_ab{hab, st}, pin_mask{nullptr, st};
-    HUB_HIP(hipHostMalloc((void **)&hmask, sizeof(int) * 2 * (size_t)P));
+    HUB_HIP(hipHostMalloc((void **)&hmask, sizeof(int) * NS * (size_t)P));
     pin_mask.p = hmask;
-    hipEvent_t cev[2] = {nullptr, nullptr};
-    HUB_HIP(hipEventCreateWithFlags(&cev[0], hipEventDisableTiming));
-    HUB_HIP(hipEventCreateWithFlags(&cev[1], hipEventDisableTiming));
+    hipEvent_t cev[NS] = {};
+    for (int i = 0; i < NS; ++i) HUB_HIP(hipEventCreateWithFlags(&cev[i], hipEventDisableTiming));
     struct EvGuard {
         hipEvent_t *e;
         ~EvGuard()
         {
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < NS; ++i)
                 if (e[i]) (void)hipEventDestroy(e[i]);
         }
     } evg{cev};
-    int kslot[2] = {0, 0};
+    int kslot[NS] = {};
     auto enqueue_copy = [&](int sl) -> hub_status {
         HUB_HIP(hipMemcpyAsync(hab + (size_t)sl * 2 * nab, alpha, sizeof(double) * nab, hipMemcpyDeviceToHost, st));
         HUB_HIP(hipMemcpyAsync(hab + (size_t)sl * 2 * nab + nab, beta, sizeof(double) * nab, hipMemcpyDeviceToHost,
@@ -868,23 +1010,28 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
             }
         }
     };
-    HUB_TRY(enqueue_copy(0));
-    int sl = 0, msl = 0;
+    std::deque<int> pend;  // copies enqueued and not yet examined, oldest first
+    int next_slot = 0, msl = 0;
+    HUB_TRY(enqueue_copy(next_slot));
+    pend.push_back(next_slot);
+    next_slot = (next_slot + 1) % NS;
     while (true) {
-        const int nsteps = nactive > 0 ? std::min(check_every, max_iter - k) : 0;
-        if (nsteps > 0) {
-            HUB_TRY(enqueue_steps(nsteps));
-            HUB_TRY(enqueue_copy(sl ^ 1));
+        while ((int)pend.size() <= kAhead && nactive > 0 && k < max_iter) {
+            HUB_TRY(enqueue_steps(std::min(check_every, max_iter - k)));
+            HUB_TRY(enqueue_copy(next_slot));
+            pend.push_back(next_slot);
+            next_slot = (next_slot + 1) % NS;
         }
-        HUB_HIP(hipEventSynchronize(cev[sl]));  // the group just enqueued keeps running
+        const int sl = pend.front();
+        pend.pop_front();
+        HUB_HIP(hipEventSynchronize(cev[sl]));  // the groups enqueued after it keep running
         const double *ha = hab + (size_t)sl * 2 * nab;
         check_copy(ha, ha + nab, kslot[sl]);
-        if (nactive == 0 || nsteps == 0) break;
+        if (nactive == 0 || (pend.empty() && k >= max_iter)) break;
         int *hm = hmask + (size_t)msl * P;
         std::memcpy(hm, hact.data(), sizeof(int) * (size_t)P);
         HUB_HIP(hipMemcpyAsync(active, hm, sizeof(int) * P, hipMemcpyHostToDevice, st));
-        msl ^= 1;
-        sl ^= 1;
+        msl = (msl + 1) % NS;
     }
     std::vector<double> e0(theta);
 
@@ -950,7 +1097,8 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
         std::memset(info, 0, sizeof(*info));
         info->steps = k;
         info->graph_replays = replays;
-        info->tile_columns = b->tb[di];
+        info->rows_per_lane = b->rr[di];
+        info->cols_per_lane = b->tb[di];
         info->block_size = b->bs[di];
         info->tune_seconds = b->tune_seconds - tune0;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1016,12 +1164,13 @@ hub_status hub_batch_create(const hub_sector *const *sectors, int32_t count, hub
     HUB_HIP(hipMemcpy(dd32, d32.data(), sizeof(BDesc<float>) * count, hipMemcpyHostToDevice));
     b->desc[0] = dd64;
     b->desc[1] = dd32;
-    // segment grid: blocks per sector ~ dim / (8 * BRB), between 1 and 64
+    // segment grid: blocks per sector ~ dim / (8 * BRB) (eight elements per
+    // lane, so the vector passes keep many loads in flight), between 1 and 1024
     std::vector<int32_t> sp, sl, sn(count), ss(count);
     for (int p = 0; p < count; ++p) {
         const int64_t d = b->off[p + 1] - b->off[p];
         int64_t nb = (d + 8 * BRB - 1) / (8 * BRB);
-        nb = std::max<int64_t>(1, std::min<int64_t>(64, nb));
+        nb = std::max<int64_t>(1, std::min<int64_t>(1024, nb));
         sn[p] = (int32_t)nb;
         ss[p] = (int32_t)sp.size();
         for (int j = 0; j < nb; ++j) {

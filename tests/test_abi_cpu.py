@@ -37,6 +37,48 @@ def test_library_exports_every_declared_function(L):
     assert sorted(hub.EXPORTED) == declared_functions()
 
 
+_C_TYPES = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "uint64_t": ctypes.c_uint64,
+            "uint32_t": ctypes.c_uint32, "double": ctypes.c_double, "float": ctypes.c_float}
+
+
+def header_structs():
+    """{struct name: [(field, C type), ...]} of the typedef'd structs of the header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    out = {}
+    for name, body in re.findall(r"typedef struct (hub_[a-z0-9_]+) \{(.*?)\} \1;", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = " ".join(decl.split())
+            if not decl:
+                continue
+            m = re.match(r"(const )?([A-Za-z0-9_]+)\s+(.*)$", decl)
+            assert m, decl
+            for d in m.group(3).split(","):
+                d = d.strip()
+                fields.append((d.lstrip("* "), "ptr" if d.startswith("*") else m.group(2)))
+        out[name] = fields
+    return out
+
+
+def test_binding_structs_match_header():
+    """Every ctypes structure of the binding has the fields of its C struct, in
+    order and of the same types (pointers as pointers)."""
+    import paper_1307_7542_amd as hub
+    pairs = {"hub_model": hub._Model, "hub_schedule": hub.Schedule, "hub_lanczos_opts": hub.LanczosOpts,
+             "hub_lanczos_info": hub.LanczosInfo, "hub_batch_info": hub.BatchInfo, "hub_gf_info": hub.GfInfo}
+    hs = header_structs()
+    assert set(pairs) == set(hs)
+    for cname, py in pairs.items():
+        want = hs[cname]
+        got = py._fields_
+        assert [f for f, _ in want] == [f for f, _ in got], cname
+        for (f, ct), (_, pt) in zip(want, got):
+            if ct == "ptr":
+                assert pt in (ctypes.c_void_p,) or issubclass(pt, ctypes._Pointer), (cname, f, pt)
+            else:
+                assert pt is _C_TYPES[ct], (cname, f, ct, pt)
+
+
 def test_status_strings(L):
     assert L.hub_status_str(0) == b"HUB_OK"
     assert L.hub_status_str(2) == b"HUB_ERR_RANGE"
