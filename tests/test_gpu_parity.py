@@ -877,6 +877,30 @@ def test_matvec_row_chunked_several_row_parts(hub, variant):
     s.close()
 
 
+def test_chunked_solve_same_for_every_shape(hub):
+    """The row-chunked product's shape (columns per work item, lane-quads per
+    lane, chunk rows) is tuned in each process, so a solve through it must not
+    depend on it: on count_up = 18564 (several row parts and chunks, 18 columns
+    leaving ragged tiles of 2 and 4), every forced shape gives the same energy
+    and step count bit for bit, in both precisions, and that energy is the
+    oracle's."""
+    m = W.ring(18, U=3.0, n_up=6, n_dn=1).with_params(eps=[0.03 * i for i in range(18)])
+    s = hub.Sector(m)
+    _, e_ref, _ = oracle.ground_state(m, want_vector=False)
+    shapes = {hub.F64: [(1, 4, 5000), (2, 4, 5000), (1, 8, 5000), (1, 4, 12000)],
+              hub.F32: [(1, 4, 5000), (2, 4, 5000), (1, 8, 5000), (2, 8, 5000), (4, 4, 5000)]}
+    for dt, tol, rel in ((hub.F64, 1e-12, 1e-10), (hub.F32, 1e-7, 1e-5)):
+        got = []
+        for tb, qpl, rows in shapes[dt]:
+            s.set_schedule(dt, hub.SCHED_CHUNKED, tile_cols=tb, quads_per_lane=qpl, chunk_rows=rows)
+            g = s.ground_state(dtype=dt, tol=tol, want_vector=False)
+            got.append((g.e0, g.info["iters"]))
+        assert all(r == got[0] for r in got), (dt, list(zip(shapes[dt], got)))
+        assert abs(got[0][0] - e_ref) <= rel * abs(e_ref), (dt, got[0], e_ref)
+        s.set_schedule(dt, None)
+    s.close()
+
+
 @pytest.mark.parametrize("which", ["square3x4_n5", "ring10_eps"])
 def test_matvec_unaligned_views(hub, which):
     """Vectors that start at an element but not a 16-byte boundary (views into a
