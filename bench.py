@@ -55,6 +55,27 @@ def parse():
     return ap.parse_args()
 
 
+def copy_rates(torch, reps=20):
+    """Device-to-device copy rates (read + write bytes per second) on this GPU:
+    a 1 GiB buffer (from HBM) and a 47 MB buffer (held in the 256 MB MALL),
+    the practical ceilings the products are set against."""
+    out = {}
+    for name, nbytes in (("hbm_1GiB", 1 << 30), ("mall_47MB", 47 << 20)):
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_GBps"] = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e6)
+        del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def product_timing(hub, torch, model, reps=10):
     """Average event time of back-to-back products on the current stream."""
     sec = hub.Sector(model)
@@ -458,6 +479,10 @@ def main():
                           "table2_ring14_offdiag_generation_s": {"two_spin": 5.02, "one_spin": 0.55},
                           "generation_speedup_claim": "1/9 to 1/11"},
     }
+    copies = copy_rates(torch)
+    out["copy_reference"] = copies
+    out["roofline"]["target_frac"] = 0.60
+    out["roofline"]["frac_of_hbm_copy"] = h64["GBps"] / copies["hbm_1GiB_GBps"]
     traffic = committed_traffic(h64["kernel"])
     if traffic:
         out["roofline"]["traffic"] = traffic["bytes"]
@@ -476,9 +501,14 @@ def main():
         out["table4_check"] = {"U": 4, "printed_E_min": TABLE4_M14_U4,
                                "e0_fp64": out["ring14_solves"]["U=4"]["e0_fp64"]}
         out["products_ring14_u4"] = product_timing(hub, torch, W.config("ring14_u4"))
+        for dt in ("f32", "f64"):  # its vectors stay in the MALL: set against the MALL-resident copy
+            out["products_ring14_u4"][dt]["frac_of_mall_copy"] = (out["products_ring14_u4"][dt]["GBps"]
+                                                                  / copies["mall_47MB_GBps"])
         out["products_square4x4"] = product_timing(hub, torch, W.config("square4x4"))
         out["lanczos_square4x4_mixed_gradients"] = square_mixed_gradients(hub, torch, W.config("square4x4"))
         out["aim_batch64"] = batch_timing(hub, torch)
+        out["aim_batch64"]["product_f64_frac_of_mall_copy"] = (out["aim_batch64"]["product_f64_GBps"]
+                                                               / copies["mall_47MB_GBps"])
         out["greens_ring14_u4"] = greens_timing(hub, torch, W.config("ring14_u4"))
         out["k0_ring14_u4"] = k0_timing(hub, torch, W.config("ring14_u4"))
     if not args.no_cpu_baseline:
