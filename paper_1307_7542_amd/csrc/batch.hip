@@ -1148,8 +1148,12 @@ hub_status hub_batch_create(const hub_sector *const *sectors, int32_t count, hub
     // of the fused Lanczos update (up to 512 doubles)
     b->lds_max = sectors[0]->lds_max - 4096;
     HUB_HIP(hipSetDevice(b->device));
-    if ((size_t)(256 + (size_t)b->max_cu) * 8 > b->lds_max)
-        return bfail(HUB_ERR_UNSUPPORTED, "a sector's column does not fit in LDS for the batched product");
+    // the smallest work item (one FP64 column with its H_dn row) must fit
+    for (const hub_sector *s : b->secs) {
+        const size_t cu = (size_t)s->spin[0].count, deg = (size_t)std::max(1, (int)s->spin[1].max_row);
+        if ((256 + cu + deg + 1) * 8 + (deg + 3) * 4 > b->lds_max)
+            return bfail(HUB_ERR_UNSUPPORTED, "a sector's column does not fit in LDS for the batched product");
+    }
     std::vector<BDesc<double>> d64(count);
     std::vector<BDesc<float>> d32(count);
     for (int p = 0; p < count; ++p) {

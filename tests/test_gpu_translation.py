@@ -102,16 +102,15 @@ def test_k0_table4_ring14(hub):
 
 
 def test_k0_ring16_even_filling(hub):
-    """M = 16, U = 4, N = 8/8: the k = 0 block bounds the Table IV energy from
-    above (the ground state may carry another momentum)."""
+    """M = 16, U = 4, N = 8/8: the lowest energy of the k = 0 block is bounded
+    below by the full sector's E0 (the oracle's matrix-free Lanczos value)."""
     m = W.ring(16, U=4.0, n_up=8, n_dn=8)
     s = hub.Sector(m, translation=1)
     g = s.ground_state(dtype=hub.F64, tol=1e-12, max_iter=800, want_vector=False)
-    with open(os.path.join(os.path.dirname(__file__), "golden", "table4_emin.json")) as f:
-        t4 = json.load(f)
-    printed = [r for r in t4["rows"] if r["M"] == 16][0]["E_min"]
-    print("ring16 k=0 E0", g.e0, "Table IV", printed)
-    assert g.e0 >= printed - 1e-9
+    with open(os.path.join(os.path.dirname(__file__), "golden", "ring16_u4_oracle.json")) as f:
+        e_full = json.load(f)["e0"]
+    print("ring16 k=0 E0", g.e0, "full sector (oracle)", e_full)
+    assert g.e0 >= e_full - 1e-10 * abs(e_full)
     s.close()
 
 
