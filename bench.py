@@ -273,7 +273,7 @@ def kernel_name(sched, es):
     if sched["family"] == 1:
         return f"k_kron_quad<{T}, {sched['tile_cols']}, {sched['block']}, {bool(sched['order'])}, false>"
     if sched["family"] == 2:
-        return f"k_kron_chunked_parts<{T}, 1024, {sched['quads_per_lane']}, {sched['tile_cols']}>"
+        return f"k_kron_chunked_parts<{T}, 1024, {sched['quads_per_lane']}, {sched['tile_cols']}, false>"
     return {3: "k_kron_fused", 4: "k_kron_csr"}.get(sched["family"], "?")
 
 
@@ -330,6 +330,8 @@ def ladder_time_to_e0(hub, torch, model):
     g64 = sec.ground_state(dtype=hub.F64, want_vector=False, tol=1e-12, max_iter=600, check_every=2,
                            time_kernels=TIME_EVERY, **tgt)
     torch.cuda.empty_cache()
+    # the FP32 fused product's shape is tuned on its first use: keep that out of the timed solve
+    sec.ground_state(dtype=hub.F32, want_vector=False, max_iter=2, allow_not_converged=True)
     torch.cuda.synchronize()
     g32 = sec.ground_state(dtype=hub.F32, refine=True, tol=1e-7, max_iter=600, check_every=2,
                            time_kernels=TIME_EVERY, **tgt)

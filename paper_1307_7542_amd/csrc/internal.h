@@ -161,6 +161,7 @@ hub_status launch_matvec(const hub_sector *s, int dtype, const void *x, void *y,
 // the partials sum to beta_k alpha_k.  Available when matvec_lz_available(s, dtype).
 bool matvec_lz_available(const hub_sector *s, int dtype);
 int64_t matvec_lz_partials(const hub_sector *s);
+int64_t matvec_lz_workspace(const hub_sector *s);  // doubles of the apart buffer launch_matvec_lz needs
 hub_status launch_matvec_lz(const hub_sector *s, int dtype, const void *x, void *w, const void *vprev,
                             const double *beta, double *apart, int64_t *npart, hipStream_t st,
                             const double *beta_prev = nullptr, int unnorm = 0);

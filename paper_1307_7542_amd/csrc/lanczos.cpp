@@ -229,7 +229,8 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     // Refuse before allocating anything when the vectors cannot fit in the free
     // device memory: three (plain recurrence) or up to max_iter + 1 stored
     // Lanczos vectors plus the update's (full reorthogonalisation), an FP64 psi
-    // when the caller passes none, and the refinement's FP64 H psi.
+    // when the caller passes none, the refinement's FP64 H psi, and the fused
+    // product's partials.
     {
         size_t free_b = 0, total_b = 0;
         HUB_HIP(hipMemGetInfo(&free_b, &total_b));
@@ -237,6 +238,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
         double need = vec * (reorth ? (double)kmax + 1.0 : 3.0);
         if (want_vec && !dev_psi) need += 8.0 * (double)n;
         if (o->refine) need += 8.0 * (double)n;
+        if (matvec_lz_available(s, dt)) need += 8.0 * (double)matvec_lz_workspace(s);
         if (need > (double)free_b) {
             set_error("Lanczos workspace of " + std::to_string(need / 1e9) + " GB exceeds the " +
                       std::to_string((double)free_b / 1e9) + " GB of free device memory" +
@@ -316,7 +318,7 @@ hub_status ground_state(const hub_sector *s, const hub_lanczos_opts *o, double *
     // sum of its partials) where the product kernel supports it, else product + update
     const bool fused = matvec_lz_available(s, dt);
     double *apart = nullptr;
-    if (fused) HUB_TRY(mem.alloc((void **)&apart, sizeof(double) * (size_t)matvec_lz_partials(s)));
+    if (fused) HUB_TRY(mem.alloc((void **)&apart, sizeof(double) * (size_t)matvec_lz_workspace(s)));
     if (fused) inf.matvec_bytes += (int64_t)es * n;  // the update's read of v_prev
     // fused: alpha's per-column partials are left in apart[0 .. np_alpha) and
     // summed by the w -= alpha v update (lz_b below); otherwise alpha goes to aout
@@ -726,7 +728,7 @@ hub_status lanczos_coefficients(const hub_sector *s, const double *f, int max_st
     // product and a separate first update
     const bool fused = matvec_lz_available(s, HUB_F64) && matvec_lz_partials(s) <= kSumInUpdate;
     double *apart = nullptr;
-    if (fused) HUB_TRY(mem.alloc((void **)&apart, sizeof(double) * (size_t)matvec_lz_partials(s)));
+    if (fused) HUB_TRY(mem.alloc((void **)&apart, sizeof(double) * (size_t)matvec_lz_workspace(s)));
     for (int k = 0; k < kmax; ++k) {
         if (fused) {
             int64_t np = 0;

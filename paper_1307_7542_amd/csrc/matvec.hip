@@ -284,6 +284,7 @@ struct LzEpi {
     int G;                    // lane-quad groups per column: ceil(count_up / 256)
     const double *beta_prev;  // unnorm: beta_{k-1} (device), NULL for beta_0
     int unnorm;
+    double *gpart;            // row-chunked product: [cd][G] group partials (summed into apart per column)
 };
 
 __device__ __forceinline__ double inv_beta(const double *b)
@@ -499,12 +500,18 @@ __global__ __launch_bounds__(BS) void k_kron_quad(MvArgs<T> A, const int32_t *__
 // neighbour rows the H_dn term reads at a time are one part's (2x9 ladder:
 // FP32 30.6 -> 30.0 ms, FP64 57.8 -> 56.1 ms against the parts of a tile
 // dispatched together).
-template <typename T, int BS, int QPL, int TB>
+//
+// EPI: the first Lanczos update fused into the store, as in k_kron_quad: each
+// wavefront's 64 lane-quads (one group of 256 rows of a column) are summed in
+// the same fixed order into E.gpart[column][group]; k_epi_colsum then adds a
+// column's groups in increasing order, so the per-column partials equal the
+// columns schedule's bit for bit.
+template <typename T, int BS, int QPL, int TB, bool EPI>
 __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const int32_t *__restrict__ ch_off,
                                                            const int64_t *__restrict__ ch_base,
                                                            const uint32_t *__restrict__ ch_ell,
                                                            const T *__restrict__ code_v, int nchunks,
-                                                           int chunk_rows, int nslices, int P)
+                                                           int chunk_rows, int nslices, int P, LzEpi<T> E)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tab = reinterpret_cast<T *>(smem_raw);
@@ -598,37 +605,75 @@ __global__ __launch_bounds__(BS) void k_kron_chunked_parts(MvArgs<T> A, const in
             }
         }
     }
+    EpiCoef<T> ec;
+    if (EPI) ec = epi_coef(E);
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int i = 0; i < QPL; ++i) {
         const int q = qa + (int)threadIdx.x + i * BS;
-        if (q >= nq) continue;
-        const int a0 = 4 * q;
+        const bool live = q < nq;
+        // with the epilogue a wavefront goes on while its first lane-quad is in
+        // range (it reduces over the wavefront), else a lane stops at the end
+        if (EPI ? (q - lane >= nq) : !live) continue;
+        const int a0 = 4 * (live ? q : 0);
 #pragma unroll
         for (int t = 0; t < TB; ++t) {
-            int kk = ds[t];
-            for (; kk + 4 <= de[t]; kk += 4) {
-                Q4<T> v[4];
+            if (live) {
+                int kk = ds[t];
+                for (; kk + 4 <= de[t]; kk += 4) {
+                    Q4<T> v[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
+                    for (int u = 0; u < 4; ++u) v[u] = ld_q4(A.x + (int64_t)A.dn_col[kk + u] * cu64 + a0);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const T w = A.dn_val[kk + u];
+                    for (int u = 0; u < 4; ++u) {
+                        const T w = A.dn_val[kk + u];
 #pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v[u].v[rr];
+                        for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v[u].v[rr];
+                    }
+                }
+                for (; kk < de[t]; ++kk) {
+                    const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
+                    const T w = A.dn_val[kk];
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v.v[rr];
                 }
             }
-            for (; kk < de[t]; ++kk) {
-                const Q4<T> v = ld_q4(A.x + (int64_t)A.dn_col[kk] * cu64 + a0);
-                const T w = A.dn_val[kk];
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) acc[i][rr][t] += w * v.v[rr];
-            }
             if (b0 + t < cd) {
-                const T o[4] = {acc[i][0][t], acc[i][1][t], acc[i][2][t], acc[i][3][t]};
-                st_q4(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
+                T o[4] = {acc[i][0][t], acc[i][1][t], acc[i][2][t], acc[i][3][t]};
+                if (EPI) {
+                    double part = 0.0;
+                    if (live) {
+                        const Q4<T> xv = ld_q4(xb[t] + a0);
+                        Q4<T> vp;
+                        if (E.vprev) {
+                            const T *pv = E.vprev + (int64_t)(b0 + t) * cu64 + a0;
+                            vp = A.stream ? ld_q4_nt(pv) : ld_q4(pv);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) o[r] = epi_w(E, ec, o[r], E.vprev ? vp.v[r] : (T)0);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) part += (double)o[r] * (double)xv.v[r];
+                    }
+                    part = quad_wave_sum(part);
+                    if (lane == 0) E.gpart[(int64_t)(b0 + t) * E.G + (q >> 6)] = part;
+                }
+                if (live) {
+                    if (EPI && A.stream) st_q4_nt(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
+                    else st_q4(A.y + (int64_t)(b0 + t) * cu64 + a0, o);
+                }
             }
         }
     }
+}
+
+// apart[b] = sum over g of gpart[b][g], g increasing (the columns schedule's order)
+__global__ void k_epi_colsum(const double *__restrict__ gpart, int G, int cd, double *__restrict__ apart)
+{
+    const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b >= cd) return;
+    double sum = 0.0;
+    for (int g = 0; g < G; ++g) sum += gpart[(int64_t)b * G + g];
+    apart[b] = sum;
 }
 
 // ---- one row per lane (count_up % 4 != 0, or unaligned vectors) ------------
@@ -809,7 +854,7 @@ hub_status allow_lds(K kernel, size_t bytes)
 template <typename T>
 LzEpi<T> no_epi()
 {
-    return LzEpi<T>{nullptr, nullptr, nullptr, 0, nullptr, 0};
+    return LzEpi<T>{nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr};
 }
 
 // ---- geometry -------------------------------------------------------------
@@ -901,8 +946,9 @@ hub_status launch_quad(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, 
     return HUB_ERR_UNSUPPORTED;
 }
 
-template <typename T, int QPL, int TB>
-hub_status launch_chunked_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const ChunkSet &C)
+template <typename T, int QPL, int TB, bool EPI>
+hub_status launch_chunked_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const ChunkSet &C,
+                            const LzEpi<T> &E)
 {
     constexpr int BSC = 1024;
     const SpinTables &U = s->spin[0];
@@ -914,20 +960,28 @@ hub_status launch_chunked_k(const hub_sector *s, const MvArgs<T> &A, hipStream_t
     const int nq = (int)(A.cu >> 2);
     const int P = (nq + BSC * QPL - 1) / (BSC * QPL);
     const int ntiles = (A.cd + TB - 1) / TB;
-    HUB_TRY(allow_lds(k_kron_chunked_parts<T, BSC, QPL, TB>, s->lds_max));
+    HUB_TRY(allow_lds(k_kron_chunked_parts<T, BSC, QPL, TB, EPI>, s->lds_max));
     const unsigned grid = 8u * (unsigned)P * (unsigned)((ntiles + 7) / 8);
-    hipLaunchKernelGGL((k_kron_chunked_parts<T, BSC, QPL, TB>), dim3(grid), dim3(BSC), lds, st, A, C.off, C.base,
-                       C.ell, code_table<T>(U), C.n, C.rows, (int)U.nslices, P);
+    hipLaunchKernelGGL((k_kron_chunked_parts<T, BSC, QPL, TB, EPI>), dim3(grid), dim3(BSC), lds, st, A, C.off,
+                       C.base, C.ell, code_table<T>(U), C.n, C.rows, (int)U.nslices, P, E);
+    if (EPI)
+        hipLaunchKernelGGL(k_epi_colsum, dim3((unsigned)((A.cd + 255) / 256)), dim3(256), 0, st,
+                           (const double *)E.gpart, E.G, A.cd, E.apart);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
 
+// row-chunked product of shape (tb, qpl); E: fused Lanczos update or NULL
 template <typename T>
 hub_status launch_chunked(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, int tb, int qpl,
-                          const ChunkSet &C)
+                          const ChunkSet &C, const LzEpi<T> *E)
 {
-#define HUB_CH(TBV, QV) \
-    if (tb == TBV && qpl == QV) return launch_chunked_k<T, QV, TBV>(s, A, st, C);
+    const LzEpi<T> ne = no_epi<T>();
+#define HUB_CH(TBV, QV)                                                                  \
+    if (tb == TBV && qpl == QV) {                                                        \
+        if (E) return launch_chunked_k<T, QV, TBV, true>(s, A, st, C, *E);              \
+        return launch_chunked_k<T, QV, TBV, false>(s, A, st, C, ne);                    \
+    }
     HUB_CH(1, 4) HUB_CH(1, 8) HUB_CH(2, 4)
     if constexpr (sizeof(T) == 4) {
         HUB_CH(2, 8) HUB_CH(4, 4)
@@ -976,8 +1030,8 @@ hub_status launch_rows_auto(const hub_sector *s, const MvArgs<T> &A, hipStream_t
 template <typename T>
 hub_status launch_sched(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const Sched &q, const LzEpi<T> *E)
 {
-    if (E && q.fam != HUB_SCHED_COLUMNS) {
-        set_error("only the columns schedule has a fused Lanczos update");
+    if (E && q.fam != HUB_SCHED_COLUMNS && q.fam != HUB_SCHED_CHUNKED) {
+        set_error("only the columns and row-chunked schedules have a fused Lanczos update");
         return HUB_ERR_UNSUPPORTED;
     }
     switch (q.fam) {
@@ -986,7 +1040,7 @@ hub_status launch_sched(const hub_sector *s, const MvArgs<T> &A, hipStream_t st,
     case HUB_SCHED_CHUNKED: {
         const ChunkSet *C = nullptr;
         HUB_TRY(chunk_set(s, HUB_SPIN_UP, q.crows > 0 ? q.crows : chunked_rows<T>(s, q.tb), &C, st));
-        return launch_chunked<T>(s, A, st, q.tb, q.qpl, *C);
+        return launch_chunked<T>(s, A, st, q.tb, q.qpl, *C, E);
     }
     case HUB_SCHED_ROWS:
         return launch_rows_auto<T>(s, A, st);
@@ -1045,7 +1099,8 @@ hub_status time_candidates(hipStream_t st, int n, F launch, int &best, float &be
 // Candidate schedules of a sector: whole columns in LDS when one fits (1-3
 // columns per workgroup, 512 or 1024 lanes, XCD or launch tile order; with the
 // fused update, the shapes whose partials also fit), else the row-chunked
-// shapes (1, 2 or 4 columns per work item, 4 or 8 lane-quads per lane).
+// shapes (1, 2 or 4 columns per work item, 4 or 8 lane-quads per lane), with
+// or without the fused update.
 template <typename T>
 std::vector<Sched> candidates(const hub_sector *s, bool epi)
 {
@@ -1065,7 +1120,6 @@ std::vector<Sched> candidates(const hub_sector *s, bool epi)
         }
         return v;
     }
-    if (epi) return v;
     for (int tb : {1, 2, 4})
         for (int qpl : {4, 8}) {
             if (!chunked_shape_ok<T>(tb, qpl) || chunked_rows<T>(s, tb) <= 0) continue;
@@ -1096,7 +1150,7 @@ hub_status tune(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, bool ep
         HUB_HIP(hipMalloc((void **)&zero, sizeof(double)));
         zb.p = zero;
         HUB_HIP(hipMemsetAsync(zero, 0, sizeof(double), st));
-        E = LzEpi<T>{A.x, zero, apart, (int)(((A.cu >> 2) + 63) / 64), nullptr, 0};
+        E = LzEpi<T>{A.x, zero, apart, (int)(((A.cu >> 2) + 63) / 64), nullptr, 0, apart + A.cd};
     }
     std::vector<Sched> c = candidates<T>(s, epi);
     if (c.empty()) {
@@ -1183,7 +1237,8 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
 }
 
 // Whether the product fused with the first Lanczos update is available: the
-// columns schedule with its partials in LDS (forced or tuned).
+// columns schedule with its partials in LDS, or the row-chunked schedule
+// (forced or tuned).
 template <typename T>
 bool lz_fusable(const hub_sector *s)
 {
@@ -1192,9 +1247,11 @@ bool lz_fusable(const hub_sector *s)
     const int di = dix<T>();
     if (s->forced[di]) {
         const Sched &q = s->sched[di];
-        return !q.nofuse && q.fam == HUB_SCHED_COLUMNS && column_fits<T>(s, q.tb, true);
+        if (q.nofuse) return false;
+        if (q.fam == HUB_SCHED_COLUMNS) return column_fits<T>(s, q.tb, true);
+        return q.fam == HUB_SCHED_CHUNKED;
     }
-    return column_fits<T>(s, 1, true);
+    return column_fits<T>(s, 1, true) || (!column_fits<T>(s, 1, false) && chunked_rows<T>(s, 1) > 0);
 }
 
 template <typename T>
@@ -1205,7 +1262,8 @@ hub_status run_kron_lz(const hub_sector *s, const void *x, void *w, const void *
     MvArgs<T> A = make_args<T>(s, x, w);
     Sched q;
     HUB_TRY(schedule_for<T>(s, A, st, true, apart, q));
-    const LzEpi<T> E{(const T *)vprev, beta, apart, (int)(((A.cu >> 2) + 63) / 64), beta_prev, unnorm};
+    const LzEpi<T> E{(const T *)vprev, beta, apart, (int)(((A.cu >> 2) + 63) / 64), beta_prev, unnorm,
+                     apart + A.cd};
     *npart = (int64_t)A.cd;
     std::lock_guard<std::mutex> lk(s->mu);
     return launch_sched<T>(s, A, st, q, &E);
@@ -1228,6 +1286,14 @@ bool matvec_lz_available(const hub_sector *s, int dtype)
 int64_t matvec_lz_partials(const hub_sector *s)
 {
     return s->spin[1].count;
+}
+
+// Doubles of the fused product's partials buffer: the per-column partials,
+// then (row-chunked schedule) one per column and group of 256 rows.
+int64_t matvec_lz_workspace(const hub_sector *s)
+{
+    const int64_t cd = s->spin[1].count, G = ((s->spin[0].count >> 2) + 63) / 64;
+    return cd * (1 + G);
 }
 
 hub_status launch_matvec_lz(const hub_sector *s, int dtype, const void *x, void *w, const void *vprev,

@@ -632,21 +632,26 @@ def test_unnormalised_recurrence_breakdown(hub):
 @pytest.mark.gpu
 def test_fused_solve_same_for_every_tile_shape(hub):
     """The fused product's tile shape (columns per workgroup, workgroup size,
-    tile order) is tuned in each process, so a solve must not depend on it.  On
-    a sector whose 91 down-spin columns leave a partial tile of two and of three
-    columns, and whose 3432 rows leave a partial group of 64 lane-quads, every
-    forced shape gives the same energy and step count bit for bit, on both
-    precisions, and that energy is the oracle's."""
+    tile order; or the row-chunked schedule and its shape) is tuned in each
+    process, so a solve must not depend on it.  On a sector whose 91 down-spin
+    columns leave a partial tile of two and of three columns, and whose 3432
+    rows leave a partial group of 64 lane-quads, every forced shape gives the
+    same energy and step count bit for bit, on both precisions, and that energy
+    is the oracle's."""
     m = W.ring(14, U=4.0, n_up=7, n_dn=2)
     s = hub.Sector(m)
     assert s.count_up % 4 == 0 and s.count_dn % 2 == 1 and s.count_dn % 3 != 0
     assert (s.count_up // 4) % 64 != 0
     _, e_ref, _ = oracle.ground_state(m, want_vector=False)
-    shapes = [(tb, bs, xc) for tb in (1, 2, 3) for bs in (512, 1024) for xc in (0, 1)]
+    shapes = [(hub.SCHED_COLUMNS, dict(tile_cols=tb, block=bs, order=xc))
+              for tb in (1, 2, 3) for bs in (512, 1024) for xc in (0, 1)]
+    # the row-chunked product with its fused update forms the same per-column partials
+    shapes += [(hub.SCHED_CHUNKED, dict(tile_cols=tb, quads_per_lane=qpl, chunk_rows=rows))
+               for tb, qpl, rows in ((1, 4, 1000), (2, 4, 1500), (1, 8, 3432))]
     for dt, tol, rel in ((hub.F64, 1e-12, 1e-10), (hub.F32, 1e-7, 1e-5)):
         got = []
-        for tb, bs, xc in shapes:
-            s.set_schedule(dt, hub.SCHED_COLUMNS, tile_cols=tb, block=bs, order=xc)
+        for fam, kw in shapes:
+            s.set_schedule(dt, fam, **kw)
             g = s.ground_state(dtype=dt, tol=tol, want_vector=False)
             got.append((g.e0, g.info["iters"]))
         assert all(r == got[0] for r in got), (dt, list(zip(shapes, got)))
