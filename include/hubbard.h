@@ -194,8 +194,9 @@ hub_status hub_matvec(const hub_sector *sec, int32_t dtype, const void *dev_x, v
  * reports it.  hub_set_schedule forces one, for tests and measurement (NULL:
  * back to the tuned one); it returns INVALID_ARG for a shape the sector cannot
  * run.  A forced schedule also applies to the products inside
- * hub_ground_state, whose Lanczos update is fused into the COLUMNS product
- * unless no_fused_update is set.
+ * hub_ground_state, whose Lanczos update is fused into the COLUMNS or CHUNKED
+ * product unless no_fused_update is set (the fused update forms the same
+ * values and partial sums in both, so a solve does not depend on the choice).
  */
 #define HUB_SCHED_AUTO 0
 #define HUB_SCHED_COLUMNS 1
