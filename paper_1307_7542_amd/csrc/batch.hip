@@ -16,6 +16,10 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
+#include <thread>
 #include <new>
 #include <cfloat>
 #include <cmath>
@@ -69,11 +73,12 @@ struct __attribute__((aligned(sizeof(T) * N < 16 ? sizeof(T) * N : 16))) BVec {
     T v[N];
 };
 
-// Role of each vector slot at step k: v = V[k % 3], v_prev = V[(k + 2) % 3],
-// v_next = V[(k + 1) % 3]; slot 3 of the pointer table is w.
+// The lockstep recurrence keeps its vectors unnormalised, u_k = beta_k v_k
+// (u_0 = v_0, beta_0 taken as 1), in three rotating slots: at step k, u_k =
+// V[k % 3], u_{k-1} = V[(k + 2) % 3], and w, then u_{k+1} in place, V[(k + 1) % 3].
 template <typename T>
 struct Roles {
-    T *v, *vp, *vn, *w;
+    T *v, *vp, *w;
 };
 
 template <typename T>
@@ -82,10 +87,12 @@ __device__ __forceinline__ Roles<T> roles(T *const *ptrs, int k)
     Roles<T> r;
     r.v = ptrs[k % 3];
     r.vp = ptrs[(k + 2) % 3];
-    r.vn = ptrs[(k + 1) % 3];
-    r.w = ptrs[3];
+    r.w = ptrs[(k + 1) % 3];
     return r;
 }
+
+// 1 / beta (0 after a breakdown)
+__device__ __forceinline__ double binv(double b) { return b > 0.0 ? 1.0 / b : 0.0; }
 
 // Batched product.  A work item is `ncol` consecutive columns of one sector,
 // taken in groups of TB columns (the last group padded).  The item's columns
@@ -101,10 +108,11 @@ __device__ __forceinline__ Roles<T> roles(T *const *ptrs, int k)
 // selected).  Every element is formed as in the single-sector product
 // (diagonal, then the H_up entries in sliced-ELL order, then the H_dn entries
 // in CSR order, one fused multiply-add each): the two agree bit for bit.
-// SEL (the Lanczos step): x = v and y = w from the pointer table at the device
-// step counter, and the first update fused in: w = H v - beta_k v_prev (rounded
-// as a separate update would be) and this item's partial of <w, v> in
-// ipart[item] (a fixed-order block sum); otherwise x, y as given.
+// SEL (the Lanczos step): x = u_k and y = w from the pointer table at the device
+// step counter, and the first update fused in: w = (H u_k) / beta_k -
+// (beta_k / beta_{k-1}) u_{k-1}, evaluated in FP64 and rounded once, and this
+// item's partial of <w, u_k> = beta_k alpha_k in ipart[item] (a fixed-order
+// block sum); otherwise x, y as given.
 template <typename T, int BS, int R, int TB, bool SEL>
 __global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ desc, const int4 *__restrict__ items,
                                                    const T *xg, T *yg, T *const *ptrs, const int *step,
@@ -126,14 +134,18 @@ __global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ 
     T *y = yg;
     const T *vp = nullptr;
     int ks = 0;
-    double bt = 0.0;
+    double sx = 1.0, bt = 0.0;  // 1 / beta_k and beta_k / beta_{k-1}
     if (SEL) {
         ks = *step;
         const Roles<T> r = roles(ptrs, ks);
         x = r.v;
         y = r.w;
         vp = r.vp + D.off;
-        if (ks > 0) bt = beta[(int64_t)it.x * kmax + ks];
+        if (ks > 0) {
+            const double bk = beta[(int64_t)it.x * kmax + ks];
+            sx = binv(bk);
+            bt = bk * (ks > 1 ? binv(beta[(int64_t)it.x * kmax + ks - 1]) : 1.0);
+        }
     }
     x += D.off;
     y += D.off;
@@ -244,7 +256,7 @@ __global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ 
                 const int64_t o = t0 + (int64_t)cc * cu + ra[j];
                 T r = acc[j][t];
                 if (SEL) {
-                    if (ks > 0) r = (T)((double)r - bt * (double)vp[o]);
+                    r = (ks > 0) ? (T)fma(sx, (double)r, -(bt * (double)vp[o])) : (T)(sx * (double)r);
                     dacc += (double)r * (double)xs[(rg[j] * cu + ra[j]) * TB + t];
                 }
                 y[o] = r;
@@ -331,25 +343,29 @@ __device__ __forceinline__ double bsum_strided(const double *v, int n, double *s
 }
 
 // Lanczos step after the fused product: alpha_k from the sector's work-item
-// partials (every block of the sector forms it alike; the first stores it),
-// then w -= alpha_k v and the block's partial of beta^2 = <w, w>.
+// partials (their sum over beta_k; every block of the sector forms it alike, the
+// first stores it), then u_{k+1} = w - (alpha_k / beta_k) u_k in place of w and
+// the block's partial of beta_{k+1}^2 = <u_{k+1}, u_{k+1}>.
 template <typename T>
 __global__ __launch_bounds__(BRB) void k_b_lz_ab(Seg S, T *const *ptrs, const int *step,
                                                  const int *__restrict__ istart, const int *__restrict__ icount,
-                                                 const double *__restrict__ ipart, double *alpha, int kmax,
-                                                 double *partial, const int *__restrict__ active)
+                                                 const double *__restrict__ ipart, double *alpha,
+                                                 const double *__restrict__ beta, int kmax, double *partial,
+                                                 const int *__restrict__ active)
 {
     __shared__ double sh[BRB];
     const int pp = S.prob[blockIdx.x];
     if (active && !active[pp]) return;
     const int k = *step;
-    const double al = bsum_strided(ipart + istart[pp], icount[pp], sh);
+    const double ib = k > 0 ? binv(beta[(int64_t)pp * kmax + k]) : 1.0;
+    const double al = bsum_strided(ipart + istart[pp], icount[pp], sh) * ib;
     if (S.local[blockIdx.x] == 0 && threadIdx.x == 0) alpha[(int64_t)pp * kmax + k] = al;
+    const double c = al * ib;
     const Roles<T> r = roles(ptrs, k);
     double acc = 0.0;
     SEG_LOOP(S, p, i)
     {
-        const T wi = (T)((double)r.w[o_p + i] - al * (double)r.v[o_p + i]);
+        const T wi = (T)((double)r.w[o_p + i] - c * (double)r.v[o_p + i]);
         r.w[o_p + i] = wi;
         acc += (double)wi * (double)wi;
     }
@@ -380,20 +396,6 @@ __global__ __launch_bounds__(BRB) void k_b_beta(Seg S, int *step, const double *
     }
 }
 
-// v_next = w / beta_{k+1} (zero after a breakdown), run after k_b_beta has
-// advanced the step counter to k + 1.
-template <typename T>
-__global__ __launch_bounds__(BRB) void k_b_lz_nx(Seg S, T *const *ptrs, const int *step, const double *beta,
-                                                 int kmax, const int *__restrict__ active)
-{
-    const int pp = S.prob[blockIdx.x];
-    if (active && !active[pp]) return;
-    const int k = *step - 1;
-    const double bt = beta[(int64_t)pp * kmax + k + 1];
-    const Roles<T> r = roles(ptrs, k);
-    SEG_LOOP(S, p, i) r.vn[o_p + i] = (bt > 0.0) ? (T)((double)r.w[o_p + i] / bt) : (T)0;
-}
-
 // Start vectors: sector-local SplitMix64 entries (same as a single-sector solve).
 template <typename T>
 __global__ __launch_bounds__(BRB) void k_b_start(Seg S, T *out, uint64_t seed)
@@ -417,33 +419,42 @@ __global__ __launch_bounds__(BRB) void k_b_div(Seg S, T *x, const double *nrm)
     SEG_LOOP(S, p, i) x[o_p + i] = (f > 0.0) ? (T)((double)x[o_p + i] / f) : (T)0;
 }
 
-// Second pass (replay with the stored alpha / beta at step k, explicit k):
-// w = H v (done by the product), w = (w - beta_k v_prev) - alpha_k v, v_next = w / beta_{k+1}.
+// Second pass (replay with the stored alpha / beta at step k, explicit k): y =
+// H u_k (done by the product, into the slot of u_{k+1}) becomes w as in the
+// product's epilogue and then u_{k+1} = w - (alpha_k / beta_k) u_k as in
+// k_b_lz_ab, with the same roundings, so the first pass's vectors come back bit
+// for bit.
 template <typename T>
-__global__ __launch_bounds__(BRB) void k_b_replay(Seg S, T *w, const T *v, const T *vp, T *vn, const double *alpha,
+__global__ __launch_bounds__(BRB) void k_b_replay(Seg S, T *y, const T *u, const T *up, const double *alpha,
                                                   const double *beta, int kmax, int k, const int *__restrict__ mlen)
 {
     const int pp = S.prob[blockIdx.x];
     if (k + 1 >= mlen[pp]) return;
-    const double bt = (k > 0) ? beta[(int64_t)pp * kmax + k] : 0.0;
-    const double al = alpha[(int64_t)pp * kmax + k];
-    const double bn = beta[(int64_t)pp * kmax + k + 1];
+    double sx = 1.0, bt = 0.0, ib = 1.0;
+    if (k > 0) {
+        const double bk = beta[(int64_t)pp * kmax + k];
+        sx = binv(bk);
+        ib = sx;
+        bt = bk * (k > 1 ? binv(beta[(int64_t)pp * kmax + k - 1]) : 1.0);
+    }
+    const double c = alpha[(int64_t)pp * kmax + k] * ib;
     SEG_LOOP(S, p, i)
     {
-        T wi = w[o_p + i];
-        if (k > 0) wi = (T)((double)wi - bt * (double)vp[o_p + i]);
-        wi = (T)((double)wi - al * (double)v[o_p + i]);
-        vn[o_p + i] = (bn > 0.0) ? (T)((double)wi / bn) : (T)0;
+        const T w = (k > 0) ? (T)fma(sx, (double)y[o_p + i], -(bt * (double)up[o_p + i]))
+                            : (T)(sx * (double)y[o_p + i]);
+        y[o_p + i] = (T)((double)w - c * (double)u[o_p + i]);
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(BRB) void k_b_psi(Seg S, double *psi, const T *v, const double *y, int kmax, int k,
+__global__ __launch_bounds__(BRB) void k_b_psi(Seg S, double *psi, const T *v, const double *y,
+                                               const double *__restrict__ beta, int kmax, int k,
                                                const int *__restrict__ mlen)
 {
     const int pp = S.prob[blockIdx.x];
     if (k >= mlen[pp]) return;
-    const double c = y[(int64_t)pp * kmax + k];
+    // v_k = u_k / beta_k (beta_0 taken as 1)
+    const double c = y[(int64_t)pp * kmax + k] * (k > 0 ? binv(beta[(int64_t)pp * kmax + k]) : 1.0);
     SEG_LOOP(S, p, i) psi[o_p + i] = (k == 0 ? 0.0 : psi[o_p + i]) + c * (double)v[o_p + i];
 }
 
@@ -775,6 +786,74 @@ hub_status tune(hub_batch *b, hipStream_t st)
     return HUB_OK;
 }
 
+// Host workers for the per-sector convergence tests (a tridiagonal solve each):
+// run(n, f) calls f(0) ... f(n - 1) on the caller and the workers and returns
+// when all are done.  The pool lives for one batched solve.
+class HostPool {
+public:
+    explicit HostPool(int nthreads)
+    {
+        for (int i = 0; i < nthreads; ++i) th_.emplace_back([this] { loop(); });
+    }
+    ~HostPool()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    void run(int n, const std::function<void(int)> &f)
+    {
+        if (th_.empty() || n < 2) {
+            for (int i = 0; i < n; ++i) f(i);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            job_ = &f;
+            n_ = n;
+            next_.store(0);
+            busy_ = (int)th_.size();
+            ++gen_;
+        }
+        cv_.notify_all();
+        work();
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [this] { return busy_ == 0; });
+        job_ = nullptr;
+    }
+
+private:
+    void work()
+    {
+        for (int i = next_.fetch_add(1); i < n_; i = next_.fetch_add(1)) (*job_)(i);
+    }
+    void loop()
+    {
+        int seen = 0;
+        while (true) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+            }
+            work();
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--busy_ == 0) done_cv_.notify_one();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(int)> *job_ = nullptr;
+    int n_ = 0, busy_ = 0, gen_ = 0;
+    std::atomic<int> next_{0};
+    bool stop_ = false;
+};
+
 template <typename T>
 hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, int32_t *iters_out, double *psi,
                        hipStream_t user_st, hub_batch_info *info)
@@ -821,12 +900,12 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
         mem.push_back(*q);
         return HUB_OK;
     };
-    T *V[4];
-    for (int i = 0; i < 4; ++i) HUB_TRY(alloc((void **)&V[i], sizeof(T) * n));
+    T *V[3];
+    for (int i = 0; i < 3; ++i) HUB_TRY(alloc((void **)&V[i], sizeof(T) * n));
     T **ptrs = nullptr;
     int *step = nullptr, *active = nullptr, *mlen = nullptr;
     double *alpha = nullptr, *beta = nullptr, *partial = nullptr, *nrm = nullptr, *ycoef = nullptr;
-    HUB_TRY(alloc((void **)&ptrs, sizeof(T *) * 4));
+    HUB_TRY(alloc((void **)&ptrs, sizeof(T *) * 3));
     HUB_TRY(alloc((void **)&step, sizeof(int) * 4));
     unsigned int *done = reinterpret_cast<unsigned int *>(step + 1);  // arrival counter of k_b_beta
     HUB_TRY(alloc((void **)&active, sizeof(int) * P));
@@ -838,7 +917,7 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
     HUB_TRY(alloc((void **)&ipart, sizeof(double) * (size_t)std::max(1, b->nitems[di])));
     HUB_TRY(alloc((void **)&nrm, sizeof(double) * (size_t)P * 4));
     HUB_TRY(alloc((void **)&ycoef, sizeof(double) * (size_t)P * kmax));
-    HUB_HIP(hipMemcpyAsync(ptrs, V, sizeof(T *) * 4, hipMemcpyHostToDevice, st));
+    HUB_HIP(hipMemcpyAsync(ptrs, V, sizeof(T *) * 3, hipMemcpyHostToDevice, st));
     std::vector<int> hact(P, 1);
     HUB_HIP(hipMemcpyAsync(active, hact.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
     HUB_HIP(hipMemsetAsync(step, 0, sizeof(int) * 4, st));
@@ -859,16 +938,14 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
     HUB_TRY(make_start(V[0]));
 
     // one Lanczos step, captured as a graph: the fused product; alpha and
-    // w -= alpha v; beta and the step counter; v_next
+    // u_{k+1} = w - (alpha / beta_k) u_k; beta_{k+1} and the step counter
     auto one_step = [&]() -> hub_status {
         HUB_TRY((launch_batch_product<T, true>(b, nullptr, nullptr, ptrs, step, active, st, beta, kmax, ipart)));
         hipLaunchKernelGGL(k_b_lz_ab<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, ptrs, (const int *)step,
                            (const int *)b->istart[di], (const int *)b->icount[di], (const double *)ipart, alpha,
-                           kmax, partial, (const int *)active);
+                           (const double *)beta, kmax, partial, (const int *)active);
         hipLaunchKernelGGL(k_b_beta, dim3(P), dim3(BRB), 0, st, S, step, (const double *)partial, beta, kmax,
                            (const int *)active, done);
-        hipLaunchKernelGGL(k_b_lz_nx<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, ptrs, (const int *)step,
-                           (const double *)beta, kmax, (const int *)active);
         HUB_HIP(hipGetLastError());
         return HUB_OK;
     };
@@ -979,9 +1056,17 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
         return HUB_OK;
     };
     // Ritz test of every active sector on a copy holding kk steps
+    // the tests of the active sectors run on a few host threads (their tridiagonal
+    // solves would otherwise keep the GPU waiting at the end of a group)
+    const int nthreads = std::max(0, std::min(7, (int)std::thread::hardware_concurrency() - 1));
+    HostPool pool(P > 1 ? nthreads : 0);
+    std::vector<int> act;
     auto check_copy = [&](const double *ha, const double *hb, int kk) {
-        for (int p = 0; p < P; ++p) {
-            if (!hact[p]) continue;
+        act.clear();
+        for (int p = 0; p < P; ++p)
+            if (hact[p]) act.push_back(p);
+        const std::function<void(int)> one = [&](int i) {
+            const int p = act[(size_t)i];
             const double *a = ha + (size_t)p * kmax;
             const double *bb = hb + (size_t)p * kmax;
             const int64_t dimp = b->off[p + 1] - b->off[p];
@@ -1002,13 +1087,15 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
             const double scale = std::fabs(th) > 0 ? std::fabs(th) : 1.0;
             theta[p] = th;
             m_final[p] = m;
-            ys[p] = y;
-            if (brk || res <= tol * scale || (int64_t)m >= dimp) {
-                conv[p] = 1;
+            ys[p] = std::move(y);
+            if (brk || res <= tol * scale || (int64_t)m >= dimp) conv[p] = 1;
+        };
+        pool.run((int)act.size(), one);
+        for (const int p : act)
+            if (conv[p]) {
                 hact[p] = 0;
                 --nactive;
             }
-        }
     };
     std::deque<int> pend;  // copies enqueued and not yet examined, oldest first
     int next_slot = 0, msl = 0;
@@ -1036,7 +1123,7 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
     std::vector<double> e0(theta);
 
     if (psi && (o->want_vector || o->refine)) {
-        // second pass with the stored alpha / beta; psi = sum_j y_j v_j per sector
+        // second pass with the stored alpha / beta; psi = sum_j (y_j / beta_j) u_j per sector
         int mmax = 0;
         std::vector<double> hy((size_t)P * kmax, 0.0);
         for (int p = 0; p < P; ++p) {
@@ -1049,11 +1136,11 @@ hub_status batch_solve(hub_batch *b, const hub_lanczos_opts *o, double *e0_out, 
         T *vp = V[2], *vc = V[0], *vn = V[1];
         for (int j = 0; j < mmax; ++j) {
             hipLaunchKernelGGL(k_b_psi<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, psi, (const T *)vc,
-                               (const double *)ycoef, kmax, j, (const int *)mlen);
+                               (const double *)ycoef, (const double *)beta, kmax, j, (const int *)mlen);
             if (j + 1 >= mmax) break;
-            HUB_TRY((launch_batch_product<T, false>(b, vc, V[3], nullptr, nullptr, nullptr, st)));
-            hipLaunchKernelGGL(k_b_replay<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, V[3], (const T *)vc,
-                               (const T *)vp, vn, (const double *)alpha, (const double *)beta, kmax, j,
+            HUB_TRY((launch_batch_product<T, false>(b, vc, vn, nullptr, nullptr, nullptr, st)));
+            hipLaunchKernelGGL(k_b_replay<T>, dim3(b->nblocks), dim3(BRB), 0, st, S, vn, (const T *)vc,
+                               (const T *)vp, (const double *)alpha, (const double *)beta, kmax, j,
                                (const int *)mlen);
             T *tmp = vp;
             vp = vc;
