@@ -679,13 +679,17 @@ __global__ void k_epi_colsum(const double *__restrict__ gpart, int G, int cd, do
 // ---- one row per lane (count_up % 4 != 0, or unaligned vectors) ------------
 // Each lane owns R rows (a, a + BS, ...) at once so the H_dn neighbour reads
 // of all R rows are in flight together.  CF: compact entries (else packed
-// {column, value} entries, for sectors without the compact format).
-template <typename T, int TB, int BS, int R, bool CF>
+// {column, value} entries, for sectors without the compact format).  EPI: the
+// first Lanczos update fused into the store (as in k_kron_quad), each lane
+// summing its rows' products in row order and the workgroup combining the
+// lanes in a fixed tree, one partial per column.
+template <typename T, int TB, int BS, int R, bool CF, bool EPI>
 __global__ __launch_bounds__(BS) void k_kron_fused(MvArgs<T> A, const int32_t *__restrict__ sl_off,
                                                    const Pk<T> *__restrict__ ell, const uint32_t *__restrict__ ellc,
-                                                   const T *__restrict__ code_v, int ntiles)
+                                                   const T *__restrict__ code_v, int ntiles, LzEpi<T> E)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[EPI ? BS : 1];
     T *tab = reinterpret_cast<T *>(smem_raw);       // 256 code values (compact format)
     T *xs = tab + (CF ? 256 : 0);
     const int tile = xcd_tile(ntiles);
@@ -709,6 +713,9 @@ __global__ __launch_bounds__(BS) void k_kron_fused(MvArgs<T> A, const int32_t *_
     }
     const int lane = threadIdx.x & 63;
     const int64_t cu64 = cu;
+    EpiCoef<T> ec;
+    if (EPI) ec = epi_coef(E);
+    double part[EPI ? TB : 1] = {};
     for (int a0 = threadIdx.x; a0 < cu; a0 += BS * R) {
         T acc[R][TB];
         int as[R];
@@ -748,7 +755,28 @@ __global__ __launch_bounds__(BS) void k_kron_fused(MvArgs<T> A, const int32_t *_
             if (a0 + j * BS < cu)
 #pragma unroll
                 for (int t = 0; t < TB; ++t)
-                    if (b0 + t < cd) A.y[(int64_t)(b0 + t) * cu64 + a0 + j * BS] = acc[j][t];
+                    if (b0 + t < cd) {
+                        const int64_t o = (int64_t)(b0 + t) * cu64 + a0 + j * BS;
+                        T w = acc[j][t];
+                        if (EPI) {
+                            w = epi_w(E, ec, w, E.vprev ? E.vprev[o] : (T)0);
+                            part[t] += (double)w * (double)xs[(a0 + j * BS) * TB + t];
+                        }
+                        A.y[o] = w;
+                    }
+    }
+    if (EPI) {
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            red[threadIdx.x] = part[t];
+            __syncthreads();
+            for (int h = BS / 2; h > 0; h >>= 1) {
+                if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0 && b0 + t < cd) E.apart[b0 + t] = red[0];
+            __syncthreads();
+        }
     }
 }
 
@@ -991,36 +1019,55 @@ hub_status launch_chunked(const hub_sector *s, const MvArgs<T> &A, hipStream_t s
     return HUB_ERR_UNSUPPORTED;
 }
 
-template <typename T, int TB, int BS, int R = 4>
-hub_status launch_rows(const hub_sector *s, const MvArgs<T> &A, hipStream_t st)
+template <typename T, int TB, int BS, int R, bool EPI>
+hub_status launch_rows(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const LzEpi<T> &E)
 {
     const SpinTables &U = s->spin[0];
     const int ntiles = (A.cd + TB - 1) / TB;
     const unsigned grid = 8u * (unsigned)((ntiles + 7) / 8);
+    const size_t lim = s->lds_max - (EPI ? (size_t)BS * sizeof(double) : 0);  // beside the static reduction array
     if (U.ell_c32) {
         const size_t lds = (size_t)(A.cu * TB + 256) * sizeof(T);
-        HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, true>, s->lds_max));
-        hipLaunchKernelGGL((k_kron_fused<T, TB, BS, R, true>), dim3(grid), dim3(BS), lds, st, A, U.sl_off,
-                           ell_of<T>(U), U.ell_c32, code_table<T>(U), ntiles);
+        HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, true, EPI>, lim));
+        hipLaunchKernelGGL((k_kron_fused<T, TB, BS, R, true, EPI>), dim3(grid), dim3(BS), lds, st, A, U.sl_off,
+                           ell_of<T>(U), U.ell_c32, code_table<T>(U), ntiles, E);
         HUB_HIP(hipGetLastError());
         return HUB_OK;
     }
     const size_t lds = (size_t)A.cu * TB * sizeof(T);
-    HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, false>, s->lds_max));
-    hipLaunchKernelGGL((k_kron_fused<T, TB, BS, R, false>), dim3(grid), dim3(BS), lds, st, A, U.sl_off,
-                       ell_of<T>(U), (const uint32_t *)nullptr, (const T *)nullptr, ntiles);
+    HUB_TRY(allow_lds(k_kron_fused<T, TB, BS, R, false, EPI>, lim));
+    hipLaunchKernelGGL((k_kron_fused<T, TB, BS, R, false, EPI>), dim3(grid), dim3(BS), lds, st, A, U.sl_off,
+                       ell_of<T>(U), (const uint32_t *)nullptr, (const T *)nullptr, ntiles, E);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
 }
 
 // one row per lane: two columns per workgroup when they fit in half of the LDS;
 // CSR rows when a column does not fit
+// One row per lane in the shape the column size allows (two columns per
+// workgroup when both fit in half the LDS), else CSR rows; E: the fused Lanczos
+// update (its reduction array takes 8 KB of the LDS; no CSR fallback).
 template <typename T>
-hub_status launch_rows_auto(const hub_sector *s, const MvArgs<T> &A, hipStream_t st)
+bool rows_fit(const hub_sector *s, bool epi)
+{
+    const size_t col = (size_t)s->spin[0].count * sizeof(T), extra = 256 * sizeof(T);
+    return col + extra <= s->lds_max - (epi ? 1024 * sizeof(double) : 0);
+}
+
+template <typename T>
+hub_status launch_rows_auto(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const LzEpi<T> *E = nullptr)
 {
     const size_t col = (size_t)A.cu * sizeof(T), extra = 256 * sizeof(T);
-    if (2 * col + extra <= s->lds_max / 2) return launch_rows<T, 2, 1024, 2>(s, A, st);
-    if (col + extra <= s->lds_max) return launch_rows<T, 1, 1024, 4>(s, A, st);
+    const size_t lim = s->lds_max - (E ? 1024 * sizeof(double) : 0);
+    const LzEpi<T> ne = no_epi<T>();
+    if (2 * col + extra <= lim / 2)
+        return E ? launch_rows<T, 2, 1024, 2, true>(s, A, st, *E) : launch_rows<T, 2, 1024, 2, false>(s, A, st, ne);
+    if (col + extra <= lim)
+        return E ? launch_rows<T, 1, 1024, 4, true>(s, A, st, *E) : launch_rows<T, 1, 1024, 4, false>(s, A, st, ne);
+    if (E) {
+        set_error("one-row-per-lane product: a column does not fit in LDS beside the update's reduction");
+        return HUB_ERR_UNSUPPORTED;
+    }
     hipLaunchKernelGGL((k_kron_csr<T, 512>), dim3((unsigned)A.cd), dim3(512), 0, st, A);
     HUB_HIP(hipGetLastError());
     return HUB_OK;
@@ -1030,8 +1077,8 @@ hub_status launch_rows_auto(const hub_sector *s, const MvArgs<T> &A, hipStream_t
 template <typename T>
 hub_status launch_sched(const hub_sector *s, const MvArgs<T> &A, hipStream_t st, const Sched &q, const LzEpi<T> *E)
 {
-    if (E && q.fam != HUB_SCHED_COLUMNS && q.fam != HUB_SCHED_CHUNKED) {
-        set_error("only the columns and row-chunked schedules have a fused Lanczos update");
+    if (E && q.fam == HUB_SCHED_CSR) {
+        set_error("the csr schedule has no fused Lanczos update");
         return HUB_ERR_UNSUPPORTED;
     }
     switch (q.fam) {
@@ -1043,7 +1090,7 @@ hub_status launch_sched(const hub_sector *s, const MvArgs<T> &A, hipStream_t st,
         return launch_chunked<T>(s, A, st, q.tb, q.qpl, *C, E);
     }
     case HUB_SCHED_ROWS:
-        return launch_rows_auto<T>(s, A, st);
+        return launch_rows_auto<T>(s, A, st, E);
     case HUB_SCHED_CSR:
         hipLaunchKernelGGL((k_kron_csr<T, 512>), dim3((unsigned)A.cd), dim3(512), 0, st, A);
         HUB_HIP(hipGetLastError());
@@ -1237,20 +1284,23 @@ hub_status run_kron(const hub_sector *s, const void *x, void *y, hipStream_t st)
 }
 
 // Whether the product fused with the first Lanczos update is available: the
-// columns schedule with its partials in LDS, or the row-chunked schedule
+// columns schedule with its partials in LDS, the row-chunked schedule, or one
+// row per lane (count_up % 4 != 0) when a column fits beside the reduction
 // (forced or tuned).
 template <typename T>
 bool lz_fusable(const hub_sector *s)
 {
-    if (!quad_ok(s)) return false;
+    if (s->k0) return false;  // the k = 0 block has its own product
     std::lock_guard<std::mutex> lk(s->mu);
     const int di = dix<T>();
     if (s->forced[di]) {
         const Sched &q = s->sched[di];
         if (q.nofuse) return false;
-        if (q.fam == HUB_SCHED_COLUMNS) return column_fits<T>(s, q.tb, true);
-        return q.fam == HUB_SCHED_CHUNKED;
+        if (q.fam == HUB_SCHED_COLUMNS) return quad_ok(s) && column_fits<T>(s, q.tb, true);
+        if (q.fam == HUB_SCHED_CHUNKED) return quad_ok(s);
+        return q.fam == HUB_SCHED_ROWS && rows_fit<T>(s, true);
     }
+    if (!quad_ok(s)) return rows_fit<T>(s, true);
     return column_fits<T>(s, 1, true) || (!column_fits<T>(s, 1, false) && chunked_rows<T>(s, 1) > 0);
 }
 
@@ -1261,7 +1311,11 @@ hub_status run_kron_lz(const hub_sector *s, const void *x, void *w, const void *
     if (!lz_fusable<T>(s)) return HUB_ERR_UNSUPPORTED;
     MvArgs<T> A = make_args<T>(s, x, w);
     Sched q;
-    HUB_TRY(schedule_for<T>(s, A, st, true, apart, q));
+    if (quad_ok(s)) {
+        HUB_TRY(schedule_for<T>(s, A, st, true, apart, q));
+    } else {
+        q.fam = HUB_SCHED_ROWS;  // the only fused shape without four-row quads
+    }
     const LzEpi<T> E{(const T *)vprev, beta, apart, (int)(((A.cu >> 2) + 63) / 64), beta_prev, unnorm,
                      apart + A.cd};
     *npart = (int64_t)A.cd;
