@@ -36,10 +36,10 @@ struct SpinTables {
     // Sliced ELL copy of H_sigma for the product: rows in slices of 64 (one
     // wavefront), each slice padded to its longest row and stored entry-major,
     // so lane r of a wavefront reads entry k of row 64*s + r at
-    // sl_off[s] + 64*k + r (padding: column = the row itself, value 0).
+    // 64*sl_off[s] + 64*k + r (padding: column = the row itself, value 0).
     int64_t nslices = 0;
-    int32_t *sl_off = nullptr;   // [nslices + 1] entry offsets (multiples of 64)
-    int32_t *ell_col = nullptr;  // [sl_off[nslices]]
+    int32_t *sl_off = nullptr;   // [nslices + 1] slice offsets in units of 64 entries
+    int32_t *ell_col = nullptr;  // [64 sl_off[nslices]]
     float *ell_v32 = nullptr;
     double *ell_v64 = nullptr;
     uint2 *ell_pk32 = nullptr;   // packed {column, FP32 value bits}: one 8-byte load per entry
