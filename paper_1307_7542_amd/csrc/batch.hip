@@ -111,8 +111,8 @@ __device__ __forceinline__ double binv(double b) { return b > 0.0 ? 1.0 / b : 0.
 // SEL (the Lanczos step): x = u_k and y = w from the pointer table at the device
 // step counter, and the first update fused in: w = (H u_k) / beta_k -
 // (beta_k / beta_{k-1}) u_{k-1}, evaluated in FP64 and rounded once, and this
-// item's partial of <w, u_k> = beta_k alpha_k in ipart[item] (a fixed-order
-// block sum); otherwise x, y as given.
+// item's partial of <w, u_k> = beta_k alpha_k in ipart[it.w] (a fixed-order
+// block sum, at the item's place in sector-major order); otherwise x, y as given.
 template <typename T, int BS, int R, int TB, bool SEL>
 __global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ desc, const int4 *__restrict__ items,
                                                    const T *xg, T *yg, T *const *ptrs, const int *step,
@@ -123,8 +123,8 @@ __global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ 
     __shared__ double red[SEL ? BS : 1];
     T *tab = reinterpret_cast<T *>(smem_raw);
     T *xs = tab + 256;
-    // items in launch order: with converged sectors masked out, the remaining
-    // work stays spread over every XCD
+    // items in launch order (costliest first): with converged sectors masked
+    // out, the remaining work stays spread over every XCD
     const int item = (int)blockIdx.x;
     if (item >= nitems) return;
     const int4 it = items[item];
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(BS) void k_batch_kron(const BDesc<T> *__restrict__ 
             if (threadIdx.x < (unsigned)o2) red[threadIdx.x] += red[threadIdx.x + o2];
             __syncthreads();
         }
-        if (threadIdx.x == 0) ipart[item] = red[0];
+        if (threadIdx.x == 0) ipart[it.w] = red[0];
     }
 }
 
@@ -697,7 +697,7 @@ hub_status build_items(hub_batch *b, int di, int target, int tb)
             return bfail(HUB_ERR_UNSUPPORTED, "sector too large for the batched product");
         for (int b0 = 0; b0 < cd; b0 += per) {
             const int n = std::min(per, cd - b0);
-            it.push_back(make_int4(p, b0, n, 0));
+            it.push_back(make_int4(p, b0, n, (int)it.size()));
             const size_t nnz = (size_t)n * (size_t)deg;
             const size_t ncp = (size_t)((n + tb - 1) / tb * tb);
             lds = std::max(lds, (256 + ncp * cu + nnz + n) * es + (nnz + 2 * (size_t)n + 1) * 4);
@@ -709,8 +709,18 @@ hub_status build_items(hub_batch *b, int di, int target, int tb)
             if (q == (void *)b->items[di]) q = nullptr;
         b->items[di] = nullptr;
     }
-    HUB_TRY(balloc(b, &b->items[di], it.size()));
-    HUB_HIP(hipMemcpy(b->items[di], it.data(), sizeof(int4) * it.size(), hipMemcpyHostToDevice));
+    // launch order: costliest items first (elements times the entries per
+    // element), so the last wave of workgroups holds the cheapest ones; .w keeps
+    // the item's sector-major index, where its alpha partial goes
+    std::vector<int4> lo(it);
+    auto cost = [&](const int4 &q) {
+        const hub_sector *sp = b->secs[q.x];
+        const double cu = (double)sp->spin[0].count, cd = (double)sp->spin[1].count;
+        return (double)q.z * cu * (1.0 + (double)sp->spin[0].nnz / cu + (double)sp->spin[1].nnz / cd);
+    };
+    std::stable_sort(lo.begin(), lo.end(), [&](const int4 &a, const int4 &c) { return cost(a) > cost(c); });
+    HUB_TRY(balloc(b, &b->items[di], lo.size()));
+    HUB_HIP(hipMemcpy(b->items[di], lo.data(), sizeof(int4) * lo.size(), hipMemcpyHostToDevice));
     b->nitems[di] = (int)it.size();
     b->lds_bytes[di] = lds;
     // the items of sector p are [istart[p], istart[p] + icount[p]) (sector-major order)
